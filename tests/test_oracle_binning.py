@@ -1,0 +1,69 @@
+"""Pins of the oracle's hit binning.
+
+Hits of each layer are placed into bins so that a track only examines hits
+near its prediction (Sec. 3: hits sorted in phi with phi bins for a fast
+look-up).  The building workload bins 64 in z by 512 in phi.
+"""
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "bins_small.txt")
+
+
+def load_fixture():
+    rows = []
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        pe, z, zb, pb = line.split()
+        phi = eval(pe, {"pi": math.pi})
+        rows.append((phi, float(z), int(zb), int(pb)))
+    return rows
+
+
+def test_hand_worked_bins(orc):
+    rows = load_fixture()
+    hits = np.array([[10 * math.cos(p), 10 * math.sin(p), z] for p, z, _, _ in rows]).T
+    offs, perm = orc.bin_layer(hits, 100.0, 64, 512)
+    pos = np.empty_like(perm)
+    pos[perm] = np.arange(perm.size)
+    for i, (_, _, zb, pb) in enumerate(rows):
+        b = zb * 512 + pb
+        assert offs[b] <= pos[i] < offs[b + 1], (i, zb, pb)
+
+
+def test_csr_properties(orc):
+    rng = np.random.default_rng(1)
+    n = 5000
+    phi = rng.uniform(-math.pi, math.pi, n)
+    z = rng.uniform(-100, 100, n)
+    r = 20.0
+    hits = np.stack([r * np.cos(phi), r * np.sin(phi), z]).astype(np.float32).astype(np.float64)
+    nz, nphi = 64, 512
+    offs, perm = orc.bin_layer(hits, 100.0, nz, nphi)
+    assert offs[0] == 0 and offs[-1] == n
+    assert np.all(np.diff(offs) >= 0)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    # every hit lies inside the phi and z range of its bin
+    ph = np.arctan2(hits[1], hits[0])
+    dphi = 2 * math.pi / nphi
+    dz = 200.0 / nz
+    for b in range(nz * nphi):
+        a, e = offs[b], offs[b + 1]
+        if a == e:
+            continue
+        idx = perm[a:e]
+        zb, pb = divmod(b, nphi)
+        assert np.all(ph[idx] >= -math.pi + pb * dphi - 1e-12)
+        assert np.all(ph[idx] < -math.pi + (pb + 1) * dphi + 1e-12)
+        assert np.all(hits[2, idx] >= -100 + zb * dz - 1e-12)
+        assert np.all(hits[2, idx] < -100 + (zb + 1) * dz + 1e-12)
+        assert np.all(np.diff(idx) > 0)  # original order within a bin
+
+
+def test_empty_layer(orc):
+    offs, perm = orc.bin_layer(np.zeros((3, 0)), 100.0, 64, 512)
+    assert perm.size == 0 and np.all(offs == 0)

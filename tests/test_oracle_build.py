@@ -1,0 +1,201 @@
+"""Pins of the oracle's combinatorial track building.
+
+Building (Sec. 3) extends each seed layer by layer with compatible hits
+(lowest chi2 increments), branching to keep up to N candidates per seed; the
+clone engine (Sec. 3.1) scores all (candidate, hit) pairs into a list, sorts
+it and copies only the best N.  A beam that keeps every branch is an
+exhaustive search, and a beam of one is the greedy "best hit" approach; both
+reduce to plain enumerations written here independently of the oracle's
+bookkeeping.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import trackgen as tg
+
+CUT = 30.0
+
+
+def small_event(seed, n_tracks, n_layers=7, noise=0.2, pt=(0.5, 10.0)):
+    rng = np.random.default_rng(seed)
+    det = tg.barrel(n_layers)
+    return tg.make_build_event(rng, n_tracks, det, noise_frac=noise, pt_range=pt)
+
+
+def layer_hits(bs, l):
+    return bs.layer_hits(0, l).T  # [n, 3]
+
+
+def seed_phase(orc, bs, s, nsl=3):
+    det = bs.det
+    x = bs.state[:, s].copy()
+    P = orc.unpack(bs.cov[:, s:s + 1])[0]
+    chi2 = 0.0
+    hits = []
+    for l in range(nsl):
+        xp, F, _, rc = orc.propagate(x, int(bs.q[s]), det.bz, det.radii[l], l == 0)
+        assert rc == 0
+        Pp = orc.cov_propagate(P, F)
+        h = int(bs.seed_hit[l, s])
+        m = layer_hits(bs, l)[h]
+        V = orc.hit_cov(m, det.sigma_r, det.sigma_rphi, det.sigma_z)
+        x, P, c2, rc = orc.update(xp, Pp, m, V)
+        chi2 += c2
+        hits.append(h)
+    return x, P, chi2, hits
+
+
+def enumerate_paths(orc, bs, s, max_missed=1, nsl=3):
+    """All hit sequences the branching rule admits: on each layer every hit
+    with chi2 < cut opens a branch; with none, a missed layer if allowed,
+    else the path ends.  Returns (nhits, chi2, hits) of every end point."""
+    det = bs.det
+    x, P, chi2, hits = seed_phase(orc, bs, s, nsl)
+    ends = []
+
+    def rec(l, x, P, chi2, nh, nm, hits):
+        if l == det.n_layers:
+            ends.append((nh, chi2, hits))
+            return
+        xp, F, _, rc = orc.propagate(x, int(bs.q[s]), det.bz, det.radii[l])
+        if rc:
+            ends.append((nh, chi2, hits + [-1] * (det.n_layers - l)))
+            return
+        Pp = orc.cov_propagate(P, F)
+        found = False
+        for h, m in enumerate(layer_hits(bs, l)):
+            V = orc.hit_cov(m, det.sigma_r, det.sigma_rphi, det.sigma_z)
+            c2, rc = orc.chi2(xp, Pp, m, V)
+            if rc == 0 and c2 < CUT:
+                found = True
+                xn, Pn, _, _ = orc.update(xp, Pp, m, V)
+                rec(l + 1, xn, Pn, chi2 + c2, nh + 1, nm, hits + [h])
+        if not found:
+            if nm < max_missed:
+                rec(l + 1, xp, Pp, chi2, nh, nm + 1, hits + [-1])
+            else:
+                ends.append((nh, chi2, hits + [-1] * (det.n_layers - l)))
+
+    rec(nsl, x, P, chi2, 3, 0, hits)
+    return ends
+
+
+def with_ghosts(bs, seed, frac=0.6, spread=0.02):
+    """Add, beside a fraction of the true hits, a ghost hit a few sigma away
+    along phi and z so that candidates branch."""
+    rng = np.random.default_rng(seed)
+    det = bs.det
+    parts, sizes = [], []
+    for l in range(det.n_layers):
+        h = bs.layer_hits(0, l)
+        n_true = int((bs.true_idx[l] >= 0).sum())
+        pick = np.nonzero(rng.random(n_true) < frac)[0] if l >= 3 else np.array([], int)
+        r = det.radii[l]
+        ph = np.arctan2(h[1, pick], h[0, pick]) + rng.normal(0, spread, pick.size) / r
+        z = h[2, pick] + rng.normal(0, 0.2, pick.size)
+        g = tg.f32(np.stack([r * np.cos(ph), r * np.sin(ph), z]))
+        parts.append(np.concatenate([h, g], axis=1))
+        sizes.append(parts[-1].shape[1])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return tg.BuildSet(det, 1, off, np.concatenate(parts, axis=1), bs.seed_off, bs.state,
+                       bs.cov, bs.q, bs.seed_hit, bs.true_idx, bs.truth_pos, bs.truth_mom)
+
+
+def test_wide_beam_equals_exhaustive_search(orc):
+    bs = with_ghosts(small_event(1, 30, n_layers=7), 11)
+    o = orc.build_event(bs, 0, max_cands=4096)
+    branched = 0
+    for s in range(bs.n_seeds):
+        ends = enumerate_paths(orc, bs, s)
+        branched += len(ends) > 1
+        best = min(ends, key=lambda e: (-e[0], e[1]))
+        assert o["nhits"][s] == best[0]
+        assert o["chi2"][s] == pytest.approx(best[1], rel=1e-12)
+        assert list(o["hit_idx"][:, s]) == best[2]
+    assert branched >= bs.n_seeds // 2  # the search really branched
+
+
+def test_narrow_beam_differs_from_wide_only_by_pruning(orc):
+    """Keeping fewer candidates can only lose: the wide beam (an exhaustive
+    search) ends at least as high in the ranking as any narrower one."""
+    bs = with_ghosts(small_event(5, 30, n_layers=7), 12)
+    wide = orc.build_event(bs, 0, max_cands=4096)
+    for nc in (1, 2, 10):
+        o = orc.build_event(bs, 0, max_cands=nc)
+        for s in range(bs.n_seeds):
+            kw = (-wide["nhits"][s], wide["chi2"][s])
+            kn = (-o["nhits"][s], o["chi2"][s])
+            assert kw <= kn
+
+
+def test_beam_of_one_is_greedy(orc):
+    bs = with_ghosts(small_event(2, 30, n_layers=8), 13)
+    o = orc.build_event(bs, 0, max_cands=1)
+    det = bs.det
+    for s in range(bs.n_seeds):
+        x, P, chi2, hits = seed_phase(orc, bs, s)
+        nh, nm = 3, 0
+        for l in range(3, det.n_layers):
+            xp, F, _, rc = orc.propagate(x, int(bs.q[s]), det.bz, det.radii[l])
+            Pp = orc.cov_propagate(P, F)
+            best = None
+            for h, m in enumerate(layer_hits(bs, l)):
+                V = orc.hit_cov(m, det.sigma_r, det.sigma_rphi, det.sigma_z)
+                c2, rc2 = orc.chi2(xp, Pp, m, V)
+                if rc2 == 0 and c2 < CUT and (best is None or c2 < best[0]):
+                    best = (c2, h, m, V)
+            if best is None:
+                if nm == 1:
+                    break
+                nm += 1
+                hits.append(-1)
+                x, P = xp, Pp
+                continue
+            x, P, _, _ = orc.update(xp, Pp, best[2], best[3])
+            chi2 += best[0]
+            nh += 1
+            hits.append(best[1])
+        hits += [-1] * (det.n_layers - len(hits))
+        assert o["nhits"][s] == nh
+        assert list(o["hit_idx"][:, s]) == hits
+        assert o["chi2"][s] == pytest.approx(chi2, rel=1e-12)
+
+
+def test_finds_true_hits(orc):
+    """On a config-3-like event (17 layers, 20% noise) the built track of
+    almost every seed is its own particle's hits; a true hit fails the cut
+    only in the chi2 tail."""
+    bs = small_event(3, 300, n_layers=17)
+    o = orc.build_event(bs, 0)
+    match = (o["hit_idx"] == bs.true_idx)
+    per_seed = match.mean(axis=0)
+    assert np.mean(per_seed == 1.0) > 0.95
+    assert np.all(o["nhits"] >= 14)
+
+
+def test_debug_records_are_consistent(orc):
+    bs = small_event(4, 60, n_layers=9)
+    o = orc.build_event(bs, 0, debug=True)
+    L, NC = 9, 10
+    for s in range(bs.n_seeds):
+        # backtrack the winning candidate's hits from the per-layer records
+        # when it survived to the end
+        n_end = o["dbg_n"][L - 1, s]
+        if n_end == 0:
+            continue
+        assert n_end <= NC
+        ranks = o["dbg"][:, :, 0, s]
+        hits = o["dbg"][:, :, 1, s]
+        paths = []
+        for r in range(n_end):
+            rr, seq = r, []
+            for l in range(L - 1, 2, -1):
+                seq.append(hits[l, rr])
+                rr = ranks[l, rr]
+            paths.append(list(bs.seed_hit[:, s]) + seq[::-1])
+        assert len({tuple(p) for p in paths}) == n_end  # distinct candidates
+        for l in range(3, L):
+            for r in range(o["dbg_n"][l, s]):
+                assert 0 <= ranks[l, r] < o["dbg_n"][l - 1, s]

@@ -1,0 +1,255 @@
+"""Pins of the oracle's whole-track fit.
+
+Track fitting "repeatedly applies the KF algorithm" over a fixed hit set
+(Sec. 2).  For a linear-Gaussian chain the filtered final state must equal
+the batch weighted-least-squares solution and the summed chi2 increments the
+least-squares minimum; on helices the filter must agree with a Gauss-Newton
+batch fit and give unit pulls when its prior is consistent.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import trackgen as tg
+
+
+def spd(rng, n, scale=1.0):
+    A = rng.normal(size=(n, n))
+    return scale * (A @ A.T + n * np.eye(n))
+
+
+@pytest.mark.parametrize("kind", ["random", "helix"])
+def test_linear_chain_equals_batch_wls(orc, kind):
+    """KF over x_k = F_k x_{k-1}, m_k = H x_k + e_k with prior (x0, C0):
+    final state and covariance equal the batch WLS solution mapped to the
+    last step, and the chi2 sum equals the minimum of the WLS objective."""
+    rng = np.random.default_rng(11 if kind == "random" else 12)
+    H = np.hstack([np.eye(3), np.zeros((3, 3))])
+    for trial in range(10):
+        nl = rng.integers(3, 6)
+        if kind == "random":
+            Fs = [np.eye(6) + 0.3 * rng.normal(size=(6, 6)) for _ in range(nl)]
+        else:
+            # Jacobians of a real helix frozen at the truth (rank 5 each)
+            x = np.array([0.0, 0.0, 0.0, 1.5, 0.7, 0.4])
+            Fs = []
+            for l in range(nl):
+                x, F, s, rc = orc.propagate(x, 1, 3.8, 4.0 * (l + 1))
+                Fs.append(F)
+        Vs = [spd(rng, 3, 0.01) for _ in range(nl)]
+        C0 = spd(rng, 6, 0.1)
+        x0 = rng.normal(size=6)
+        ms = [rng.normal(size=3) for _ in range(nl)]
+        # Kalman filter built from the oracle's primitives
+        xk, Pk, c2sum = x0.copy(), C0.copy(), 0.0
+        for F, V, m in zip(Fs, Vs, ms):
+            xp = F @ xk
+            Pp = orc.cov_propagate(Pk, F)
+            xk, Pk, c2, rc = orc.update(xp, Pp, m, V)
+            assert rc == 0
+            c2sum += c2
+        # batch WLS over the initial state
+        Phi, rows, rhs, W = np.eye(6), [], [], []
+        Phis = []
+        for F in Fs:
+            Phi = F @ Phi
+            Phis.append(Phi.copy())
+        A = np.linalg.inv(C0)
+        b = A @ x0
+        for Ph, V, m in zip(Phis, Vs, ms):
+            G = H @ Ph
+            Vi = np.linalg.inv(V)
+            A = A + G.T @ Vi @ G
+            b = b + G.T @ Vi @ m
+        xs = np.linalg.solve(A, b)
+        cov0 = np.linalg.inv(A)
+        xN = Phis[-1] @ xs
+        PN = Phis[-1] @ cov0 @ Phis[-1].T
+        sig = np.sqrt(np.abs(np.diag(PN))) + 1e-300
+        np.testing.assert_allclose(xk, xN, rtol=0, atol=1e-9 * (np.abs(xN).max() + sig.max()))
+        np.testing.assert_allclose(Pk, PN, rtol=0, atol=1e-9 * np.abs(PN).max())
+        obj = (xs - x0) @ np.linalg.solve(C0, xs - x0)
+        for Ph, V, m in zip(Phis, Vs, ms):
+            res = m - H @ Ph @ xs
+            obj += res @ np.linalg.solve(V, res)
+        assert c2sum == pytest.approx(obj, rel=1e-9)
+
+
+def pulls(fs, o):
+    P = np_unpack(o["cov"])
+    d = o["state"] - np.concatenate([fs.truth_pos[-1], fs.truth_mom[-1]])
+    x, y = fs.truth_pos[-1, 0], fs.truth_pos[-1, 1]
+    r = np.hypot(x, y)
+    tx, ty = -y / r, x / r
+    vt = tx * tx * P[:, 0, 0] + 2 * tx * ty * P[:, 0, 1] + ty * ty * P[:, 1, 1]
+    out = {"t": (d[0] * tx + d[1] * ty) / np.sqrt(vt)}
+    for i, name in [(2, "z"), (3, "px"), (4, "py"), (5, "pz")]:
+        out[name] = d[i] / np.sqrt(P[:, i, i])
+    return out
+
+
+def np_unpack(p):
+    out = np.zeros(p.shape[1:] + (6, 6))
+    k = 0
+    for i in range(6):
+        for j in range(i, 6):
+            out[..., i, j] = out[..., j, i] = p[k]
+            k += 1
+    return out
+
+
+def consistent_fit_set(n, seed, f=0.03, pt_range=(0.5, 10.0)):
+    """Config-1 shapes with a prior narrow enough for the linearised filter."""
+    rng = np.random.default_rng(seed)
+    det = tg.barrel(10)
+    tr = tg.sample_truth(rng, n, pt_range=pt_range)
+    pos, mom, reached = tg.truth_crossings(tr, det)
+    hits = tg.smear_hits(rng, pos, det)
+    st, cv = tg.truth_smeared_seed(rng, pos[0], mom[0], f_par=f, f_perp=f / 10, f_pz=f,
+                                   f_pzt=f / 10, sig_xy=f, sig_z=10 * f)
+    return tg.FitSet(det, st, cv, tr["q"], hits, np.ones((10, n), np.uint8), pos, mom)
+
+
+def test_pulls_and_chi2_are_unit(orc):
+    fs = consistent_fit_set(1000, 21)
+    o = orc.fit(fs)
+    assert np.all(o["status"] == 0)
+    assert np.all(o["nupd"] == 10)
+    for name, p in pulls(fs, o).items():
+        assert abs(p.mean()) <= 0.1, name
+        assert 0.93 <= p.std() <= 1.07, (name, p.std())
+    # each 3-D hit on a cylinder carries two measurements
+    assert 0.95 <= np.mean(o["chi2"] / (2 * o["nupd"])) <= 1.05
+
+
+def test_config1_three_hit_seeds_run(orc):
+    """Seeds from three hits carry a poor curvature estimate; the linearised
+    filter diverges for a minority of them (chi2/ndf > 5 with the diffuse-
+    prior ndf 2 n - 5, or a track lost on the way).  The rest fit cleanly."""
+    fs = tg.config1()
+    o = orc.fit(fs)
+    bad = (o["status"] != 0) | (o["chi2"] / np.maximum(1, 2 * o["nupd"] - 5) > 5)
+    assert bad.mean() < 0.15
+    assert np.all(o["status"][~bad] == 0)
+    assert np.all(o["nupd"][o["status"] == 0] == 10)
+    P = np_unpack(o["cov"])
+    for i in np.nonzero(~bad)[0]:
+        w = np.linalg.eigvalsh(P[i])
+        assert w[1] > 0 and w[0] > -1e-9 * w[-1]
+
+
+def test_covariance_invariants_on_the_surface(orc):
+    """After the last update the covariance is symmetric positive semi-
+    definite of rank 5.  Its null vector is the radial direction at the
+    predicted point (the constrained propagation cannot move off the
+    cylinder and the update does not move along the normal), which differs
+    from the radial direction at the filtered point by the small tangential
+    shift of the update (~ sigma_rphi / r)."""
+    fs = consistent_fit_set(200, 22)
+    o = orc.fit(fs)
+    P = np_unpack(o["cov"])
+    for i in range(fs.n):
+        x, y = o["state"][0, i], o["state"][1, i]
+        r = math.hypot(x, y)
+        nvec = np.array([x / r, y / r, 0, 0, 0, 0])
+        np.testing.assert_array_equal(P[i], P[i].T)
+        w, U = np.linalg.eigh(P[i])
+        assert abs(w[0]) <= 1e-12 * w[-1]
+        assert w[1] > 1e-8 * w[-1]
+        assert abs(U[:, 0] @ nvec) >= math.cos(1e-3)
+        # positive definite on the complement of the surface normal
+        Q, _ = np.linalg.qr(np.column_stack([nvec, np.eye(6)[:, 1:]]))
+        B = Q[:, 1:]
+        np.linalg.cholesky(B.T @ P[i] @ B)
+
+
+def gauss_newton(orc, det, x0, C0, q, hits, iters=8):
+    """Batch MAP fit of the seed-level state with numerical Jacobians."""
+    W0 = np.linalg.cholesky(np.linalg.inv(C0)).T
+    Vis = [np.linalg.cholesky(np.linalg.inv(orc.hit_cov(hits[l], det.sigma_r, det.sigma_rphi,
+                                                          det.sigma_z))).T
+           for l in range(det.n_layers)]
+
+    def resid(x):
+        out = [W0 @ (x - x0)]
+        y = x
+        for l, r in enumerate(det.radii):
+            y, F, s, rc = orc.propagate(y, q, det.bz, r, l == 0)
+            out.append(Vis[l] @ (hits[l] - y[:3]))
+        return np.concatenate(out), y
+
+    x = x0.copy()
+    for _ in range(iters):
+        r0, _ = resid(x)
+        J = np.zeros((r0.size, 6))
+        for j in range(6):
+            h = 1e-7 * max(1.0, abs(x[j]))
+            a = x.copy()
+            a[j] += h
+            b = x.copy()
+            b[j] -= h
+            J[:, j] = (resid(a)[0] - resid(b)[0]) / (2 * h)
+        x = x - np.linalg.lstsq(J, r0, rcond=None)[0]
+    return resid(x)[1]
+
+
+def test_filter_agrees_with_gauss_newton(orc):
+    """The filter linearises at its running estimate; with a 1% prior the
+    linearisation error stays below 0.05 sigma of the batch optimum (it
+    grows with the prior width: about 0.1 sigma at 3%)."""
+    fs = consistent_fit_set(12, 23, f=0.01)
+    o = orc.fit(fs)
+    P = np_unpack(o["cov"])
+    for i in range(fs.n):
+        C0 = np_unpack(fs.cov[:, i:i + 1])[0]
+        xe = gauss_newton(orc, fs.det, fs.state[:, i], C0, int(fs.q[i]),
+                          fs.hits[:, :, i], iters=12)
+        sig = np.sqrt(np.diag(P[i]))
+        d = np.abs(o["state"][:, i] - xe)
+        assert np.all(d <= 0.05 * sig + 1e-9), (i, d / sig)
+
+
+def test_missing_layers_and_early_end(orc):
+    """A missing hit means propagate-only; the fit ends at the last hit."""
+    fs = consistent_fit_set(50, 24)
+    valid = np.ones((10, 50), np.uint8)
+    valid[4, :] = 0
+    valid[8:, :] = 0
+    o = orc.fit_arrays(fs.det, fs.state, fs.cov, fs.q, fs.hits, valid)
+    assert np.all(o["nupd"] == 7)
+    r = np.hypot(o["state"][0], o["state"][1])
+    np.testing.assert_allclose(r, fs.det.radii[7], rtol=1e-6)  # filtered point, near the cylinder
+    # dropping layer 5 equals fitting with a hit of infinite variance there:
+    # compare with a fit over the same hits without layer 5 via a detector
+    # that lacks that radius
+    det2 = tg.Detector(radii=tuple(r for i, r in enumerate(fs.det.radii[:8]) if i != 4))
+    keep = [0, 1, 2, 3, 5, 6, 7]
+    o2 = orc.fit_arrays(det2, fs.state, fs.cov, fs.q, fs.hits[keep], None)
+    np.testing.assert_allclose(o["state"], o2["state"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(o["chi2"], o2["chi2"], rtol=1e-10)
+
+
+def test_no_reach_status(orc):
+    """A track whose transverse circle is smaller than a layer stops there
+    with NO_REACH and keeps its last state inside that layer."""
+    fs = consistent_fit_set(5, 25)
+    st = fs.state.copy()
+    pt_low = 0.9 * 0.00299792458 * 3.8 * 30.0 / 2  # circle diameter 27 cm
+    phi = np.arctan2(st[4], st[3])
+    st[3] = pt_low * np.cos(phi)
+    st[4] = pt_low * np.sin(phi)
+    valid = np.zeros((10, 5), np.uint8)
+    valid[0] = 1
+    valid[9] = 1
+    P0 = np.zeros((5, 6, 6))
+    P0[:] = np.diag([1e-4, 1e-4, 1e-2, (0.01 * pt_low) ** 2, (0.01 * pt_low) ** 2, 1e-4])
+    cov = np.stack([P0[:, i, j] for i in range(6) for j in range(i, 6)])
+    o = orc.fit_arrays(fs.det, st, cov, fs.q, fs.hits, valid)
+    assert np.all(o["status"] & orc.NO_REACH)
+    r = np.hypot(o["state"][0], o["state"][1])
+    # the last layer it reached: inside the track's circle (diameter 27 cm
+    # around a centre up to ~4 cm off the axis), short of the hit layer
+    assert np.all(r < 32.0)
+    assert np.all(np.min(np.abs(r[:, None] - np.array(fs.det.radii)[None]), axis=1) < 1e-9)
+    assert np.all(o["nupd"] == 1)
