@@ -1,0 +1,230 @@
+"""Benchmark: batched Kalman-filter track fitting on one MI355X.
+
+Workload: 1,000,000 synthetic tracks on 10 cylindrical barrel layers
+(r = 4..40 cm, uniform Bz = 3.8 T, no material), pT log-uniform 0.5-100
+GeV, |eta| < 1, hits smeared by 0.01 cm in r-phi and 0.1 cm in z, seeds
+drawn around the truth.  One step = one fit of every track (propagate to
+each layer along the helix, Kalman update with its hit) on inputs already
+resident in HBM.  The headline is the FP32-bulk path; the plain FP64 path,
+the per-layer graph sweep and the FP64 CPU oracle are measured beside it.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of the fit per track and layer, counted from the
+# implementation's formulas (propagation in the storage precision, update in
+# FP64; an FMA counts 2).  See the measurement section of the design notes.
+FLOP_PROP_PER_LAYER = 860      # path solve (3 Newton steps), transport, Jacobian, F P F^T
+FLOP_UPD_PER_LAYER = 585       # V, S, S^-1, chi2, gain, state, Joseph covariance
+PEAK_FP32 = 157.3e12           # MI355X vector FP32 (datasheet, packed issue)
+PEAK_FP64 = 78.6e12            # MI355X vector FP64
+HBM_PEAK = 8.0e12              # bytes/s
+
+
+def sweep_bytes_per_track_layer(prec_bytes):
+    """HBM bytes of one layer step of one track in the per-layer sweep:
+    read + write state (6) and covariance (21), read the hit (3) and its
+    valid flag, charge, end layer, status, chi2 and hit count, write status,
+    chi2, hit count; FP32 storage adds the double position round trip."""
+    b = 2 * 27 * prec_bytes + 3 * prec_bytes + 1 + 1 + 1 + 2 * (4 + 8 + 4)
+    if prec_bytes == 4:
+        b += 2 * 3 * 8
+    return b
+
+
+def fused_bytes_per_track(prec_bytes, n_layers):
+    """HBM bytes of one track in the fused fit: seed state + covariance,
+    charge, hits and valid flags in; state, covariance, chi2, count, status out."""
+    return (27 * prec_bytes + 1 + n_layers * (3 * prec_bytes + 1)) + (27 * prec_bytes + 8 + 4 + 4)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU work of the oracle sample (core-seconds)")
+    ap.add_argument("--profile", action="store_true",
+                    help="only the timed FP32-bulk loop (for rocprofv3 runs)")
+    return ap.parse_args()
+
+
+def timed_loop(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def per_launch_ms(fn, reps, torch):
+    """Average duration of one launch, from events recorded on the stream the
+    kernels run on (torch's current stream, which the binding passes down)."""
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record(s)
+        fn()
+        b.record(s)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by tracks/events with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1605_05508_amd as ktf
+    import trackgen as tg
+    from tests.helpers import fit_inputs  # device staging of generated arrays
+
+    print(f"[bench] generating {args.n} tracks", file=sys.stderr, flush=True)
+    fs = tg.config2(n=args.n)
+    n, L = fs.n, fs.det.n_layers
+    ctx = ktf.Context.for_detector(fs.det)
+    d32 = fit_inputs(fs, "fp32b")
+    d64 = fit_inputs(fs, "fp64")
+    out32 = ctx.alloc_fit_out(n, d32["state"].shape[1], torch.float32)
+    out64 = ctx.alloc_fit_out(n, d64["state"].shape[1], torch.float64)
+    print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
+    ctx.autotune_fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], out=out32)
+    ctx.autotune_fit(d64["state"], d64["cov"], d64["q"], d64["hits"], d64["valid"], out=out64)
+    torch.cuda.synchronize()
+
+    def run32(mode="auto"):
+        ctx.fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], mode=mode, out=out32)
+
+    def run64(mode="auto"):
+        ctx.fit(d64["state"], d64["cov"], d64["q"], d64["hits"], d64["valid"], mode=mode, out=out64)
+
+    print("[bench] timing FP32-bulk fused fit", file=sys.stderr, flush=True)
+    ms, wall_ms = timed_loop(run32, args.steps, args.warmup, torch)
+    if args.profile:
+        print(json.dumps({"ms_per_step": ms, "n": n}))
+        return
+    k_ms = per_launch_ms(run32, 10, torch)
+
+    print("[bench] timing FP64 fused, graph sweeps", file=sys.stderr, flush=True)
+    ms64, _ = timed_loop(run64, max(3, args.steps // 2), 2, torch)
+    ms32_sw, _ = timed_loop(lambda: run32("sweep_graph"), max(3, args.steps // 2), 2, torch)
+    ms64_sw, _ = timed_loop(lambda: run64("sweep_graph"), max(3, args.steps // 2), 2, torch)
+
+    # results of the timed configurations, for the error report
+    run32()
+    run64()
+    torch.cuda.synchronize()
+    g32 = {k: v.cpu().numpy()[..., :n] for k, v in out32.items()}
+    g64 = {k: v.cpu().numpy()[..., :n] for k, v in out64.items()}
+
+    # roofline of the dominant kernel (the fused FP32-bulk fit)
+    f32 = FLOP_PROP_PER_LAYER * L * n
+    f64 = FLOP_UPD_PER_LAYER * L * n
+    t_bound = f32 / PEAK_FP32 + f64 / PEAK_FP64
+    mixed_peak = (f32 + f64) / t_bound
+    achieved = (f32 + f64) / (k_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(mixed_peak / 1e12, 1),
+            "unit": "TFLOP/s", "frac": round(achieved / mixed_peak, 4), "traffic": None,
+            "kernel": "fit_fused_kernel<float,float>", "kernel_ms": round(k_ms, 4),
+            "flop_per_track": (FLOP_PROP_PER_LAYER + FLOP_UPD_PER_LAYER) * L,
+            "hbm_GBps": round(fused_bytes_per_track(4, L) * n / (k_ms * 1e-3) / 1e9, 1)}
+    sweep = {}
+    for name, msv, pb in [("fp32b", ms32_sw, 4), ("fp64", ms64_sw, 8)]:
+        by = sweep_bytes_per_track_layer(pb) * L * n
+        sweep[name] = {"tracks_per_s": round(n / (msv * 1e-3)), "ms": round(msv, 4),
+                       "hbm_GBps": round(by / (msv * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(by / (msv * 1e-3) / HBM_PEAK, 4)}
+
+    result = {
+        "metric": "fitted tracks/s FP32-bulk vs FP64 plain at pull-RMS match; p50/p99 event ms",
+        "value": round(n / (ms * 1e-3)),
+        "unit": "tracks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "FP32-bulk vs FP64 fit at scale: 1,000,000 tracks, 10 barrel layers "
+                               "r=4..40 cm, Bz=3.8 T, pT log-uniform 0.5-100 GeV",
+                   "tracks": n, "layers": L, "precision": "fp32-bulk (fp64 S-inverse and Joseph update)",
+                   "launch": ctx.tuned_shape("fp32b", n)},
+        "roofline": roof,
+        "fp64_plain": {"tracks_per_s": round(n / (ms64 * 1e-3)), "ms": round(ms64, 4),
+                       "launch": ctx.tuned_shape("fp64", n)},
+        "speedup_fp32b_over_fp64": round(ms64 / ms, 3),
+        "sweep_graph": sweep,
+        "wall_ms_per_step": round(wall_ms, 4),
+    }
+
+    if not args.no_cpu:
+        import oracle
+        cores = oracle.default_threads()
+        # size the sample for about args.cpu_seconds of CPU work
+        probe = 2000
+        t0 = time.perf_counter()
+        oracle.fit(fs.subset(np.arange(probe)), nthreads=1)
+        per_track = (time.perf_counter() - t0) / probe
+        m = int(min(n, max(probe, args.cpu_seconds / per_track)))
+        sub = fs.subset(np.arange(m))
+        print(f"[bench] CPU oracle on {m} tracks x {cores} threads", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        o = oracle.fit(sub, nthreads=cores)
+        t_cpu = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(m / t_cpu), "unit": "tracks/s", "cores": cores,
+                                  "kind": "oracle",
+                                  "sample": f"first {m} of the {n} tracks, FP64 scalar C, "
+                                            f"{cores} threads, wall {t_cpu:.2f} s"}
+        # accuracy of both GPU paths on the oracle's sample
+        from tests.helpers import fp32_errors, pulls
+        acc = {}
+        for name, g in (("fp32b", g32), ("fp64", g64)):
+            gs = {k: v[..., :m] for k, v in g.items()}
+            e_pos, e_mom = fp32_errors(gs, o, 40.0)
+            pg = pulls(gs["state"], gs["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
+            po = pulls(o["state"], o["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
+            acc[name] = {"e_pos_max": float(e_pos.max()), "e_mom_max": float(e_mom.max()),
+                         "e_mom_p999": float(np.quantile(e_mom, 0.999)),
+                         "pull_rms_ratio": {kk: round(float(np.sqrt(np.mean(pg[kk] ** 2)) /
+                                                            np.sqrt(np.mean(po[kk] ** 2))), 5)
+                                            for kk in pg},
+                         "status_mismatch": int(np.sum(gs["status"].astype(np.uint32) != o["status"]))}
+        acc["oracle_pull_rms"] = {kk: round(float(np.sqrt(np.mean(v ** 2))), 4) for kk, v in po.items()}
+        result["accuracy_vs_oracle"] = acc
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * ktf.h -- C-ABI of libktf: batched Kalman-filter track fitting and
+ * combinatorial track building on AMD MI355X (gfx950).
+ *
+ * The problem statement follows the paper's Kalman-filter tracking (Sec. 2):
+ * seeds -- "an initial estimate of the track parameters based on a few hits
+ * in a subset of the innermost layers" -- and hits on cylindrical barrel
+ * layers go in; building (Sec. 3) collects compatible hits layer by layer,
+ * keeping the best candidates per seed by chi2 (the clone engine of
+ * Sec. 3.1); fitting runs the filter over each track's hits; fitted track
+ * parameters, covariances and chi2 come out.
+ *
+ * Conventions (all calls):
+ *  - Units cm, GeV, tesla; the field is uniform along +z.
+ *  - Track state (x, y, z, px, py, pz) in the global frame, on the surface of
+ *    the layer it was last propagated to.  Covariances are symmetric 6x6
+ *    stored as the 21-value upper triangle in row order
+ *    (00,01,02,03,04,05,11,12,13,14,15,22,...,55).
+ *  - Device arrays are structure-of-arrays, element-major: component c of
+ *    track i is at [c * pitch + i], pitch >= n (a multiple of 64 keeps
+ *    loads aligned).  Element type is double for KTF_FP64 and float for
+ *    KTF_FP32_BULK unless a field says otherwise.
+ *  - Every pointer named "device" must be device memory of the current HIP
+ *    device; "host" pointers are ordinary host memory.  The caller owns all
+ *    buffers it passes; the library owns its context, its workspace and its
+ *    staging copies.
+ *  - Calls return KTF_OK (0) or a negative error code; ktf_last_error()
+ *    returns a message for the last failure on a context.  Problems of a
+ *    single track never fail a call: they set bits in its status word.
+ */
+#ifndef KTF_H
+#define KTF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KTF_VERSION_MAJOR 0
+#define KTF_VERSION_MINOR 1
+
+#define KTF_MAX_LAYERS 32
+#define KTF_MAX_CANDS 16
+
+/* return codes */
+#define KTF_OK 0
+#define KTF_EINVAL (-1)     /* bad argument: null pointer, pitch < n, bad config   */
+#define KTF_ENOMEM (-2)     /* device memory or HBM budget exhausted               */
+#define KTF_EAGAIN (-3)     /* ktf_poll: result not ready yet                      */
+#define KTF_ENOTFOUND (-4)  /* ktf_poll: unknown or already collected ticket       */
+#define KTF_EDEVICE (-5)    /* HIP runtime error (message in ktf_last_error)       */
+
+/* per-track status bits */
+#define KTF_ST_NO_REACH 1u   /* helix never reaches the next layer: track stops   */
+#define KTF_ST_S_NOT_PD 2u   /* residual covariance S not positive definite: hit skipped */
+#define KTF_ST_NONFINITE 4u  /* non-finite state or covariance: track stops       */
+
+typedef enum {
+  KTF_FP64 = 0,      /* everything in double                                     */
+  KTF_FP32_BULK = 1  /* float storage, float propagation (path solve, transport,
+                        Jacobian, F P F^T); the update (S, S^-1, chi2, gain,
+                        state and Joseph covariance update) in double            */
+} ktf_precision;
+
+typedef enum {
+  KTF_FIT_AUTO = 0,        /* fused kernel with the tuned launch shape            */
+  KTF_FIT_FUSED = 1,       /* one kernel: all layers of a track in registers      */
+  KTF_FIT_PERSISTENT = 2,  /* fused body, persistent blocks pulling track tiles    */
+  KTF_FIT_SWEEP = 3,       /* one launch per layer, state round-trips HBM          */
+  KTF_FIT_SWEEP_GRAPH = 4  /* the per-layer launches captured once as a hipGraph
+                              and replayed                                        */
+} ktf_fit_mode;
+
+typedef struct ktf_ctx ktf_ctx;
+
+/* Detector, resolution and building parameters; copied by ktf_create. */
+typedef struct {
+  int32_t n_layers;        /* 1..KTF_MAX_LAYERS                                  */
+  const double *layer_r;   /* host [n_layers], increasing radii (cm)             */
+  double z_half;           /* barrel half-length (cm), binning range             */
+  double bz;               /* field (T)                                          */
+  double sigma_r;          /* radial hit variance term of V (cm), > 0            */
+  double sigma_rphi;       /* hit resolution along phi (cm)                      */
+  double sigma_z;          /* hit resolution along z (cm)                        */
+  int32_t n_zbins;         /* hit bins along z per layer                         */
+  int32_t n_phibins;       /* hit bins along phi per layer                       */
+  int32_t max_cands;       /* candidates kept per seed per layer, 1..KTF_MAX_CANDS */
+  int32_t max_missed;      /* layers a candidate may skip                        */
+  int32_t n_seed_layers;   /* innermost layers fitted with the seed's own hits   */
+  double chi2_cut;         /* a hit is compatible when its chi2 increment < cut  */
+  uint64_t hbm_budget_bytes; /* serving: device bytes the in-flight events may use */
+  int32_t max_inflight;    /* serving: events on the device at once              */
+} ktf_config;
+
+/* Create a context on the current HIP device.  Returns KTF_EINVAL for an
+ * invalid config, KTF_EDEVICE when no device is usable. */
+int ktf_create(const ktf_config *cfg, ktf_ctx **out);
+/* Destroy a context: stops the serving thread (pending tickets are dropped)
+ * and frees its device memory.  NULL is accepted. */
+int ktf_destroy(ktf_ctx *ctx);
+/* Message for the last failed call on ctx (never NULL; "" if none). */
+const char *ktf_last_error(const ktf_ctx *ctx);
+
+/* ---------------------------------------------------------------- fitting
+ * Kalman-filter fit (Sec. 2: "repeatedly apply the KF algorithm without
+ * branching" over a fixed hit set).  For each track: start from the seed on
+ * layer 0's surface, then for l = 0 .. last: propagate along the helix to
+ * layer l's cylinder (the first step takes the root of least |s|, so a seed
+ * slightly off the surface is projected onto it), propagate the covariance
+ * with the surface-constrained Jacobian, and if the track has a hit there
+ * update with it.  The fit ends at the track's last layer with a hit.
+ */
+typedef struct {
+  int64_t n;                /* tracks                                            */
+  int64_t pitch;            /* >= n                                              */
+  ktf_precision prec;
+  const void *seed_state;   /* device [6][pitch]                                 */
+  const void *seed_cov;     /* device [21][pitch]                                */
+  const int8_t *charge;     /* device [pitch], +1 or -1                          */
+  const void *hits;         /* device [n_layers][3][pitch]: x, y, z              */
+  const uint8_t *hit_valid; /* device [n_layers][pitch], 0 = no hit; NULL = all   */
+} ktf_fit_in;
+
+typedef struct {
+  void *state;              /* device [6][pitch]: filtered state at the last layer */
+  void *cov;                /* device [21][pitch]                                */
+  double *chi2;             /* device [n]: sum of chi2 increments                */
+  int32_t *n_upd;           /* device [n]: hits used (ndf = 2 n_upd for a
+                               consistent prior)                                */
+  uint32_t *status;         /* device [n]: KTF_ST_* bits                         */
+} ktf_fit_out;
+
+/* Enqueue a fit on hip_stream (NULL = default stream); returns once the
+ * work is enqueued.  Inputs must stay valid until the stream reaches it.
+ * Outputs may not alias inputs.  KTF_EINVAL on null pointers or pitch < n.
+ * The sweep modes keep per-track scratch in the context: two sweeps on one
+ * context must be ordered (same stream, or synchronized by the caller). */
+int ktf_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, ktf_fit_mode mode,
+            void *hip_stream);
+
+/* Time each launch shape of the fused fit (block size x plain/persistent) on
+ * the given inputs and keep the fastest for this precision and size class;
+ * KTF_FIT_AUTO then uses it.  Runs synchronously on hip_stream and
+ * overwrites out. */
+int ktf_autotune_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, void *hip_stream);
+/* Describe the chosen launch shape for (prec, n) as text into buf. */
+int ktf_tuned_shape(ktf_ctx *ctx, ktf_precision prec, int64_t n, char *buf, size_t len);
+
+/* --------------------------------------------------------------- building
+ * Combinatorial track building with the clone engine (Sec. 3, 3.1), for a
+ * batch of independent events.  Per layer the hits are binned (n_zbins x
+ * n_phibins over |z| < z_half and phi in [-pi, pi)) so that each candidate
+ * only scores hits near its prediction; the compatible set is by definition
+ * every hit with chi2 increment < chi2_cut, the bins only accelerate it.
+ * Per seed: fit the seed's hits on the first n_seed_layers layers, then for
+ * each further layer propagate every live candidate, score the hits, and
+ * record (parent, hit, chi2 total, hits + 1); a candidate with no compatible
+ * hit records one missed layer while it has fewer than max_missed, else it
+ * ends.  Records are ranked by (more hits, lower chi2 total, lower parent
+ * rank, lower hit index, missed layer last); the best max_cands are cloned
+ * from their parents and updated with their hits.  The result per seed is
+ * the best of the survivors and the ended candidates by (more hits, lower
+ * chi2, earlier end, lower rank).  Hit indices are positions within the
+ * (event, layer) hit list as given.
+ */
+typedef struct {
+  int32_t n_events;
+  const int64_t *seed_off;  /* host [n_events+1]: seeds of event e are
+                               [seed_off[e], seed_off[e+1])                     */
+  const int64_t *hit_off;   /* host [n_events*n_layers+1]: hits of (event e,
+                               layer l) are [hit_off[e*L+l], hit_off[e*L+l+1]) */
+  int64_t hit_pitch;        /* >= hit_off[n_events*n_layers]                     */
+  const void *hits;         /* device [3][hit_pitch]: x, y, z                    */
+  int64_t seed_pitch;       /* >= seed_off[n_events]                              */
+  const void *seed_state;   /* device [6][seed_pitch]                            */
+  const void *seed_cov;     /* device [21][seed_pitch]                           */
+  const int8_t *charge;     /* device [seed_pitch]                               */
+  const int32_t *seed_hit;  /* device [n_seed_layers][seed_pitch]: index of the
+                               seed's hit on each seed layer, -1 = none         */
+  ktf_precision prec;
+} ktf_event_batch;
+
+typedef struct {
+  int32_t *hit_idx;         /* device [n_layers][seed_pitch], -1 = no hit        */
+  void *state;              /* device [6][seed_pitch]: the chosen candidate      */
+  void *cov;                /* device [21][seed_pitch]                           */
+  double *chi2;             /* device [seed_pitch]                               */
+  int32_t *n_hits;          /* device [seed_pitch]                               */
+  uint32_t *status;         /* device [seed_pitch]                               */
+  int32_t *cand_hist;       /* optional device [n_layers][max_cands][2][seed_pitch]:
+                               (parent rank, hit) of each candidate kept after
+                               each layer, -1 where none; NULL to skip          */
+  int32_t *cand_count;      /* optional device [n_layers][seed_pitch]            */
+} ktf_build_out;
+
+/* Enqueue building of all events of the batch on hip_stream.  Host offset
+ * arrays are read during the call.  Uses context workspace (grown as
+ * needed, KTF_ENOMEM when it cannot be); a call first waits for the device
+ * work of the previous ktf_build / ktf_bin_hits on the same context, which
+ * shares that workspace.  Calls on one context must not overlap in time
+ * from several host threads. */
+int ktf_build(ktf_ctx *ctx, const ktf_event_batch *ev, ktf_build_out *out, void *hip_stream);
+
+/* Bin the hits of every (event, layer) of a batch: offsets
+ * [n_events*n_layers][n_zbins*n_phibins+1] (device int32, CSR within each
+ * (event, layer)) and perm [hit_pitch] (device int32: original index, within
+ * its (event, layer), of the hit at each binned position; binned positions
+ * are ordered by (bin, original index)).  Exposed for tests and tools. */
+int ktf_bin_hits(ktf_ctx *ctx, const ktf_event_batch *ev, int32_t *offsets, int32_t *perm,
+                 void *hip_stream);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching: events are submitted from host memory as they
+ * arrive; a scheduler thread admits queued events while the in-flight
+ * device footprint stays within hbm_budget_bytes and fewer than
+ * max_inflight events are in flight, runs build + final fit for each
+ * admitted group on its own stream (groups overlap on the device), and
+ * returns results through ktf_poll.  Results are identical to running the
+ * event alone.
+ */
+typedef struct {
+  int64_t n_seeds;
+  const int64_t *hit_off;   /* host [n_layers+1]                                 */
+  const float *hits;        /* host [3][hit_off[n_layers]] (SoA)                 */
+  const float *seed_state;  /* host [6][n_seeds]                                 */
+  const float *seed_cov;    /* host [21][n_seeds]                                */
+  const int8_t *charge;     /* host [n_seeds]                                    */
+  const int32_t *seed_hit;  /* host [n_seed_layers][n_seeds]                     */
+  ktf_precision prec;       /* arithmetic of build and fit for this event        */
+} ktf_event_host;
+
+typedef struct {
+  int32_t *hit_idx;         /* host [n_layers][n_seeds]                          */
+  float *state;             /* host [6][n_seeds]: final fit over the built hits  */
+  float *cov;               /* host [21][n_seeds]                                */
+  double *chi2;             /* host [n_seeds]: final fit chi2                    */
+  int32_t *n_hits;          /* host [n_seeds]                                    */
+  uint32_t *status;         /* host [n_seeds]                                    */
+  double t_submit, t_admit, t_done; /* seconds on the library's monotonic clock  */
+} ktf_result_host;
+
+/* Copy the event into library staging and queue it; returns a ticket.  The
+ * caller may free its buffers after return.  KTF_ENOMEM if the event alone
+ * exceeds the HBM budget.  Thread-safe. */
+int ktf_submit(ktf_ctx *ctx, const ktf_event_host *ev, uint64_t *ticket);
+/* Collect a finished event into the caller's host buffers (sized for the
+ * event's n_seeds) and forget the ticket.  KTF_EAGAIN while pending,
+ * KTF_ENOTFOUND for an unknown ticket.  Thread-safe. */
+int ktf_poll(ktf_ctx *ctx, uint64_t ticket, ktf_result_host *out);
+/* Seconds on the clock used for t_submit / t_admit / t_done. */
+double ktf_now(void);
+/* Events queued, in flight and finished-but-uncollected. */
+int ktf_serving_stats(ktf_ctx *ctx, int64_t *queued, int64_t *inflight, int64_t *done);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KTF_H */

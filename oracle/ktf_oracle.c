@@ -523,6 +523,7 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
   c->status = 0;
   for (int l = 0; l < L; ++l) c->hit[l] = -1;
   int nlive = 1;
+  int seed_reached = 0;
   for (int l = 0; l < NSL && l < L; ++l) {
     double xp[6], F[36], Pp[36], s;
     if (orc_propagate(c->x, q, g->bz, g->radii[l], l == 0, xp, F, &s)) {
@@ -530,6 +531,7 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
       nlive = 0;
       break;
     }
+    seed_reached = l + 1;
     orc_cov_propagate(c->P, F, Pp);
     int h = seed_hit[l];
     memcpy(c->x, xp, sizeof xp);
@@ -553,13 +555,16 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
     best = *c;
     have_best = 1;
   }
-  if (dbg_n)
-    for (int l = 0; l < NSL && l < L; ++l) dbg_n[l] = nlive;
-  if (dbg)
-    for (int l = 0; l < NSL && l < L; ++l) {
+  /* debug records of the seed layers: one candidate on each layer the seed
+   * reached, with the hit it actually took */
+  for (int l = 0; l < NSL && l < L; ++l) {
+    const int reached = l < seed_reached;
+    if (dbg_n) dbg_n[l] = reached;
+    if (dbg && reached) {
       dbg[(l * NC) * 2 + 0] = 0;
-      dbg[(l * NC) * 2 + 1] = seed_hit[l];
+      dbg[(l * NC) * 2 + 1] = c->hit[l];
     }
+  }
 
   for (int l = NSL; l < L && nlive > 0; ++l) {
     const int64_t h0 = layer_off[l], h1 = layer_off[l + 1];

@@ -1,0 +1,275 @@
+// api.hip -- C-ABI entry points: context, fitting, launch-shape tuning.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "ctx.hpp"
+
+namespace ktf {
+
+int fail(ktf_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->set_error(buf);
+  return code;
+}
+
+int hip_fail(ktf_ctx* c, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(c, KTF_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(c, KTF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+FitArgs make_fit_args(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out) {
+  FitArgs a{};
+  a.n = in->n;
+  a.pitch = in->pitch;
+  a.state = in->seed_state;
+  a.cov = in->seed_cov;
+  a.q = in->charge;
+  a.hits = in->hits;
+  a.valid = in->hit_valid;
+  a.state_o = out->state;
+  a.cov_o = out->cov;
+  a.chi2 = out->chi2;
+  a.nupd = out->n_upd;
+  a.status = out->status;
+  a.n_layers = c->cfg.n_layers;
+  a.bz = c->cfg.bz;
+  a.hr.sr2 = c->cfg.sigma_r * c->cfg.sigma_r;
+  a.hr.srphi2 = c->cfg.sigma_rphi * c->cfg.sigma_rphi;
+  a.hr.sz2 = c->cfg.sigma_z * c->cfg.sigma_z;
+  for (int l = 0; l < c->cfg.n_layers; ++l) a.radii[l] = c->radii[l];
+  return a;
+}
+
+static int size_class(int64_t n) {
+  int k = 0;
+  while ((int64_t(1) << (k + 1)) <= n && k < 62) ++k;
+  return k;
+}
+
+static int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* out) {
+  if (!c || !in || !out) return fail(c, KTF_EINVAL, "ktf_fit: null argument");
+  if (in->n < 0 || in->pitch < in->n)
+    return fail(c, KTF_EINVAL, "ktf_fit: n=%lld pitch=%lld", (long long)in->n, (long long)in->pitch);
+  if (in->prec != KTF_FP64 && in->prec != KTF_FP32_BULK)
+    return fail(c, KTF_EINVAL, "ktf_fit: unknown precision %d", (int)in->prec);
+  if (in->n > 0 && (!in->seed_state || !in->seed_cov || !in->charge || !in->hits || !out->state ||
+                    !out->cov || !out->chi2 || !out->n_upd || !out->status))
+    return fail(c, KTF_EINVAL, "ktf_fit: null buffer");
+  return KTF_OK;
+}
+
+// blocks per CU for the persistent kernel, from the occupancy calculator
+int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs);
+
+static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode, int bs,
+                   bool persistent, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (mode == KTF_FIT_SWEEP || mode == KTF_FIT_SWEEP_GRAPH) {
+    if ((e = c->fit_lend.ensure((size_t)a.pitch)) != hipSuccess) return hip_fail(c, e, "sweep workspace");
+    a.lend = static_cast<uint8_t*>(c->fit_lend.p);
+    if (prec == KTF_FP32_BULK) {
+      if ((e = c->fit_pos.ensure((size_t)a.pitch * 3 * sizeof(double))) != hipSuccess)
+        return hip_fail(c, e, "sweep workspace");
+      a.pos_ws = static_cast<double*>(c->fit_pos.p);
+    }
+    if (mode == KTF_FIT_SWEEP) {
+      for (int l = 0; l < a.n_layers && e == hipSuccess; ++l) e = launch_fit_layer(a, prec, l, st);
+      return e == hipSuccess ? KTF_OK : hip_fail(c, e, "fit layer launch");
+    }
+    // graph: capture the per-layer launches once per argument set, replay
+    SweepGraph& g = c->sweep;
+    if (!g.valid || g.prec != prec || memcmp(&g.args, &a, sizeof a) != 0) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      g.exec = nullptr;
+      g.graph = nullptr;
+      g.valid = false;
+      e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+      for (int l = 0; l < a.n_layers && e == hipSuccess; ++l)
+        e = launch_fit_layer(a, prec, l, c->capture_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
+      if (e == hipSuccess) e = e2;
+      if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(c, e, "sweep graph capture");
+      }
+      e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(c, e, "sweep graph instantiate");
+      }
+      g.graph = graph;
+      g.args = a;
+      g.prec = prec;
+      g.valid = true;
+    }
+    e = hipGraphLaunch(g.exec, st);
+    return e == hipSuccess ? KTF_OK : hip_fail(c, e, "sweep graph launch");
+  }
+  int pblocks = 0;
+  if (persistent) {
+    if ((e = c->counters.ensure(64 * sizeof(unsigned long long))) != hipSuccess)
+      return hip_fail(c, e, "counters");
+    a.counters = static_cast<unsigned long long*>(c->counters.p);
+    a.tile_count = (a.n + bs - 1) / bs;
+    pblocks = persistent_blocks(c, prec, bs) * c->n_cu;
+    if (pblocks <= 0) pblocks = c->n_cu;
+    if ((e = launch_fill_u64(a.counters, 1, 0ull, st)) != hipSuccess) return hip_fail(c, e, "fill");
+  }
+  e = launch_fit_fused(a, prec, bs, persistent, pblocks, st);
+  return e == hipSuccess ? KTF_OK : hip_fail(c, e, "fit launch");
+}
+
+}  // namespace ktf
+
+using namespace ktf;
+
+extern "C" {
+
+int ktf_create(const ktf_config* cfg, ktf_ctx** out) {
+  if (!cfg || !out) return KTF_EINVAL;
+  *out = nullptr;
+  if (cfg->n_layers < 1 || cfg->n_layers > KTF_MAX_LAYERS || !cfg->layer_r) return KTF_EINVAL;
+  for (int l = 0; l < cfg->n_layers; ++l)
+    if (!(cfg->layer_r[l] > 0.0) || (l > 0 && !(cfg->layer_r[l] > cfg->layer_r[l - 1])))
+      return KTF_EINVAL;
+  if (!(cfg->sigma_r > 0.0) || !(cfg->sigma_rphi > 0.0) || !(cfg->sigma_z > 0.0)) return KTF_EINVAL;
+  if (cfg->max_cands < 1 || cfg->max_cands > KTF_MAX_CANDS || cfg->max_missed < 0 ||
+      cfg->n_seed_layers < 1 || cfg->n_seed_layers > cfg->n_layers || cfg->n_zbins < 1 ||
+      cfg->n_phibins < 1 || !(cfg->z_half > 0.0))
+    return KTF_EINVAL;
+  ktf_ctx* c = new ktf_ctx();
+  c->cfg = *cfg;
+  c->radii.assign(cfg->layer_r, cfg->layer_r + cfg->n_layers);
+  c->cfg.layer_r = c->radii.data();
+  hipError_t e = hipGetDevice(&c->device);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, c->device);
+  if (e == hipSuccess) {
+    c->n_cu = prop.multiProcessorCount;
+    c->gcn_arch = prop.gcnArchName;
+    e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+  }
+  if (e != hipSuccess) {
+    delete c;
+    return KTF_EDEVICE;
+  }
+  *out = c;
+  return KTF_OK;
+}
+
+int ktf_destroy(ktf_ctx* c) {
+  if (!c) return KTF_OK;
+  serve_shutdown(c);
+  (void)hipDeviceSynchronize();
+  if (c->sweep.exec) (void)hipGraphExecDestroy(c->sweep.exec);
+  if (c->sweep.graph) (void)hipGraphDestroy(c->sweep.graph);
+  c->fit_lend.release();
+  c->fit_pos.release();
+  c->counters.release();
+  for (DevBuf* b : {&c->b_off, &c->b_perm, &c->b_binned, &c->b_cand[0], &c->b_cand[1], &c->b_prop,
+                    &c->b_rec, &c->b_hist, &c->b_best, &c->b_misc, &c->b_stage})
+    b->release();
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  if (c->build_done) (void)hipEventDestroy(c->build_done);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  delete c;
+  return KTF_OK;
+}
+
+const char* ktf_last_error(const ktf_ctx* c) {
+  if (!c) return "";
+  return c->last_error.c_str();
+}
+
+int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mode,
+            void* hip_stream) {
+  int rc = check_fit_args(c, in, out);
+  if (rc) return rc;
+  if (in->n == 0) return KTF_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  FitArgs a = make_fit_args(c, in, out);
+  int bs = 256;
+  bool persistent = false;
+  switch (mode) {
+    case KTF_FIT_AUTO: {
+      auto it = c->tuned.find({(int)in->prec, size_class(in->n)});
+      if (it != c->tuned.end()) {
+        bs = it->second.block;
+        persistent = it->second.persistent;
+      }
+      break;
+    }
+    case KTF_FIT_FUSED: break;
+    case KTF_FIT_PERSISTENT: persistent = true; break;
+    case KTF_FIT_SWEEP:
+    case KTF_FIT_SWEEP_GRAPH: break;
+    default: return fail(c, KTF_EINVAL, "ktf_fit: unknown mode %d", (int)mode);
+  }
+  return run_fit(c, a, in->prec, mode, bs, persistent, st);
+}
+
+int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* hip_stream) {
+  int rc = check_fit_args(c, in, out);
+  if (rc) return rc;
+  if (in->n == 0) return KTF_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  FitArgs a = make_fit_args(c, in, out);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(c, KTF_EDEVICE, "autotune: event create");
+  TunedShape best;
+  best.ms = 1e30f;
+  for (int bs : kBlockSizes) {
+    for (int pers = 0; pers < 2; ++pers) {
+      rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, pers != 0, st);  // warm-up
+      if (rc) break;
+      float tot = 0.f;
+      const int reps = 3;
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps && rc == 0; ++r) rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, pers != 0, st);
+      (void)hipEventRecord(e1, st);
+      if (rc) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(c, KTF_EDEVICE, "autotune: sync");
+        break;
+      }
+      (void)hipEventElapsedTime(&tot, e0, e1);
+      const float ms = tot / reps;
+      if (ms < best.ms) {
+        best.ms = ms;
+        best.block = bs;
+        best.persistent = pers != 0;
+        best.persistent_blocks = pers ? persistent_blocks(c, in->prec, bs) : 0;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  c->tuned[{(int)in->prec, size_class(in->n)}] = best;
+  return KTF_OK;
+}
+
+int ktf_tuned_shape(ktf_ctx* c, ktf_precision prec, int64_t n, char* buf, size_t len) {
+  if (!c || !buf || len == 0) return KTF_EINVAL;
+  auto it = c->tuned.find({(int)prec, size_class(n)});
+  if (it == c->tuned.end()) {
+    snprintf(buf, len, "{\"block\": 256, \"persistent\": false, \"tuned\": false}");
+  } else {
+    snprintf(buf, len, "{\"block\": %d, \"persistent\": %s, \"blocks_per_cu\": %d, \"ms\": %.4f, \"tuned\": true}",
+             it->second.block, it->second.persistent ? "true" : "false",
+             it->second.persistent_blocks, it->second.ms);
+  }
+  return KTF_OK;
+}
+
+}  // extern "C"

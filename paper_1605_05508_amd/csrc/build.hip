@@ -1,0 +1,941 @@
+// build.hip -- combinatorial track building with the clone engine (gfx950).
+//
+// Building (Sec. 3) extends every seed layer by layer.  The hits of each
+// (event, layer) are first placed in z x phi bins so that a candidate only
+// scores the hits near its prediction (the paper's fix for the "nHits"
+// problem: hits sorted in phi per bin and layer with phi bins as a fast
+// look-up).  Then, per layer, the clone engine (Sec. 3.1):
+//   score   one lane per live candidate: propagate to the layer, scan the
+//           bins inside a window that no compatible hit can lie outside of,
+//           keep the candidate's best records (a bookkeeping list) -- no
+//           candidate is copied here;
+//   select  one 16-lane group per seed: merge the candidates' sorted record
+//           lists with wave shuffles to the best max_cands by the ranking
+//           (more hits, lower chi2, lower parent rank, lower hit index, a
+//           missed layer last), then each selected record's lane clones its
+//           parent's propagated state and applies the Kalman update;
+//   final   one lane per seed: the best survivor or ended candidate, hit
+//           indices recovered by walking the per-layer (parent, hit) records.
+//
+// Layout: candidate slots are rank-major (slot = rank * seed_pitch + seed)
+// so waves of high ranks, mostly empty, retire at once; every per-slot
+// field is its own structure-of-arrays row.  Positions are kept in double,
+// momentum and covariance in the storage precision.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.hpp"
+#include "kf_math.hpp"
+
+namespace ktf {
+
+constexpr int kGroup = 16;  // lanes per seed in the select step (>= KTF_MAX_CANDS)
+constexpr double kPi = 3.14159265358979323846;
+
+template <typename T> struct BuildNewton;
+template <> struct BuildNewton<double> { static constexpr int n = 4; };
+template <> struct BuildNewton<float> { static constexpr int n = 3; };
+
+struct BuildArgs {
+  BuildGeom g;
+  int32_t n_events;
+  int32_t n_groups;        // n_events * n_layers
+  int32_t n_bins;          // n_zbins * n_phibins
+  int64_t n_seeds, sp;     // seeds, seed pitch
+  int64_t S;               // candidate slots = max_cands * sp
+  int64_t n_hits;          // total hits
+  int64_t hp;              // hit pitch
+  const int64_t* seed_off; // device [n_events+1]
+  const int64_t* hit_off;  // device [n_groups+1]
+  const void* hits;        // [3][hp]
+  const void* seed_state;  // [6][sp]
+  const void* seed_cov;    // [21][sp]
+  const int8_t* q;         // [sp]
+  const int32_t* seed_hit; // [nsl][sp]
+  // binning
+  int32_t* bin_off;        // [n_groups][n_bins+1]
+  int32_t* bin_cur;        // [n_groups][n_bins]
+  int32_t* hit_bin;        // [n_hits]
+  int32_t* perm;           // [n_hits]: local index of the hit at each binned position
+  void* hb;                // [3][n_hits]: binned coordinates
+  // candidates (double buffered), propagated parents, records
+  double* cpos[2];
+  void* cmom[2];
+  void* ccov[2];
+  double* cchi2[2];
+  uint32_t* cmeta[2];      // nh | nm << 8 | status << 16
+  double* ppos;
+  void* pmom;
+  void* pcov;
+  double* rchi;            // [max_cands][S]
+  int32_t* rhit;           // [max_cands][S]
+  int32_t* rcount;         // [S]: records, -1 ended (no reach), -2 ended (missed too often)
+  int32_t* hist;           // [L][max_cands][2][sp]
+  int32_t* count;          // [L][sp]
+  // best ended candidate per seed
+  double* bpos;
+  void* bmom;
+  void* bcov;
+  double* bchi2;
+  uint32_t* bmeta;
+  int32_t* bend;           // end layer, -1 = none
+  int32_t* brank;
+  // outputs
+  int32_t* o_hit;          // [L][sp]
+  void* o_state;
+  void* o_cov;
+  double* o_chi2;
+  int32_t* o_nhits;
+  uint32_t* o_status;
+};
+
+__device__ __forceinline__ int find_event(const int64_t* off, int n, int64_t j) {
+  int lo = 0, hi = n;  // off[lo] <= j < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= j) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t pack_meta(int nh, int nm, uint32_t st) {
+  return (uint32_t)nh | ((uint32_t)nm << 8) | (st << 16);
+}
+__device__ __forceinline__ int meta_nh(uint32_t m) { return (int)(m & 0xffu); }
+__device__ __forceinline__ int meta_nm(uint32_t m) { return (int)((m >> 8) & 0xffu); }
+__device__ __forceinline__ uint32_t meta_st(uint32_t m) { return m >> 16; }
+
+// bin of a hit: zbin = floor((z + zh) nz / (2 zh)) clamped, phibin =
+// floor((atan2(y, x) + pi) nphi / (2 pi)) mod nphi; same arithmetic order in
+// double as the definition, no contraction.
+__device__ __forceinline__ int hit_bin_of(double x, double y, double z, double zh, int nz, int nphi) {
+#pragma clang fp contract(off)
+  const double zf = floor((z + zh) * nz / (2.0 * zh));
+  const int zb = zf < 0.0 ? 0 : (zf > nz - 1 ? nz - 1 : (int)zf);
+  const double phi = atan2(y, x);
+  int pb = (int)floor((phi + kPi) * nphi / (2.0 * kPi));
+  pb = ((pb % nphi) + nphi) % nphi;
+  return zb * nphi + pb;
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename TS>
+__global__ void bin_count_kernel(BuildArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_hits) return;
+  const int g = find_event(a.hit_off, a.n_groups, j);
+  const TS* h = static_cast<const TS*>(a.hits);
+  const int b = hit_bin_of((double)h[j], (double)h[a.hp + j], (double)h[2 * a.hp + j], a.g.z_half,
+                           a.g.n_zbins, a.g.n_phibins);
+  a.hit_bin[j] = b;
+  atomicAdd(&a.bin_cur[(int64_t)g * a.n_bins + b], 1);
+}
+
+// one block per (event, layer): exclusive scan of the bin counts into the CSR
+// offsets, and the cursor reset to each bin's start
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(BuildArgs a) {
+  __shared__ int32_t part[kScanThreads];
+  const int g = blockIdx.x;
+  const int nb = a.n_bins;
+  int32_t* cnt = a.bin_cur + (int64_t)g * nb;
+  int32_t* off = a.bin_off + (int64_t)g * (nb + 1);
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = threadIdx.x * per;
+  const int b1 = min(nb, b0 + per);
+  int32_t s = 0;
+  for (int b = b0; b < b1; ++b) s += cnt[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {  // Hillis-Steele inclusive scan
+    const int32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int32_t run = part[threadIdx.x] - s;  // exclusive prefix of this thread's range
+  for (int b = b0; b < b1; ++b) {
+    const int32_t c = cnt[b];
+    off[b] = run;
+    cnt[b] = run;
+    run += c;
+  }
+  if (threadIdx.x == kScanThreads - 1) off[nb] = part[kScanThreads - 1];
+}
+
+__global__ void bin_scatter_kernel(BuildArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_hits) return;
+  const int g = find_event(a.hit_off, a.n_groups, j);
+  const int b = a.hit_bin[j];
+  const int32_t pos = atomicAdd(&a.bin_cur[(int64_t)g * a.n_bins + b], 1);
+  a.perm[a.hit_off[g] + pos] = (int32_t)(j - a.hit_off[g]);
+}
+
+// one lane per (event, layer, bin): order the bin's hits by original index
+// (the scatter's atomics left them in arrival order) and copy their
+// coordinates into binned order
+template <typename TS>
+__global__ void bin_sort_kernel(BuildArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)a.n_groups * a.n_bins) return;
+  const int g = (int)(t / a.n_bins);
+  const int b = (int)(t - (int64_t)g * a.n_bins);
+  const int32_t* off = a.bin_off + (int64_t)g * (a.n_bins + 1);
+  const int32_t lo = off[b], hi = off[b + 1];
+  if (lo == hi) return;
+  const int64_t base = a.hit_off[g];
+  int32_t* p = a.perm + base;
+  for (int32_t i = lo + 1; i < hi; ++i) {  // insertion sort, bins hold a few hits
+    const int32_t v = p[i];
+    int32_t k = i - 1;
+    while (k >= lo && p[k] > v) {
+      p[k + 1] = p[k];
+      --k;
+    }
+    p[k + 1] = v;
+  }
+  const TS* h = static_cast<const TS*>(a.hits);
+  TS* o = static_cast<TS*>(a.hb);
+  for (int32_t i = lo; i < hi; ++i) {
+    const int64_t src = base + p[i];
+    o[base + i] = h[src];
+    o[a.n_hits + base + i] = h[a.hp + src];
+    o[2 * a.n_hits + base + i] = h[2 * a.hp + src];
+  }
+}
+
+// ------------------------------------------------------------- candidates
+template <typename TS, typename TP>
+__device__ __forceinline__ void load_cand(const double* pos, const void* mom, const void* cov,
+                                          int64_t S, int64_t slot, TrackState<TP>& x, TP P[21]) {
+  const TS* m = static_cast<const TS*>(mom);
+  const TS* c = static_cast<const TS*>(cov);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x.pos[k] = pos[k * S + slot];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x.mom[k] = (TP)m[k * S + slot];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) P[k] = (TP)c[k * S + slot];
+}
+
+template <typename TS, typename TP>
+__device__ __forceinline__ void store_cand(double* pos, void* mom, void* cov, int64_t S, int64_t slot,
+                                           const TrackState<TP>& x, const TP P[21]) {
+  TS* m = static_cast<TS*>(mom);
+  TS* c = static_cast<TS*>(cov);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pos[k * S + slot] = x.pos[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k * S + slot] = (TS)x.mom[k];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k * S + slot] = (TS)P[k];
+}
+
+__device__ __forceinline__ HitRes hit_res(const BuildArgs& a) {
+  return HitRes{a.g.hr.sr2, a.g.hr.srphi2, a.g.hr.sz2};
+}
+
+// seed phase: fit each seed over the seed layers with its own hits
+template <typename TS, typename TP>
+__global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  const int L = a.g.n_layers, NSL = a.g.n_seed_layers;
+  const int e = find_event(a.seed_off, a.n_events, s);
+  const TS* st = static_cast<const TS*>(a.seed_state);
+  const TS* cv = static_cast<const TS*>(a.seed_cov);
+  TrackState<TP> x;
+  TP P[21];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * a.sp + s];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * a.sp + s];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * a.sp + s];
+  const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
+  const HitRes hr = hit_res(a);
+  const TS* hits = static_cast<const TS*>(a.hits);
+  double chi2 = 0.0;
+  int nh = 0;
+  uint32_t status = 0;
+  int reached = 0;
+  for (int l = 0; l < NSL; ++l) {
+    TrackState<TP> xp;
+    Jac<TP> F;
+    if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], l == 0, xp, F)) {
+      status |= kNoReach;
+      break;
+    }
+    reached = l + 1;
+    TP Pp[21];
+    cov_propagate(P, F, Pp);
+    const int g = e * L + l;
+    const int32_t h0 = a.seed_hit[l * a.sp + s];
+    // an index outside the layer's hit list counts as no hit
+    const int32_t h = (h0 >= 0 && h0 < a.hit_off[g + 1] - a.hit_off[g]) ? h0 : -1;
+    int32_t used = -1;
+    x = xp;
+#pragma unroll
+    for (int c = 0; c < 21; ++c) P[c] = Pp[c];
+    if (h >= 0) {
+      const int64_t hi = a.hit_off[g] + h;
+      const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
+      Residual R;
+      if (residual(xp, Pp, m, hr, R)) {
+        apply_update(xp, Pp, R, x, P);
+        chi2 += R.chi2;
+        ++nh;
+        used = h;
+      } else {
+        status |= kSNotPD;
+      }
+    }
+    a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 0 * a.sp + s] = 0;
+    a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 1 * a.sp + s] = used;
+  }
+  for (int l = 0; l < NSL; ++l) a.count[(int64_t)l * a.sp + s] = l < reached ? 1 : 0;
+  store_cand<TS, TP>(a.cpos[0], a.cmom[0], a.ccov[0], a.S, s, x, P);
+  a.cchi2[0][s] = chi2;
+  a.cmeta[0][s] = pack_meta(nh, 0, status);
+  if (reached < NSL) {  // the seed itself ended: it is the best ended candidate
+    store_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
+    a.bchi2[s] = chi2;
+    a.bmeta[s] = pack_meta(nh, 0, status);
+    a.bend[s] = reached;
+    a.brank[s] = 0;
+    a.count[(int64_t)(NSL - 1) * a.sp + s] = 0;
+  } else {
+    a.bend[s] = -1;
+  }
+}
+
+// ---------------------------------------------------------------- scoring
+// record key within one parent: (chi2 total, hit index) ascending
+__device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32_t h2) {
+  return c1 < c2 || (c1 == c2 && (uint32_t)h1 < (uint32_t)h2);
+}
+
+template <typename TS, typename TP>
+__global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, int cur) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.S) return;
+  const int rank = (int)(t / a.sp);
+  const int64_t s = t - (int64_t)rank * a.sp;
+  if (s >= a.n_seeds) return;
+  const int nlive = a.count[(int64_t)(l - 1) * a.sp + s];
+  if (rank >= nlive) return;
+  const int64_t slot = t;
+  const int L = a.g.n_layers, NC = a.g.max_cands;
+  const int e = find_event(a.seed_off, a.n_events, s);
+  TrackState<TP> x;
+  TP P[21];
+  load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, slot, x, P);
+  const uint32_t meta = a.cmeta[cur][slot];
+  const double pchi2 = a.cchi2[cur][slot];
+  const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
+  TrackState<TP> xp;
+  Jac<TP> F;
+  if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], false, xp, F)) {
+    a.rcount[slot] = -1;
+    return;
+  }
+  TP Pp[21];
+  cov_propagate(P, F, Pp);
+  store_cand<TS, TP>(a.ppos, a.pmom, a.pcov, a.S, slot, xp, Pp);
+
+  // search window: for any unit vector u, chi2 < cut implies
+  // |u.d| < sqrt(cut u^T S u) (Cauchy-Schwarz in the S^-1 metric); with u
+  // the tangent and z, and the hit covariance bounded by its largest
+  // transverse variance, no compatible hit lies outside (5% margin; hits
+  // are taken to lie within 1% of the layer radius)
+  const double cut = a.g.chi2_cut;
+  const double rho = sqrt(xp.pos[0] * xp.pos[0] + xp.pos[1] * xp.pos[1]);
+  const double tx = -xp.pos[1] / rho, ty = xp.pos[0] / rho;
+  const double ptt = tx * tx * (double)Pp[pidx(0, 0)] + 2.0 * tx * ty * (double)Pp[pidx(0, 1)] +
+                     ty * ty * (double)Pp[pidx(1, 1)];
+  const double vmax = fmax(a.g.hr.sr2, a.g.hr.srphi2);
+  const double bt = 1.05 * sqrt(cut * (fmax(ptt, 0.0) + vmax)) + 1e-7;
+  const double bzw = 1.05 * sqrt(cut * (fmax((double)Pp[pidx(2, 2)], 0.0) + a.g.hr.sz2)) + 1e-7;
+  const int nz = a.g.n_zbins, nphi = a.g.n_phibins;
+  const double zh = a.g.z_half;
+  const double zp = xp.pos[2];
+  int zlo = (int)floor((zp - bzw + zh) * nz / (2.0 * zh));
+  int zhi = (int)floor((zp + bzw + zh) * nz / (2.0 * zh));
+  zlo = max(0, min(nz - 1, zlo));
+  zhi = max(0, min(nz - 1, zhi));
+  const double sphi = bt / (0.99 * rho);
+  int plo = 0, phi_hi = nphi - 1;
+  bool full_phi = true;
+  if (sphi < 0.5) {
+    const double dphi = 1.1 * sphi;  // asin(x) <= 1.1 x for x <= 0.5
+    const double php = atan2(xp.pos[1], xp.pos[0]);
+    plo = (int)floor((php - dphi + kPi) * nphi / (2.0 * kPi));
+    phi_hi = (int)floor((php + dphi + kPi) * nphi / (2.0 * kPi));
+    full_phi = (phi_hi - plo + 1) >= nphi;
+  }
+  const int g = e * L + l;
+  const int32_t* off = a.bin_off + (int64_t)g * (a.n_bins + 1);
+  const int64_t base = a.hit_off[g];
+  const TS* hb = static_cast<const TS*>(a.hb);
+  const HitRes hr = hit_res(a);
+  int nrec = 0;
+  double* rchi = a.rchi;
+  int32_t* rhit = a.rhit;
+  for (int zb = zlo; zb <= zhi; ++zb) {
+    // up to two contiguous runs of phi bins (wrap-around)
+    int runs[2][2];
+    int nrun;
+    if (full_phi) {
+      runs[0][0] = 0; runs[0][1] = nphi - 1; nrun = 1;
+    } else {
+      const int a0 = ((plo % nphi) + nphi) % nphi;
+      const int a1 = a0 + (phi_hi - plo);
+      if (a1 < nphi) {
+        runs[0][0] = a0; runs[0][1] = a1; nrun = 1;
+      } else {
+        runs[0][0] = a0; runs[0][1] = nphi - 1;
+        runs[1][0] = 0; runs[1][1] = a1 - nphi; nrun = 2;
+      }
+    }
+    for (int ri = 0; ri < nrun; ++ri) {
+      const int32_t j0 = off[zb * nphi + runs[ri][0]];
+      const int32_t j1 = off[zb * nphi + runs[ri][1] + 1];
+      for (int32_t j = j0; j < j1; ++j) {
+        const int64_t hj = base + j;
+        const double m[3] = {(double)hb[hj], (double)hb[a.n_hits + hj], (double)hb[2 * a.n_hits + hj]};
+        Residual R;
+        if (!residual(xp, Pp, m, hr, R)) continue;
+        if (!(R.chi2 < cut)) continue;
+        const double c2 = pchi2 + R.chi2;
+        const int32_t hid = a.perm[hj];
+        // insert into the sorted list of at most NC records
+        if (nrec == NC && !rec_less(c2, hid, rchi[(int64_t)(NC - 1) * a.S + slot],
+                                    rhit[(int64_t)(NC - 1) * a.S + slot]))
+          continue;
+        int pos = nrec < NC ? nrec : NC - 1;
+        while (pos > 0 && rec_less(c2, hid, rchi[(int64_t)(pos - 1) * a.S + slot],
+                                   rhit[(int64_t)(pos - 1) * a.S + slot])) {
+          rchi[(int64_t)pos * a.S + slot] = rchi[(int64_t)(pos - 1) * a.S + slot];
+          rhit[(int64_t)pos * a.S + slot] = rhit[(int64_t)(pos - 1) * a.S + slot];
+          --pos;
+        }
+        rchi[(int64_t)pos * a.S + slot] = c2;
+        rhit[(int64_t)pos * a.S + slot] = hid;
+        if (nrec < NC) ++nrec;
+      }
+    }
+  }
+  if (nrec == 0) {
+    if (meta_nm(meta) < a.g.max_missed) {
+      rchi[slot] = pchi2;
+      rhit[slot] = -1;
+      nrec = 1;
+    } else {
+      a.rcount[slot] = -2;
+      return;
+    }
+  }
+  a.rcount[slot] = nrec;
+}
+
+// ----------------------------------------------------------------- select
+// ranking key: more hits, lower chi2, lower parent, lower hit (missed last)
+struct Key {
+  int nh;
+  double chi2;
+  int parent;
+  uint32_t hit;
+  bool valid;
+};
+
+__device__ __forceinline__ bool key_less(const Key& x, const Key& y) {
+  if (x.valid != y.valid) return x.valid;
+  if (!x.valid) return false;
+  if (x.nh != y.nh) return x.nh > y.nh;
+  if (x.chi2 != y.chi2) return x.chi2 < y.chi2;
+  if (x.parent != y.parent) return x.parent < y.parent;
+  return x.hit < y.hit;
+}
+
+__device__ __forceinline__ Key shfl_key(const Key& k, int src_lane_xor) {
+  Key o;
+  o.nh = __shfl_xor(k.nh, src_lane_xor, kGroup);
+  o.chi2 = __shfl_xor(k.chi2, src_lane_xor, kGroup);
+  o.parent = __shfl_xor(k.parent, src_lane_xor, kGroup);
+  o.hit = (uint32_t)__shfl_xor((int)k.hit, src_lane_xor, kGroup);
+  o.valid = __shfl_xor((int)k.valid, src_lane_xor, kGroup) != 0;
+  return o;
+}
+
+__device__ __forceinline__ Key group_min(Key k) {
+#pragma unroll
+  for (int d = kGroup / 2; d >= 1; d >>= 1) {
+    const Key o = shfl_key(k, d);
+    if (key_less(o, k)) k = o;
+  }
+  return k;
+}
+
+// final-choice key: more hits, lower chi2, earlier end, lower rank
+__device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, int nh2, double c2,
+                                           int e2, int r2) {
+  if (nh1 != nh2) return nh1 > nh2;
+  if (c1 != c2) return c1 < c2;
+  if (e1 != e2) return e1 < e2;
+  return r1 < r2;
+}
+
+template <typename TS, typename TP>
+__global__ __launch_bounds__(256) void build_select_kernel(BuildArgs a, int l, int cur) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(gt % kGroup);
+  const int64_t s = gt / kGroup;
+  const bool seed_ok = s < a.n_seeds;
+  const int NC = a.g.max_cands;
+  const int L = a.g.n_layers;
+  const int nxt = cur ^ 1;
+  const int nlive = seed_ok ? a.count[(int64_t)(l - 1) * a.sp + s] : 0;
+  const bool par = lane < nlive;
+  const int64_t pslot = (int64_t)lane * a.sp + s;
+  int rc = 0, nh = 0, nm = 0;
+  uint32_t pst = 0;
+  double pchi2 = 0.0;
+  if (par) {
+    rc = a.rcount[pslot];
+    const uint32_t m = a.cmeta[cur][pslot];
+    nh = meta_nh(m);
+    nm = meta_nm(m);
+    pst = meta_st(m) | (rc == -1 ? kNoReach : 0u);
+    pchi2 = a.cchi2[cur][pslot];
+  }
+
+  // ended parents: the best of them may become the seed's best ended one
+  {
+    Key ek;
+    ek.valid = par && rc < 0;
+    ek.nh = nh;
+    ek.chi2 = pchi2;
+    ek.parent = lane;
+    ek.hit = 0;
+    const Key best = group_min(ek);
+    if (best.valid && lane == best.parent) {
+      const int be = a.bend[s];
+      const bool better = be < 0 || final_less(nh, pchi2, l, lane, meta_nh(a.bmeta[s]), a.bchi2[s],
+                                               be, a.brank[s]);
+      if (better) {
+        TrackState<TP> x;
+        TP P[21];
+        load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, pslot, x, P);
+        store_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
+        a.bchi2[s] = pchi2;
+        a.bmeta[s] = pack_meta(nh, nm, pst);
+        a.bend[s] = l;
+        a.brank[s] = lane;
+      }
+    }
+  }
+
+  // merge the parents' sorted record lists into the best NC
+  int head = 0;
+  int my_parent = -1, my_rec = -1;
+  int nsel = 0;
+  for (int kk = 0; kk < NC; ++kk) {
+    Key key;
+    key.valid = par && rc > 0 && head < rc;
+    if (key.valid) {
+      const int32_t h = a.rhit[(int64_t)head * a.S + pslot];
+      key.chi2 = a.rchi[(int64_t)head * a.S + pslot];
+      key.nh = h >= 0 ? nh + 1 : nh;
+      key.hit = (uint32_t)h;
+      key.parent = lane;
+    } else {
+      key.nh = 0;
+      key.chi2 = 0.0;
+      key.hit = 0;
+      key.parent = 0;
+    }
+    const Key w = group_min(key);
+    if (!w.valid) break;
+    // the winner's record index: the winning lane's head before advancing
+    const int wave_lane = (int)(threadIdx.x & 63);
+    const int widx = __shfl(head, (wave_lane & ~(kGroup - 1)) + w.parent, 64);
+    if (lane == kk) {
+      my_parent = w.parent;
+      my_rec = widx;
+    }
+    if (lane == w.parent) ++head;
+    ++nsel;
+  }
+  if (!seed_ok) return;
+  if (lane == 0) a.count[(int64_t)l * a.sp + s] = nsel;
+  if (lane >= nsel) return;
+
+  // clone + update: child `lane` from its parent's propagated state
+  const int64_t ps = (int64_t)my_parent * a.sp + s;
+  const int32_t h = a.rhit[(int64_t)my_rec * a.S + ps];
+  const double c2 = a.rchi[(int64_t)my_rec * a.S + ps];
+  const uint32_t pm = a.cmeta[cur][ps];
+  TrackState<TP> xp;
+  TP Pp[21];
+  load_cand<TS, TP>(a.ppos, a.pmom, a.pcov, a.S, ps, xp, Pp);
+  TrackState<TP> x = xp;
+  TP P[21];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) P[c] = Pp[c];
+  int cnh = meta_nh(pm), cnm = meta_nm(pm);
+  if (h >= 0) {
+    const int e = find_event(a.seed_off, a.n_events, s);
+    const int64_t hi = a.hit_off[e * L + l] + h;
+    const TS* hits = static_cast<const TS*>(a.hits);
+    const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
+    Residual R;
+    residual(xp, Pp, m, hit_res(a), R);  // scored positive definite already
+    apply_update(xp, Pp, R, x, P);
+    ++cnh;
+  } else {
+    ++cnm;
+  }
+  const int64_t cs = (int64_t)lane * a.sp + s;
+  store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], a.S, cs, x, P);
+  a.cchi2[nxt][cs] = c2;
+  a.cmeta[nxt][cs] = pack_meta(cnh, cnm, meta_st(pm));
+  a.hist[((int64_t)l * NC + lane) * 2 * a.sp + 0 * a.sp + s] = my_parent;
+  a.hist[((int64_t)l * NC + lane) * 2 * a.sp + 1 * a.sp + s] = h;
+}
+
+// ------------------------------------------------------------------ final
+template <typename TS, typename TP>
+__global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  const int L = a.g.n_layers;
+  const int NC = a.g.max_cands;
+  const int nalive = a.count[(int64_t)(L - 1) * a.sp + s];
+  int best_r = -1;
+  int bnh = 0;
+  double bc2 = 0.0;
+  for (int r = 0; r < nalive; ++r) {
+    const int64_t slot = (int64_t)r * a.sp + s;
+    const int nh = meta_nh(a.cmeta[cur][slot]);
+    const double c2 = a.cchi2[cur][slot];
+    if (best_r < 0 || final_less(nh, c2, L, r, bnh, bc2, L, best_r)) {
+      best_r = r;
+      bnh = nh;
+      bc2 = c2;
+    }
+  }
+  const int be = a.bend[s];
+  bool from_ended = false;
+  int end_layer = L, rank = best_r;
+  if (be >= 0 && (best_r < 0 || final_less(meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s], bnh,
+                                            bc2, L, best_r))) {
+    from_ended = true;
+    end_layer = be;
+    rank = a.brank[s];
+  }
+  TrackState<TP> x;
+  TP P[21];
+  uint32_t meta;
+  double c2;
+  if (from_ended) {
+    load_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
+    meta = a.bmeta[s];
+    c2 = a.bchi2[s];
+  } else {
+    const int64_t slot = (int64_t)rank * a.sp + s;
+    load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, slot, x, P);
+    meta = a.cmeta[cur][slot];
+    c2 = a.cchi2[cur][slot];
+  }
+  // walk the (parent, hit) records back from the end layer
+  for (int l = L - 1; l >= end_layer; --l) a.o_hit[(int64_t)l * a.sp + s] = -1;
+  int r = rank;
+  for (int l = end_layer - 1; l >= 0; --l) {
+    if (r < 0 || r >= NC) {  // no record: nothing further back
+      a.o_hit[(int64_t)l * a.sp + s] = -1;
+      continue;
+    }
+    const int64_t hb = ((int64_t)l * NC + r) * 2 * a.sp;
+    a.o_hit[(int64_t)l * a.sp + s] = a.hist[hb + a.sp + s];
+    r = a.hist[hb + s];
+  }
+  TS* so = static_cast<TS*>(a.o_state);
+  TS* co = static_cast<TS*>(a.o_cov);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) so[c * a.sp + s] = (TS)x.pos[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) so[(c + 3) * a.sp + s] = (TS)x.mom[c];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) co[c * a.sp + s] = (TS)P[c];
+  uint32_t st = meta_st(meta);
+  if (!finite_state(x, P)) st |= kNonFinite;
+  a.o_chi2[s] = c2;
+  a.o_nhits[s] = meta_nh(meta);
+  a.o_status[s] = st;
+}
+
+// -------------------------------------------------------------- host side
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename TS, typename TP>
+static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) {
+  const int bs = 256;
+  const int64_t nbins_all = (int64_t)a.n_groups * a.n_bins;
+  if (nbins_all > 0) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nbins_all, bs)), dim3(bs), 0, st, a.bin_cur, nbins_all, 0);
+    if (a.n_hits > 0)
+      hipLaunchKernelGGL((bin_count_kernel<TS>), dim3(nblk(a.n_hits, bs)), dim3(bs), 0, st, a);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_groups), dim3(kScanThreads), 0, st, a);
+    if (a.n_hits > 0)
+      hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(a.n_hits, bs)), dim3(bs), 0, st, a);
+    hipLaunchKernelGGL((bin_sort_kernel<TS>), dim3(nblk(nbins_all, bs)), dim3(bs), 0, st, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || bins_only || a.n_seeds == 0) return e;
+  hipLaunchKernelGGL((build_seed_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
+  int cur = 0;
+  for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
+    hipLaunchKernelGGL((build_score_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
+    hipLaunchKernelGGL((build_select_kernel<TS, TP>), dim3(nblk(a.n_seeds * kGroup, bs)), dim3(bs), 0,
+                       st, a, l, cur);
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL((build_final_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
+  return hipGetLastError();
+}
+
+static int validate_batch(ktf_ctx* c, const ktf_event_batch* ev) {
+  const int L = c->cfg.n_layers;
+  if (ev->n_events < 0 || !ev->seed_off || !ev->hit_off)
+    return fail(c, KTF_EINVAL, "ktf_build: bad event batch");
+  if (ev->prec != KTF_FP64 && ev->prec != KTF_FP32_BULK)
+    return fail(c, KTF_EINVAL, "ktf_build: unknown precision");
+  if (ev->seed_off[0] != 0 || ev->hit_off[0] != 0)
+    return fail(c, KTF_EINVAL, "ktf_build: offsets must start at 0");
+  for (int e = 0; e < ev->n_events; ++e)
+    if (ev->seed_off[e + 1] < ev->seed_off[e]) return fail(c, KTF_EINVAL, "ktf_build: seed_off not monotone");
+  const int64_t G = (int64_t)ev->n_events * L;
+  for (int64_t g = 0; g < G; ++g) {
+    if (ev->hit_off[g + 1] < ev->hit_off[g]) return fail(c, KTF_EINVAL, "ktf_build: hit_off not monotone");
+    if (ev->hit_off[g + 1] - ev->hit_off[g] > INT32_MAX)
+      return fail(c, KTF_EINVAL, "ktf_build: too many hits in one layer");
+  }
+  const int64_t ns = ev->seed_off[ev->n_events];
+  const int64_t nh = ev->hit_off[G];
+  if (ev->seed_pitch < ns || ev->hit_pitch < nh) return fail(c, KTF_EINVAL, "ktf_build: pitch < size");
+  if (ns > 0 && (!ev->seed_state || !ev->seed_cov || !ev->charge || !ev->seed_hit))
+    return fail(c, KTF_EINVAL, "ktf_build: null seed buffer");
+  if (nh > 0 && !ev->hits) return fail(c, KTF_EINVAL, "ktf_build: null hits");
+  return KTF_OK;
+}
+
+// Fills the workspace part of BuildArgs; allocates (grows) context buffers.
+static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildArgs& a, hipStream_t st) {
+  const ktf_config& cfg = c->cfg;
+  const int L = cfg.n_layers;
+  memset(&a, 0, sizeof a);
+  a.g.n_layers = L;
+  a.g.n_zbins = cfg.n_zbins;
+  a.g.n_phibins = cfg.n_phibins;
+  a.g.max_cands = cfg.max_cands;
+  a.g.max_missed = cfg.max_missed;
+  a.g.n_seed_layers = cfg.n_seed_layers;
+  a.g.bz = cfg.bz;
+  a.g.z_half = cfg.z_half;
+  a.g.chi2_cut = cfg.chi2_cut;
+  a.g.hr.sr2 = cfg.sigma_r * cfg.sigma_r;
+  a.g.hr.srphi2 = cfg.sigma_rphi * cfg.sigma_rphi;
+  a.g.hr.sz2 = cfg.sigma_z * cfg.sigma_z;
+  for (int l = 0; l < L; ++l) a.g.radii[l] = c->radii[l];
+  a.n_events = ev->n_events;
+  a.n_groups = ev->n_events * L;
+  a.n_bins = cfg.n_zbins * cfg.n_phibins;
+  a.n_seeds = ev->seed_off[ev->n_events];
+  a.sp = ev->seed_pitch;
+  a.S = (int64_t)cfg.max_cands * a.sp;
+  a.n_hits = ev->hit_off[a.n_groups];
+  a.hp = ev->hit_pitch;
+  a.hits = ev->hits;
+  a.seed_state = ev->seed_state;
+  a.seed_cov = ev->seed_cov;
+  a.q = ev->charge;
+  a.seed_hit = ev->seed_hit;
+  const size_t ts = ev->prec == KTF_FP64 ? 8 : 4;
+  hipError_t e;
+  // offsets to the device through pinned staging
+  const size_t n_off = (size_t)(ev->n_events + 1) + (size_t)(a.n_groups + 1);
+  const size_t off_bytes = n_off * sizeof(int64_t);
+  if (c->h_pinned_bytes < off_bytes) {
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    c->h_pinned = nullptr;
+    c->h_pinned_bytes = 0;
+    if ((e = hipHostMalloc(&c->h_pinned, off_bytes * 2, 0)) != hipSuccess) return hip_fail(c, e, "pinned staging");
+    c->h_pinned_bytes = off_bytes * 2;
+  }
+  // calls on one context share the workspace and the staging buffer: wait
+  // until the previous call's work (on whatever stream) has finished
+  if (c->build_done) {
+    if ((e = hipEventSynchronize(c->build_done)) != hipSuccess) return hip_fail(c, e, "previous build");
+  }
+  int64_t* hp = static_cast<int64_t*>(c->h_pinned);
+  memcpy(hp, ev->seed_off, sizeof(int64_t) * (ev->n_events + 1));
+  memcpy(hp + ev->n_events + 1, ev->hit_off, sizeof(int64_t) * (a.n_groups + 1));
+  if ((e = c->b_stage.ensure(off_bytes)) != hipSuccess) return hip_fail(c, e, "workspace");
+  if ((e = hipMemcpyAsync(c->b_stage.p, hp, off_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(c, e, "offsets copy");
+  a.seed_off = static_cast<const int64_t*>(c->b_stage.p);
+  a.hit_off = a.seed_off + ev->n_events + 1;
+
+  const int64_t nb = a.n_bins;
+  const int64_t nhits = std::max<int64_t>(a.n_hits, 1);
+  if ((e = c->b_off.ensure(sizeof(int32_t) * ((size_t)a.n_groups * (nb + 1) + (size_t)a.n_groups * nb))) != hipSuccess)
+    return hip_fail(c, e, "bin workspace");
+  a.bin_off = static_cast<int32_t*>(c->b_off.p);
+  a.bin_cur = a.bin_off + (size_t)a.n_groups * (nb + 1);
+  if ((e = c->b_perm.ensure(sizeof(int32_t) * 2 * (size_t)nhits)) != hipSuccess) return hip_fail(c, e, "bin workspace");
+  a.perm = static_cast<int32_t*>(c->b_perm.p);
+  a.hit_bin = a.perm + nhits;
+  if ((e = c->b_binned.ensure(ts * 3 * (size_t)nhits)) != hipSuccess) return hip_fail(c, e, "bin workspace");
+  a.hb = c->b_binned.p;
+  if (bins_only) return KTF_OK;
+
+  const int64_t S = std::max<int64_t>(a.S, 1);
+  const size_t cand_bytes = (size_t)S * (3 * 8 + 24 * ts + 8 + 4);
+  for (int b = 0; b < 2; ++b) {
+    if ((e = c->b_cand[b].ensure(cand_bytes)) != hipSuccess) return hip_fail(c, e, "candidate workspace");
+    char* p = static_cast<char*>(c->b_cand[b].p);
+    a.cpos[b] = reinterpret_cast<double*>(p);
+    p += (size_t)S * 3 * 8;
+    a.cchi2[b] = reinterpret_cast<double*>(p);
+    p += (size_t)S * 8;
+    a.cmom[b] = p;
+    p += (size_t)S * 3 * ts;
+    a.ccov[b] = p;
+    p += (size_t)S * 21 * ts;
+    a.cmeta[b] = reinterpret_cast<uint32_t*>(p);
+  }
+  if ((e = c->b_prop.ensure((size_t)S * (3 * 8 + 24 * ts))) != hipSuccess) return hip_fail(c, e, "workspace");
+  {
+    char* p = static_cast<char*>(c->b_prop.p);
+    a.ppos = reinterpret_cast<double*>(p);
+    p += (size_t)S * 3 * 8;
+    a.pmom = p;
+    p += (size_t)S * 3 * ts;
+    a.pcov = p;
+  }
+  const int NC = cfg.max_cands;
+  if ((e = c->b_rec.ensure((size_t)S * (NC * 12 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
+  {
+    char* p = static_cast<char*>(c->b_rec.p);
+    a.rchi = reinterpret_cast<double*>(p);
+    p += (size_t)S * NC * 8;
+    a.rhit = reinterpret_cast<int32_t*>(p);
+    p += (size_t)S * NC * 4;
+    a.rcount = reinterpret_cast<int32_t*>(p);
+  }
+  const int64_t sp = std::max<int64_t>(a.sp, 1);
+  if ((e = c->b_best.ensure((size_t)sp * (3 * 8 + 24 * ts + 8 + 4 + 4 + 4))) != hipSuccess)
+    return hip_fail(c, e, "workspace");
+  {
+    char* p = static_cast<char*>(c->b_best.p);
+    a.bpos = reinterpret_cast<double*>(p);
+    p += (size_t)sp * 3 * 8;
+    a.bchi2 = reinterpret_cast<double*>(p);
+    p += (size_t)sp * 8;
+    a.bmom = p;
+    p += (size_t)sp * 3 * ts;
+    a.bcov = p;
+    p += (size_t)sp * 21 * ts;
+    a.bmeta = reinterpret_cast<uint32_t*>(p);
+    p += (size_t)sp * 4;
+    a.bend = reinterpret_cast<int32_t*>(p);
+    p += (size_t)sp * 4;
+    a.brank = reinterpret_cast<int32_t*>(p);
+  }
+  return KTF_OK;
+}
+
+static hipError_t record_done(ktf_ctx* c, hipStream_t st) {
+  if (!c->build_done) {
+    hipError_t e = hipEventCreateWithFlags(&c->build_done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(c->build_done, st);
+}
+
+int build_impl(ktf_ctx* c, const ktf_event_batch* ev, ktf_build_out* out, hipStream_t st) {
+  int rc = validate_batch(c, ev);
+  if (rc) return rc;
+  if (!out->hit_idx || !out->state || !out->cov || !out->chi2 || !out->n_hits || !out->status)
+    return fail(c, KTF_EINVAL, "ktf_build: null output");
+  BuildArgs a;
+  if ((rc = prepare(c, ev, false, a, st))) return rc;
+  const int L = c->cfg.n_layers, NC = c->cfg.max_cands;
+  const int64_t sp = std::max<int64_t>(a.sp, 1);
+  hipError_t e;
+  if (out->cand_hist) {
+    a.hist = out->cand_hist;
+  } else {
+    if ((e = c->b_hist.ensure(sizeof(int32_t) * (size_t)L * NC * 2 * sp)) != hipSuccess)
+      return hip_fail(c, e, "history workspace");
+    a.hist = static_cast<int32_t*>(c->b_hist.p);
+  }
+  if (out->cand_count) {
+    a.count = out->cand_count;
+  } else {
+    if ((e = c->b_misc.ensure(sizeof(int32_t) * (size_t)L * sp)) != hipSuccess)
+      return hip_fail(c, e, "count workspace");
+    a.count = static_cast<int32_t*>(c->b_misc.p);
+  }
+  // (parent, hit) records start as "none" so that unused ranks read -1
+  const int64_t nh = (int64_t)L * NC * 2 * sp;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nh, 256)), dim3(256), 0, st, a.hist, nh, -1);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk((int64_t)L * sp, 256)), dim3(256), 0, st, a.count,
+                     (int64_t)L * sp, 0);
+  a.o_hit = out->hit_idx;
+  a.o_state = out->state;
+  a.o_cov = out->cov;
+  a.o_chi2 = out->chi2;
+  a.o_nhits = out->n_hits;
+  a.o_status = out->status;
+  e = ev->prec == KTF_FP64 ? run_build<double, double>(a, false, st) : run_build<float, float>(a, false, st);
+  if (e == hipSuccess) e = record_done(c, st);
+  return e == hipSuccess ? KTF_OK : hip_fail(c, e, "build launch");
+}
+
+int bin_impl(ktf_ctx* c, const ktf_event_batch* ev, int32_t* offsets, int32_t* perm, hipStream_t st) {
+  int rc = validate_batch(c, ev);
+  if (rc) return rc;
+  BuildArgs a;
+  if ((rc = prepare(c, ev, true, a, st))) return rc;
+  hipError_t e = ev->prec == KTF_FP64 ? run_build<double, double>(a, true, st) : run_build<float, float>(a, true, st);
+  if (e != hipSuccess) return hip_fail(c, e, "binning launch");
+  const size_t ob = sizeof(int32_t) * (size_t)a.n_groups * (a.n_bins + 1);
+  if ((e = hipMemcpyAsync(offsets, a.bin_off, ob, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hip_fail(c, e, "copy offsets");
+  if (a.n_hits > 0 &&
+      (e = hipMemcpyAsync(perm, a.perm, sizeof(int32_t) * (size_t)a.n_hits, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hip_fail(c, e, "copy perm");
+  if ((e = record_done(c, st)) != hipSuccess) return hip_fail(c, e, "event record");
+  return KTF_OK;
+}
+
+}  // namespace ktf
+
+extern "C" int ktf_build(ktf_ctx* c, const ktf_event_batch* ev, ktf_build_out* out, void* st) {
+  if (!c || !ev || !out) return KTF_EINVAL;
+  return ktf::build_impl(c, ev, out, static_cast<hipStream_t>(st));
+}
+
+extern "C" int ktf_bin_hits(ktf_ctx* c, const ktf_event_batch* ev, int32_t* offsets, int32_t* perm,
+                            void* st) {
+  if (!c || !ev || !offsets || !perm) return KTF_EINVAL;
+  return ktf::bin_impl(c, ev, offsets, perm, static_cast<hipStream_t>(st));
+}

@@ -1,0 +1,300 @@
+// fit.hip -- batched Kalman-filter track fit kernels for gfx950.
+//
+// One track per lane.  Inputs and outputs are structure-of-arrays with a
+// common pitch, so lane i of a wave touches element i of every row and each
+// row access is one coalesced 256-byte (float) or 512-byte (double) wave
+// transaction.  The fit of a track is the Kalman filter of Sec. 2 run over
+// its layers: propagate to the next cylinder, update with the hit there.
+//
+// Variants:
+//  fused       all layers of a track in registers, read the seed and the
+//              hits once, write the result once (the arithmetic-bound design)
+//  persistent  the fused body in a fixed grid of blocks that pull tiles of
+//              tracks from a device counter until the tiles run out, which
+//              evens out tracks with very different hit counts
+//  layer       one layer of every track per launch; the state and covariance
+//              round-trip HBM between launches (the memory-bound design used
+//              for per-layer graph sweeps)
+#include "kf_math.hpp"
+#include "ktf_internal.hpp"
+
+namespace ktf {
+
+template <typename T> struct NewtonIters;
+template <> struct NewtonIters<double> { static constexpr int n = 4; };
+template <> struct NewtonIters<float> { static constexpr int n = 3; };
+
+// Storage type TS, propagation type TP.
+template <typename TS, typename TP>
+__device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
+  const int64_t p = a.pitch;
+  const TS* st = static_cast<const TS*>(a.state);
+  const TS* cv = static_cast<const TS*>(a.cov);
+  TrackState<TP> x;
+  TP P[21];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * p + i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * p + i];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * p + i];
+  const TP k = (TP)(kCLight * (double)a.q[i] * a.bz);
+  const int L = a.n_layers;
+  uint32_t vmask = 0;
+  for (int l = 0; l < L; ++l)
+    if (a.valid == nullptr || a.valid[l * p + i]) vmask |= 1u << l;
+  const int lend = vmask ? 32 - __builtin_clz(vmask) : 1;
+
+  const HitRes hr{a.hr.sr2, a.hr.srphi2, a.hr.sz2};
+  double chi2 = 0.0;
+  int32_t nupd = 0;
+  uint32_t status = 0;
+  const TS* hits = static_cast<const TS*>(a.hits);
+  // the next layer's hit is loaded one layer ahead so that its latency
+  // hides behind the current layer's arithmetic
+  TS hn0 = TS(0), hn1 = TS(0), hn2 = TS(0);
+  if (vmask & 1u) {
+    hn0 = hits[i];
+    hn1 = hits[p + i];
+    hn2 = hits[2 * p + i];
+  }
+  for (int l = 0; l < lend; ++l) {
+    const double m[3] = {(double)hn0, (double)hn1, (double)hn2};
+    if (l + 1 < lend && ((vmask >> (l + 1)) & 1u)) {
+      const TS* h = hits + (int64_t)(l + 1) * 3 * p;
+      hn0 = h[i];
+      hn1 = h[p + i];
+      hn2 = h[2 * p + i];
+    }
+    TrackState<TP> xp;
+    Jac<TP> F;
+    if (!propagate<TP, NewtonIters<TP>::n>(x, k, a.radii[l], l == 0, xp, F)) {
+      status |= kNoReach;
+      break;
+    }
+    TP Pp[21];
+    cov_propagate(P, F, Pp);
+    bool used = false;
+    if ((vmask >> l) & 1u) {
+      Residual R;
+      if (residual(xp, Pp, m, hr, R)) {
+        apply_update(xp, Pp, R, x, P);
+        chi2 += R.chi2;
+        ++nupd;
+        used = true;
+      } else {
+        status |= kSNotPD;
+      }
+    }
+    if (!used) {
+      x = xp;
+#pragma unroll
+      for (int c = 0; c < 21; ++c) P[c] = Pp[c];
+    }
+    if (!finite_state(x, P)) {
+      status |= kNonFinite;
+      break;
+    }
+  }
+  TS* so = static_cast<TS*>(a.state_o);
+  TS* co = static_cast<TS*>(a.cov_o);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x.mom[c];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) co[c * p + i] = (TS)P[c];
+  a.chi2[i] = chi2;
+  a.nupd[i] = nupd;
+  a.status[i] = status;
+}
+
+template <typename TS, typename TP, int BS>
+__global__ __launch_bounds__(BS) void fit_fused_kernel(FitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < a.n) fit_one_track<TS, TP>(a, i);
+}
+
+// Persistent blocks: every block loops taking the next tile of BS tracks
+// from counters[0]; all waves leave once the tile index passes tile_count.
+template <typename TS, typename TP, int BS>
+__global__ __launch_bounds__(BS) void fit_persistent_kernel(FitArgs a) {
+  __shared__ long long tile;
+  for (;;) {
+    if (threadIdx.x == 0) tile = (long long)atomicAdd(&a.counters[0], 1ull);
+    __syncthreads();
+    const long long t = tile;
+    __syncthreads();
+    if (t >= a.tile_count) break;
+    const int64_t i = t * BS + threadIdx.x;
+    if (i < a.n) fit_one_track<TS, TP>(a, i);
+  }
+}
+
+// One layer of every track.  Layer 0 reads the seed and initialises the
+// outputs and the per-track end layer; later layers work in place on the
+// outputs.  A track that has stopped (NO_REACH / NONFINITE) or is past its
+// last hit is left untouched.
+template <typename TS, typename TP, int BS>
+__global__ __launch_bounds__(BS) void fit_layer_kernel(FitArgs a, int l) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t p = a.pitch;
+  int lend;
+  uint32_t status;
+  double chi2;
+  int32_t nupd;
+  const TS* st;
+  const TS* cv;
+  if (l == 0) {
+    uint32_t vmask = 0;
+    for (int ll = 0; ll < a.n_layers; ++ll)
+      if (a.valid == nullptr || a.valid[ll * p + i]) vmask |= 1u << ll;
+    lend = vmask ? 32 - __builtin_clz(vmask) : 1;
+    a.lend[i] = (uint8_t)lend;
+    status = 0;
+    chi2 = 0.0;
+    nupd = 0;
+    st = static_cast<const TS*>(a.state);
+    cv = static_cast<const TS*>(a.cov);
+  } else {
+    lend = a.lend[i];
+    status = a.status[i];
+    if (l >= lend || (status & (kNoReach | kNonFinite))) return;
+    chi2 = a.chi2[i];
+    nupd = a.nupd[i];
+    st = static_cast<const TS*>(a.state_o);
+    cv = static_cast<const TS*>(a.cov_o);
+  }
+  TrackState<TP> x;
+  TP P[21];
+  if (l == 0 || a.pos_ws == nullptr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * p + i];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x.pos[c] = a.pos_ws[c * p + i];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * p + i];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * p + i];
+  const TP k = (TP)(kCLight * (double)a.q[i] * a.bz);
+  const HitRes hr{a.hr.sr2, a.hr.srphi2, a.hr.sz2};
+  TrackState<TP> xp;
+  Jac<TP> F;
+  if (!propagate<TP, NewtonIters<TP>::n>(x, k, a.radii[l], l == 0, xp, F)) {
+    status |= kNoReach;
+  } else {
+    TP Pp[21];
+    cov_propagate(P, F, Pp);
+    bool used = false;
+    if (a.valid == nullptr || a.valid[l * p + i]) {
+      const TS* h = static_cast<const TS*>(a.hits) + (int64_t)l * 3 * p;
+      const double m[3] = {(double)h[i], (double)h[p + i], (double)h[2 * p + i]};
+      Residual R;
+      if (residual(xp, Pp, m, hr, R)) {
+        apply_update(xp, Pp, R, x, P);
+        chi2 += R.chi2;
+        ++nupd;
+        used = true;
+      } else {
+        status |= kSNotPD;
+      }
+    }
+    if (!used) {
+      x = xp;
+#pragma unroll
+      for (int c = 0; c < 21; ++c) P[c] = Pp[c];
+    }
+    if (!finite_state(x, P)) status |= kNonFinite;
+  }
+  TS* so = static_cast<TS*>(a.state_o);
+  TS* co = static_cast<TS*>(a.cov_o);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x.mom[c];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) co[c * p + i] = (TS)P[c];
+  a.chi2[i] = chi2;
+  a.nupd[i] = nupd;
+  a.status[i] = status;
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int bs = 256;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+template <typename TS, typename TP, int BS>
+static hipError_t launch_fused_bs(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
+  if (persistent) {
+    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, BS>), dim3(pblocks), dim3(BS), 0, st, a);
+  } else {
+    const int64_t nb = (a.n + BS - 1) / BS;
+    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, BS>), dim3((unsigned)nb), dim3(BS), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename TS, typename TP>
+static hipError_t launch_fused_t(const FitArgs& a, int bs, bool persistent, int pblocks,
+                                 hipStream_t st) {
+  switch (bs) {
+    case 64: return launch_fused_bs<TS, TP, 64>(a, persistent, pblocks, st);
+    case 128: return launch_fused_bs<TS, TP, 128>(a, persistent, pblocks, st);
+    case 256: return launch_fused_bs<TS, TP, 256>(a, persistent, pblocks, st);
+    case 512: return launch_fused_bs<TS, TP, 512>(a, persistent, pblocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, bool persistent,
+                            int persistent_blocks, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  if (prec == KTF_FP64) return launch_fused_t<double, double>(a, bs, persistent, persistent_blocks, st);
+  return launch_fused_t<float, float>(a, bs, persistent, persistent_blocks, st);
+}
+
+hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  constexpr int BS = 256;
+  const unsigned nb = (unsigned)((a.n + BS - 1) / BS);
+  if (prec == KTF_FP64)
+    hipLaunchKernelGGL((fit_layer_kernel<double, double, BS>), dim3(nb), dim3(BS), 0, st, a, layer);
+  else
+    hipLaunchKernelGGL((fit_layer_kernel<float, float, BS>), dim3(nb), dim3(BS), 0, st, a, layer);
+  return hipGetLastError();
+}
+
+}  // namespace ktf
+
+namespace ktf {
+
+template <typename TS, typename TP>
+static int occ_blocks(int bs) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (bs) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 64>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 128>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 256>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 512>, 512, 0); break;
+    default: break;
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
+int persistent_blocks(ktf_ctx*, ktf_precision prec, int bs) {
+  return prec == KTF_FP64 ? occ_blocks<double, double>(bs) : occ_blocks<float, float>(bs);
+}
+
+}  // namespace ktf

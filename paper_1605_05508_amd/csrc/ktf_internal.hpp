@@ -1,0 +1,55 @@
+// ktf_internal.hpp -- kernel argument blocks and launchers shared by the
+// library's translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ktf.h"
+
+namespace ktf {
+
+struct HitResD {
+  double sr2, srphi2, sz2;
+};
+
+// Arguments of the fit kernels (passed by value in the kernarg segment).
+struct FitArgs {
+  int64_t n, pitch;
+  const void* state;
+  const void* cov;
+  const int8_t* q;
+  const void* hits;
+  const uint8_t* valid;
+  void* state_o;
+  void* cov_o;
+  double* chi2;
+  int32_t* nupd;
+  uint32_t* status;
+  uint8_t* lend;        // sweep: per-track end layer (workspace)
+  double* pos_ws;       // sweep, float storage: positions in double between layers [3][pitch]
+  unsigned long long* counters;  // persistent: tile counters
+  int64_t tile_count;   // persistent: number of tiles
+  int32_t n_layers;
+  double bz;
+  HitResD hr;
+  double radii[KTF_MAX_LAYERS];
+};
+
+// launch shapes of the fused fit
+constexpr int kBlockSizes[4] = {64, 128, 256, 512};
+
+hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, bool persistent,
+                            int persistent_blocks, hipStream_t st);
+hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
+
+// ------------------------------------------------------------------ build
+struct BuildGeom {
+  int32_t n_layers, n_zbins, n_phibins, max_cands, max_missed, n_seed_layers;
+  double bz, z_half, chi2_cut;
+  HitResD hr;
+  double radii[KTF_MAX_LAYERS];
+};
+
+}  // namespace ktf

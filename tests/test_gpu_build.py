@@ -1,0 +1,173 @@
+"""GPU parity of combinatorial track building against the FP64 oracle.
+
+Building (Sec. 3) with the clone engine (Sec. 3.1): hit indices, hit counts
+and every layer's kept (parent, hit) list must match the oracle bit-exactly
+for the FP64 path; chi2 and the chosen state within 1e-10.  The FP32-bulk
+path may only differ where the oracle itself faced a near-tie (a decision
+within tau of flipping), and then only from that layer on.
+"""
+import numpy as np
+import pytest
+
+import trackgen as tg
+from helpers import build_inputs, certified, fp64_close, host, with_ghosts
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def k():
+    import paper_1605_05508_amd as k
+    return k
+
+
+def ctx_for(k, det, **kw):
+    return k.Context.for_detector(det, **kw)
+
+
+def small_batch(seed, n_events, n_tracks, n_layers=17, ghosts=False):
+    rng = np.random.default_rng(seed)
+    det = tg.barrel(n_layers)
+    evs = []
+    for e in range(n_events):
+        ev = tg.make_build_event(rng, n_tracks, det)
+        if ghosts:
+            ev = with_ghosts(ev, seed * 100 + e)
+        evs.append(ev)
+    return tg.concat_events(evs)
+
+
+def oracle_batch(orc, bs, **kw):
+    outs = [orc.build_event(bs, e, debug=True, **kw) for e in range(bs.n_events)]
+    cat = {}
+    for key in outs[0]:
+        cat[key] = np.concatenate([o[key] for o in outs], axis=-1)
+    return cat
+
+
+def test_bins_match_oracle(k, orc):
+    bs = small_batch(1, 3, 400, n_layers=6)
+    ctx = ctx_for(k, bs.det)
+    for prec in ("fp64", "fp32b"):
+        d = build_inputs(bs, prec, hit_pad=64)
+        offs, perm = ctx.bin_hits(d)
+        offs, perm = offs.cpu().numpy(), perm.cpu().numpy()
+        L = bs.det.n_layers
+        for e in range(bs.n_events):
+            for l in range(L):
+                g = e * L + l
+                h = bs.layer_hits(e, l)
+                oo, op = orc.bin_layer(h, 100.0, 64, 512)
+                a, b = bs.hit_off[g], bs.hit_off[g + 1]
+                assert np.array_equal(offs[g], oo), (prec, e, l)
+                assert np.array_equal(perm[a:b], op), (prec, e, l)
+
+
+@pytest.mark.parametrize("ghosts", [False, True])
+def test_fp64_build_matches_oracle(k, orc, ghosts):
+    bs = small_batch(2, 3, 300, ghosts=ghosts)
+    ctx = ctx_for(k, bs.det)
+    d = build_inputs(bs, "fp64", seed_pad=64)
+    g = host(ctx.build(d, hist=True), bs.n_seeds)
+    o = oracle_batch(orc, bs)
+    assert np.array_equal(g["hit_idx"], o["hit_idx"])
+    assert np.array_equal(g["nhits"], o["nhits"])
+    assert np.array_equal(g["count"], o["dbg_n"])
+    L, NC = bs.det.n_layers, 10
+    for l in range(L):
+        for r in range(NC):
+            live = o["dbg_n"][l] > r
+            assert np.array_equal(g["hist"][l, r, :, live], o["dbg"][l, r, :, live].T.T), (l, r)
+    assert np.array_equal(g["status"].astype(np.uint32), o["status"])
+    np.testing.assert_allclose(g["chi2"], o["chi2"], rtol=1e-10, atol=1e-12)
+    fp64_close(dict(state=g["state"], cov=g["cov"], chi2=g["chi2"], nupd=g["nhits"], status=g["status"]),
+               dict(state=o["state"], cov=o["cov"], chi2=o["chi2"], nupd=o["nhits"], status=o["status"]),
+               check_diverged=False)
+    # a real search: candidates branched and some seeds kept several
+    assert (o["dbg_n"] > 1).any()
+
+
+@pytest.mark.parametrize("nc,missed", [(1, 1), (3, 0), (16, 2)])
+def test_beam_widths(k, orc, nc, missed):
+    bs = small_batch(3, 2, 150, n_layers=9, ghosts=True)
+    ctx = ctx_for(k, bs.det, max_cands=nc, max_missed=missed)
+    d = build_inputs(bs, "fp64")
+    g = host(ctx.build(d), bs.n_seeds)
+    o = oracle_batch(orc, bs, max_cands=nc, max_missed=missed)
+    assert np.array_equal(g["hit_idx"], o["hit_idx"])
+    assert np.array_equal(g["nhits"], o["nhits"])
+    np.testing.assert_allclose(g["chi2"], o["chi2"], rtol=1e-10, atol=1e-12)
+
+
+def test_edge_cases(k, orc):
+    """An event without seeds, a layer without hits, and an event whose seeds
+    find nothing beyond the seed layers."""
+    rng = np.random.default_rng(4)
+    det = tg.barrel(8)
+    e1 = tg.make_build_event(rng, 50, det)
+    e0 = tg.make_build_event(rng, 0, det)
+    e2 = tg.make_build_event(rng, 40, det)
+    # empty layer 5 in e2
+    L = det.n_layers
+    keep = np.ones(e2.hits.shape[1], bool)
+    keep[e2.hit_off[5]:e2.hit_off[6]] = False
+    sizes = np.diff(e2.hit_off)
+    sizes[5] = 0
+    e2 = tg.BuildSet(det, 1, np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64), e2.hits[:, keep],
+                     e2.seed_off, e2.state, e2.cov, e2.q, e2.seed_hit, e2.true_idx, e2.truth_pos,
+                     e2.truth_mom)
+    bs = tg.concat_events([e1, e0, e2])
+    ctx = ctx_for(k, det)
+    d = build_inputs(bs, "fp64")
+    g = host(ctx.build(d), bs.n_seeds)
+    o = oracle_batch(orc, bs)
+    assert np.array_equal(g["hit_idx"], o["hit_idx"])
+    assert np.array_equal(g["nhits"], o["nhits"])
+    assert np.all(g["hit_idx"][5, 50:] == -1)
+
+
+def test_config3_full_size_sampled(k, orc):
+    """The full combinatorial-building workload (100 events x 5,000 tracks,
+    17 layers, 20% noise) in one batch; sampled seeds checked against the
+    brute-force oracle, FP64 exactly and FP32-bulk up to certified ties."""
+    bs = tg.config3()
+    ctx = ctx_for(k, bs.det)
+    rng = np.random.default_rng(5)
+    res = {}
+    for prec in ("fp64", "fp32b"):
+        d = build_inputs(bs, prec)
+        res[prec] = host(ctx.build(d, hist=True), bs.n_seeds)
+        del d
+    # overall physics sanity: most seeds find their own particle's hits
+    match = (res["fp64"]["hit_idx"] == bs.true_idx).all(axis=0)
+    assert match.mean() > 0.95
+    for e in rng.choice(bs.n_events, 4, replace=False):
+        s0 = int(bs.seed_off[e])
+        loc = rng.choice(int(bs.seed_off[e + 1] - s0), 40, replace=False)
+        o = orc.build_event(bs, int(e), seeds=loc, debug=True)
+        gi = s0 + loc
+        g = res["fp64"]
+        assert np.array_equal(g["hit_idx"][:, gi], o["hit_idx"])
+        np.testing.assert_allclose(g["chi2"][gi], o["chi2"], rtol=1e-10)
+        g = res["fp32b"]
+        for j, s in enumerate(gi):
+            if np.array_equal(g["hit_idx"][:, s], o["hit_idx"][:, j]):
+                continue
+            ok, layer = certified(o["dbg_n"][:, j], o["dbg"][:, :, :, j], o["margin"][:, j],
+                                  g["count"][:, s], g["hist"][:, :, :, s], 1e-3)
+            assert ok, (e, s, layer)
+
+
+def test_fp32_build_agrees_up_to_ties(k, orc):
+    bs = small_batch(6, 2, 400, ghosts=True)
+    ctx = ctx_for(k, bs.det)
+    d = build_inputs(bs, "fp32b")
+    g = host(ctx.build(d, hist=True), bs.n_seeds)
+    o = oracle_batch(orc, bs)
+    same = (g["hit_idx"] == o["hit_idx"]).all(axis=0)
+    assert same.mean() > 0.98
+    for s in np.nonzero(~same)[0]:
+        ok, layer = certified(o["dbg_n"][:, s], o["dbg"][:, :, :, s], o["margin"][:, s],
+                              g["count"][:, s], g["hist"][:, :, :, s], 1e-3)
+        assert ok, (s, layer)
+    np.testing.assert_allclose(g["chi2"][same], o["chi2"][same], rtol=1e-3, atol=1e-3)

@@ -1,0 +1,178 @@
+"""GPU parity of the batched Kalman-filter fit against the FP64 oracle.
+
+The fit is the Kalman filter of Sec. 2 run over each track's layers.  FP64
+path: every output within 1e-10 of the oracle (relative to the value plus
+its own uncertainty); FP32-bulk path: position error / r and momentum error
+/ |p| against the FP64 oracle, and pull widths within 1% of the oracle's.
+"""
+import numpy as np
+import pytest
+
+import trackgen as tg
+from helpers import fit_inputs, fp32_errors, fp64_close, host, pad_pitch, pulls
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fused", "persistent", "sweep", "sweep_graph"]
+
+
+@pytest.fixture(scope="module")
+def k():
+    import paper_1605_05508_amd as k
+    return k
+
+
+@pytest.fixture(scope="module")
+def ctx10(k):
+    return k.Context(tg.barrel(10).radii)
+
+
+@pytest.fixture(scope="module")
+def c1(orc):
+    fs = tg.config1()
+    return fs, orc.fit(fs)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_fp64_config1_matches_oracle(ctx10, c1, mode):
+    fs, o = c1
+    d = fit_inputs(fs, "fp64")
+    out = ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode)
+    g = host(out, fs.n)
+    fp64_close(g, o)
+
+
+def test_fp64_ragged_and_missing_layers(ctx10, orc):
+    """Several tiles plus a ragged tail, tracks with missing layers and early
+    ends, pitch larger than n."""
+    rng = np.random.default_rng(31)
+    fs = tg.make_fit_set(rng, 5000 + 37, tg.barrel(10), pt_range=(0.5, 100.0), pt_log=True)
+    v = fs.valid.copy()
+    v[rng.random(v.shape) < 0.15] = 0
+    v[0] = 1
+    fs.valid = v
+    o = orc.fit(fs)
+    d = fit_inputs(fs, "fp64", pitch=pad_pitch(fs.n) + 128)
+    for mode in MODES:
+        out = ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode)
+        fp64_close(host(out, fs.n), o)
+
+
+def test_modes_agree(ctx10):
+    """The fused and persistent kernels share one per-track body, as do the
+    per-layer sweep and its graph replay: each pair is bitwise identical and
+    every run repeats bitwise.  Between the two families the compiler may
+    contract different multiply-adds, so they agree to rounding."""
+    rng = np.random.default_rng(32)
+    fs = tg.make_fit_set(rng, 3000, tg.barrel(10), pt_range=(0.5, 100.0), pt_log=True)
+    for prec in ("fp64", "fp32b"):
+        d = fit_inputs(fs, prec)
+        run = lambda m: host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=m), fs.n)
+        res = {m: run(m) for m in MODES}
+        again = {m: run(m) for m in MODES}
+        for m in MODES:
+            for key in res[m]:
+                assert np.array_equal(res[m][key], again[m][key]), (prec, m, key)
+        for a, b in (("fused", "persistent"), ("sweep", "sweep_graph")):
+            for key in res[a]:
+                assert np.array_equal(res[a][key], res[b][key]), (prec, a, b, key)
+        tol = 1e-12 if prec == "fp64" else 1e-5
+        f, w = res["fused"], res["sweep"]
+        assert np.array_equal(f["nupd"], w["nupd"]) and np.array_equal(f["status"], w["status"])
+        np.testing.assert_allclose(w["state"], f["state"], rtol=tol, atol=tol)
+        np.testing.assert_allclose(w["chi2"], f["chi2"], rtol=100 * tol)
+
+
+def test_fp32_bulk_accuracy_and_pulls(ctx10, orc):
+    fs = tg.config2(n=200_000)
+    o = orc.fit(fs)
+    d = fit_inputs(fs, "fp32b")
+    g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"]), fs.n)
+    assert np.array_equal(g["nupd"], o["nupd"])
+    e_pos, e_mom = fp32_errors(g, o, 40.0)
+    assert e_pos.max() < 1e-6
+    assert np.quantile(e_mom, 0.999) < 1e-4
+    assert e_mom.max() < 5e-4
+    assert np.abs(g["chi2"] - o["chi2"]).max() / max(1, o["chi2"].max()) < 1e-2
+    pg = pulls(g["state"], g["cov"], fs.truth_pos[-1], fs.truth_mom[-1])
+    po = pulls(o["state"], o["cov"], fs.truth_pos[-1], fs.truth_mom[-1])
+    for name in pg:
+        rg, ro = np.sqrt(np.mean(pg[name] ** 2)), np.sqrt(np.mean(po[name] ** 2))
+        assert abs(rg / ro - 1) < 0.01, (name, rg, ro)
+
+
+def test_full_size_sampled(ctx10, orc):
+    """Config 2 at its full 1e6 tracks in the launch the benchmark times;
+    a sample of tracks is checked against the oracle one by one."""
+    fs = tg.config2()
+    for prec in ("fp64", "fp32b"):
+        d = fit_inputs(fs, prec)
+        g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"]), fs.n)
+        idx = np.random.default_rng(7).choice(fs.n, 3000, replace=False)
+        sub = fs.subset(idx)
+        o = orc.fit(sub)
+        gs = {key: v[..., idx] for key, v in g.items()}
+        if prec == "fp64":
+            fp64_close(gs, o)
+        else:
+            e_pos, e_mom = fp32_errors(gs, o, 40.0)
+            assert e_mom.max() < 5e-4 and e_pos.max() < 1e-6
+        assert np.all(g["status"] == 0)
+        assert np.all(g["nupd"] == 10)
+
+
+def test_status_flags(ctx10, orc):
+    rng = np.random.default_rng(33)
+    fs = tg.make_fit_set(rng, 256, tg.barrel(10))
+    st = fs.state.copy()
+    # tracks 0..9: too soft to reach the outer layers
+    ptl = 0.9 * 0.00299792458 * 3.8 * 30.0 / 2
+    ph = np.arctan2(st[4, :10], st[3, :10])
+    st[3, :10], st[4, :10] = ptl * np.cos(ph), ptl * np.sin(ph)
+    cov = fs.cov.copy()
+    cov[15, :10] = cov[18, :10] = (0.01 * ptl) ** 2
+    cov[16, :10] = 0
+    hits = fs.hits.copy()
+    hits[5, 0, 20:25] = np.nan  # non-finite hits on layer 5
+    fs2 = tg.FitSet(fs.det, st, cov, fs.q, hits, fs.valid, fs.truth_pos, fs.truth_mom)
+    o = orc.fit(fs2)
+    for prec in ("fp64", "fp32b"):
+        d = fit_inputs(fs2, prec)
+        g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"]), fs.n)
+        assert np.all(g["status"][:10] & 1)
+        assert np.array_equal(g["status"].astype(np.uint32), o["status"])
+        assert np.all(g["status"][20:25] != 0)
+        assert np.all(g["status"][30:] == 0)
+
+
+def test_empty_and_single(ctx10, orc):
+    import torch
+    fs = tg.config1(n=1)
+    o = orc.fit(fs)
+    d = fit_inputs(fs, "fp64")
+    fp64_close(host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"]), 1), o)
+    e = ctx10.fit(d["state"], d["cov"], d["q"][:0], d["hits"], d["valid"])
+    torch.cuda.synchronize()
+    assert e["state"].shape[1] == 64
+
+
+def test_autotune_keeps_results(ctx10):
+    rng = np.random.default_rng(34)
+    fs = tg.make_fit_set(rng, 20000, tg.barrel(10))
+    d = fit_inputs(fs, "fp32b")
+    ref = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="fused"), fs.n)
+    ctx10.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"])
+    assert '"tuned": true' in ctx10.tuned_shape("fp32b", fs.n)
+    g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="auto"), fs.n)
+    for key in ref:
+        assert np.array_equal(ref[key], g[key])
+
+
+def test_bad_arguments_raise(ctx10):
+    import torch
+    fs = tg.config1(n=10)
+    d = fit_inputs(fs, "fp64")
+    with pytest.raises(ValueError):
+        ctx10.fit(d["state"].float(), d["cov"], d["q"], d["hits"], d["valid"])
+    with pytest.raises(ValueError):
+        ctx10.fit(d["state"], d["cov"], d["q"], d["hits"][:5], d["valid"])

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import trackgen as tg
+from helpers import with_ghosts
 
 CUT = 30.0
 
@@ -80,27 +81,6 @@ def enumerate_paths(orc, bs, s, max_missed=1, nsl=3):
 
     rec(nsl, x, P, chi2, 3, 0, hits)
     return ends
-
-
-def with_ghosts(bs, seed, frac=0.6, spread=0.02):
-    """Add, beside a fraction of the true hits, a ghost hit a few sigma away
-    along phi and z so that candidates branch."""
-    rng = np.random.default_rng(seed)
-    det = bs.det
-    parts, sizes = [], []
-    for l in range(det.n_layers):
-        h = bs.layer_hits(0, l)
-        n_true = int((bs.true_idx[l] >= 0).sum())
-        pick = np.nonzero(rng.random(n_true) < frac)[0] if l >= 3 else np.array([], int)
-        r = det.radii[l]
-        ph = np.arctan2(h[1, pick], h[0, pick]) + rng.normal(0, spread, pick.size) / r
-        z = h[2, pick] + rng.normal(0, 0.2, pick.size)
-        g = tg.f32(np.stack([r * np.cos(ph), r * np.sin(ph), z]))
-        parts.append(np.concatenate([h, g], axis=1))
-        sizes.append(parts[-1].shape[1])
-    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    return tg.BuildSet(det, 1, off, np.concatenate(parts, axis=1), bs.seed_off, bs.state,
-                       bs.cov, bs.q, bs.seed_hit, bs.true_idx, bs.truth_pos, bs.truth_mom)
 
 
 def test_wide_beam_equals_exhaustive_search(orc):
