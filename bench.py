@@ -62,7 +62,81 @@ def parse():
                     help="target CPU work of the oracle sample (core-seconds)")
     ap.add_argument("--profile", action="store_true",
                     help="only the timed FP32-bulk loop (for rocprofv3 runs)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serve-events", type=int, default=200)
+    ap.add_argument("--rates", type=str, default="500,2000")
     return ap.parse_args()
+
+
+def serving_measurement(ktf, tg, n_events, rates):
+    """Poisson arrivals of building events (5,000 tracks, 10% heavy events of
+    20,000-50,000 tracks, 17 layers, 20% noise) into the continuous-batching
+    loop (build + final fit per event), against the plain FP64 path serving
+    one event at a time."""
+    import threading
+    arrivals, ntr, rng = tg.config5_stream(n_events=n_events, rate=1.0)
+    det = tg.barrel(17)
+    evs = [tg.make_build_event(rng, int(n), det) for n in ntr]
+    host = [dict(hit_off=e.hit_off, hits=e.hits, state=e.state, cov=e.cov, q=e.q, seed_hit=e.seed_hit)
+            for e in evs]
+
+    def run(ctx, rate, prec, sequential=False):
+        lat, tracks = [], 0
+        pend = {}
+        lock = threading.Lock()
+        start = ctx.now() + 0.05
+
+        def submitter():
+            for i, ev in enumerate(host):
+                if not sequential:
+                    t_arr = start + arrivals[i] / rate
+                    dt = t_arr - ctx.now()
+                    if dt > 0:
+                        time.sleep(dt)
+                t = ctx.submit(dict(ev, prec=prec))
+                with lock:
+                    pend[t] = i
+                if sequential:
+                    while True:
+                        with lock:
+                            if t not in pend:
+                                break
+                        time.sleep(0.0002)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        done = 0
+        t_end = None
+        while done < len(host):
+            with lock:
+                items = list(pend.items())
+            for t, i in items:
+                r = ctx.poll(t, evs[i].n_seeds)
+                if r is not None:
+                    with lock:
+                        del pend[t]
+                    lat.append((r["t_done"] - r["t_submit"]) * 1e3)
+                    tracks += evs[i].n_seeds
+                    done += 1
+                    t_end = r["t_done"]
+            time.sleep(0.0002)
+        th.join()
+        span = t_end - start
+        lat = np.array(lat)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "events_per_s": round(len(host) / span, 1), "tracks_per_s": round(tracks / span)}
+
+    out = {"events": n_events, "mean_tracks_per_event": round(float(np.mean(ntr)))}
+    ctx = ktf.Context.for_detector(det, hbm_budget_bytes=16 << 30, max_inflight=64)
+    run(ctx, 1e9, "fp32b")  # warm-up: workspaces grow to their working size
+    out["fp32b_continuous"] = {str(r): run(ctx, r, "fp32b") for r in rates}
+    ctx.close()
+    ctx1 = ktf.Context.for_detector(det, hbm_budget_bytes=16 << 30, max_inflight=1)
+    run(ctx1, 1e9, "fp64", sequential=True)
+    out["fp64_one_at_a_time"] = run(ctx1, 1e9, "fp64", sequential=True)
+    ctx1.close()
+    return out
 
 
 def timed_loop(fn, steps, warmup, torch):
@@ -223,6 +297,10 @@ def main():
                          "status_mismatch": int(np.sum(gs["status"].astype(np.uint32) != o["status"]))}
         acc["oracle_pull_rms"] = {kk: round(float(np.sqrt(np.mean(v ** 2))), 4) for kk, v in po.items()}
         result["accuracy_vs_oracle"] = acc
+    if not args.no_serving:
+        print("[bench] serving loop", file=sys.stderr, flush=True)
+        rates = [float(r) for r in args.rates.split(",")]
+        result["serving"] = serving_measurement(ktf, tg, args.serve_events, rates)
     print(json.dumps(result))
 
 

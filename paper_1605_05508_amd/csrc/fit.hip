@@ -211,6 +211,10 @@ __global__ __launch_bounds__(BS) void fit_layer_kernel(FitArgs a, int l) {
   }
   TS* so = static_cast<TS*>(a.state_o);
   TS* co = static_cast<TS*>(a.cov_o);
+  if (a.pos_ws != nullptr) {  // float storage: positions carried in double
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.pos_ws[c * p + i] = x.pos[c];
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
 #pragma unroll
