@@ -60,8 +60,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work of the oracle sample (core-seconds)")
-    ap.add_argument("--profile", action="store_true",
-                    help="only the timed FP32-bulk loop (for rocprofv3 runs)")
+    ap.add_argument("--profile", choices=["fit", "build", "copy"], default=None,
+                    help="only one timed loop, for rocprofv3 runs (copy: a plain copy of "
+                         "known size to calibrate the HBM byte counters)")
+    ap.add_argument("--workload", choices=["fit", "uneven"], default="fit",
+                    help="fit: the headline line; uneven: events of uneven size in one "
+                         "launch versus per-event launches")
+    ap.add_argument("--no-build", action="store_true", help="skip the building measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-events", type=int, default=200)
     ap.add_argument("--rates", type=str, default="500,2000")
@@ -139,6 +144,127 @@ def serving_measurement(ktf, tg, n_events, rates):
     return out
 
 
+def build_measurement(ctx_cls, tg, torch, reps=5, orc=None):
+    """Combinatorial building of 100 events x 5,000 tracks (17 layers, 20%
+    noise hits, 64 x 512 bins, 10 candidates, chi2 < 30, one missed layer)
+    in one batch."""
+    from tests.helpers import build_inputs
+    bs = tg.config3()
+    ctx = ctx_cls.for_detector(bs.det)
+    out = {"events": bs.n_events, "seeds": bs.n_seeds, "hits": int(bs.hits.shape[1])}
+    for prec in ("fp32b", "fp64"):
+        d = build_inputs(bs, prec)
+        o = ctx.build(d)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            ctx.build(d, out=o)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        hit = o["hit_idx"].cpu().numpy()[:, :bs.n_seeds]
+        eff = float((hit == bs.true_idx).all(axis=0).mean())
+        out[prec] = {"ms": round(ms, 3), "seeds_per_s": round(bs.n_seeds / (ms * 1e-3)),
+                     "events_per_s": round(bs.n_events / (ms * 1e-3), 1),
+                     "all_hits_true_fraction": round(eff, 4)}
+        del d, o
+    if orc is not None:
+        m = 100
+        t0 = time.perf_counter()
+        orc.build_event(bs, 0, seeds=np.arange(m), nthreads=orc.default_threads())
+        t = time.perf_counter() - t0
+        out["cpu_oracle"] = {"seeds_per_s": round(m / t, 1), "cores": orc.default_threads(),
+                             "sample": f"{m} seeds of one event, brute force over every hit"}
+    ctx.close()
+    return out
+
+
+def uneven_workload(args):
+    """Events of uneven size: 2,000 events with log-normal track counts
+    (median 3,000, sigma 0.8, clipped 50-50,000), 6-17 hits per track with
+    0-3 missing layers, FP32-bulk.  One launch over all events (fused,
+    persistent, per-layer graph sweep) against one launch per event."""
+    import torch
+    import paper_1605_05508_amd as ktf
+    import trackgen as tg
+    from tests.helpers import fit_inputs
+    print("[bench] generating the uneven-events workload", file=sys.stderr, flush=True)
+    fs, offs = tg.config4()
+    n = fs.n
+    ctx = ktf.Context.for_detector(fs.det)
+    d = fit_inputs(fs, "fp32b")
+    out = ctx.alloc_fit_out(n, d["state"].shape[1], torch.float32)
+    print("[bench] autotuning", file=sys.stderr, flush=True)
+    ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out)
+    res = {"events": len(offs) - 1, "tracks": n,
+           "hits_per_track": round(float(fs.valid.sum(axis=0).mean()), 3)}
+    for mode in ("auto", "fused", "persistent", "sweep_graph"):
+        ms, _ = timed_loop(lambda: ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"],
+                                           mode=mode, out=out), 10, 2, torch)
+        res[mode] = {"ms": round(ms, 4), "tracks_per_s": round(n / (ms * 1e-3))}
+    res["tuned_launch"] = ctx.tuned_shape("fp32b", n)
+    # per-event launches on views of the same buffers (each event its own pitch window)
+    print("[bench] per-event launches", file=sys.stderr, flush=True)
+    per = []
+    for e in range(len(offs) - 1):
+        a, b = int(offs[e]), int(offs[e + 1])
+        ev = tg.FitSet(fs.det, fs.state[:, a:b], fs.cov[:, a:b], fs.q[a:b], fs.hits[:, :, a:b],
+                       fs.valid[:, a:b], fs.truth_pos[:, :, a:b], fs.truth_mom[:, :, a:b])
+        per.append((fit_inputs(ev, "fp32b"), b - a))
+    outs = [ctx.alloc_fit_out(m, dd["state"].shape[1], torch.float32) for dd, m in per]
+
+    def all_events():
+        for (dd, m), oo in zip(per, outs):
+            ctx.fit(dd["state"], dd["cov"], dd["q"], dd["hits"], dd["valid"], mode="fused", out=oo)
+
+    ms, wall = timed_loop(all_events, 3, 1, torch)
+    res["per_event_launches"] = {"ms": round(ms, 4), "tracks_per_s": round(n / (ms * 1e-3)),
+                                 "launches": len(per), "wall_ms": round(wall, 3)}
+    res["one_launch_speedup"] = round(ms / res["auto"]["ms"], 2)
+    line = {"metric": "fitted tracks/s, uneven events in one launch vs per-event launches",
+            "value": res["auto"]["tracks_per_s"], "unit": "tracks/s", "n_gpus": 1,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "uneven batching: 2,000 events, log-normal track counts, "
+                                   "6-17 hits, 0-3 missing layers, 17 layers"},
+            "detail": res}
+    print(json.dumps(line))
+
+
+def profile_run(args):
+    """One timed loop only, for rocprofv3 (no oracle, no other kernels)."""
+    import torch
+    import paper_1605_05508_amd as ktf
+    import trackgen as tg
+    from tests.helpers import build_inputs, fit_inputs
+    if args.profile == "copy":
+        # a plain device copy of known size: 256 MiB read, 256 MiB written
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "steps": args.steps}))
+        return
+    if args.profile == "fit":
+        fs = tg.config2(n=args.n)
+        ctx = ktf.Context.for_detector(fs.det)
+        d = fit_inputs(fs, "fp32b")
+        out = ctx.alloc_fit_out(fs.n, d["state"].shape[1], torch.float32)
+        run = lambda: ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="fused", out=out)
+        ms, _ = timed_loop(run, args.steps, args.warmup, torch)
+        print(json.dumps({"ms_per_step": ms, "n": fs.n}))
+        return
+    bs = tg.config3()
+    ctx = ktf.Context.for_detector(bs.det)
+    d = build_inputs(bs, "fp32b")
+    o = ctx.build(d)
+    run = lambda: ctx.build(d, out=o)
+    ms, _ = timed_loop(run, args.steps, args.warmup, torch)
+    print(json.dumps({"ms_per_step": ms, "seeds": bs.n_seeds}))
+
+
 def timed_loop(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -177,6 +303,12 @@ def main():
               "(the path shards by tracks/events with no exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        profile_run(args)
+        return
+    if args.workload == "uneven":
+        uneven_workload(args)
+        return
     import torch
     import paper_1605_05508_amd as ktf
     import trackgen as tg
@@ -203,9 +335,6 @@ def main():
 
     print("[bench] timing FP32-bulk fused fit", file=sys.stderr, flush=True)
     ms, wall_ms = timed_loop(run32, args.steps, args.warmup, torch)
-    if args.profile:
-        print(json.dumps({"ms_per_step": ms, "n": n}))
-        return
     k_ms = per_launch_ms(run32, 10, torch)
 
     print("[bench] timing FP64 fused, graph sweeps", file=sys.stderr, flush=True)
@@ -297,6 +426,12 @@ def main():
                          "status_mismatch": int(np.sum(gs["status"].astype(np.uint32) != o["status"]))}
         acc["oracle_pull_rms"] = {kk: round(float(np.sqrt(np.mean(v ** 2))), 4) for kk, v in po.items()}
         result["accuracy_vs_oracle"] = acc
+    if not args.no_build:
+        print("[bench] building", file=sys.stderr, flush=True)
+        orc = None
+        if not args.no_cpu:
+            import oracle as orc
+        result["building"] = build_measurement(ktf.Context, tg, torch, orc=orc)
     if not args.no_serving:
         print("[bench] serving loop", file=sys.stderr, flush=True)
         rates = [float(r) for r in args.rates.split(",")]

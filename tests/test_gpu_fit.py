@@ -76,11 +76,13 @@ def test_modes_agree(ctx10):
         for a, b in (("fused", "persistent"), ("sweep", "sweep_graph")):
             for key in res[a]:
                 assert np.array_equal(res[a][key], res[b][key]), (prec, a, b, key)
-        tol = 1e-12 if prec == "fp64" else 1e-5
+        # FP32 rounding differs between the families at the level of each
+        # one's error against the FP64 oracle (a few 1e-5 relative)
+        tol = 1e-12 if prec == "fp64" else 2e-4
         f, w = res["fused"], res["sweep"]
         assert np.array_equal(f["nupd"], w["nupd"]) and np.array_equal(f["status"], w["status"])
         np.testing.assert_allclose(w["state"], f["state"], rtol=tol, atol=tol)
-        np.testing.assert_allclose(w["chi2"], f["chi2"], rtol=100 * tol)
+        np.testing.assert_allclose(w["chi2"], f["chi2"], rtol=50 * tol, atol=tol)
 
 
 def test_fp32_bulk_accuracy_and_pulls(ctx10, orc):
@@ -122,27 +124,36 @@ def test_full_size_sampled(ctx10, orc):
 
 
 def test_status_flags(ctx10, orc):
+    """Tracks 0..9 are too soft to reach the layers beyond ~27 cm (tight
+    prior, no hits in between so nothing corrects the momentum): NO_REACH,
+    with the last state kept.  Tracks 20..24 carry a NaN hit on layer 5: the
+    residual covariance is not positive definite there, the hit is skipped
+    (S_NOT_PD) and the fit goes on."""
     rng = np.random.default_rng(33)
     fs = tg.make_fit_set(rng, 256, tg.barrel(10))
     st = fs.state.copy()
-    # tracks 0..9: too soft to reach the outer layers
     ptl = 0.9 * 0.00299792458 * 3.8 * 30.0 / 2
     ph = np.arctan2(st[4, :10], st[3, :10])
     st[3, :10], st[4, :10] = ptl * np.cos(ph), ptl * np.sin(ph)
     cov = fs.cov.copy()
-    cov[15, :10] = cov[18, :10] = (0.01 * ptl) ** 2
-    cov[16, :10] = 0
+    P0 = np.diag([1e-4, 1e-4, 1e-2, (0.01 * ptl) ** 2, (0.01 * ptl) ** 2, 1e-4])
+    for kk, (i, j) in enumerate([(i, j) for i in range(6) for j in range(i, 6)]):
+        cov[kk, :10] = P0[i, j]
+    valid = fs.valid.copy()
+    valid[1:9, :10] = 0
     hits = fs.hits.copy()
-    hits[5, 0, 20:25] = np.nan  # non-finite hits on layer 5
-    fs2 = tg.FitSet(fs.det, st, cov, fs.q, hits, fs.valid, fs.truth_pos, fs.truth_mom)
+    hits[5, 0, 20:25] = np.nan
+    fs2 = tg.FitSet(fs.det, st, cov, fs.q, hits, valid, fs.truth_pos, fs.truth_mom)
     o = orc.fit(fs2)
+    assert np.all(o["status"][:10] == orc.NO_REACH) and np.all(o["status"][20:25] == orc.S_NOT_PD)
     for prec in ("fp64", "fp32b"):
         d = fit_inputs(fs2, prec)
-        g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"]), fs.n)
-        assert np.all(g["status"][:10] & 1)
-        assert np.array_equal(g["status"].astype(np.uint32), o["status"])
-        assert np.all(g["status"][20:25] != 0)
-        assert np.all(g["status"][30:] == 0)
+        for mode in MODES:
+            g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode), fs.n)
+            assert np.array_equal(g["status"].astype(np.uint32), o["status"]), (prec, mode)
+            assert np.array_equal(g["nupd"], o["nupd"]), (prec, mode)
+        if prec == "fp64":
+            fp64_close(g, o, check_diverged=False)
 
 
 def test_empty_and_single(ctx10, orc):

@@ -24,11 +24,33 @@ Packed symmetric 6x6 covariances use the 21-value upper triangle in row order
 """
 from __future__ import annotations
 
+import concurrent.futures as _cf
 import dataclasses
 import math
+import os
 from typing import Optional
 
 import numpy as np
+
+_CHUNK = 1 << 18
+
+
+def _threads() -> int:
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(fn, n, *arrays):
+    """Run fn over track chunks in threads (numpy releases the GIL in its
+    loops); fn(sl) fills its outputs for the slice sl."""
+    if n <= _CHUNK:
+        fn(slice(0, n))
+        return
+    sls = [slice(a, min(n, a + _CHUNK)) for a in range(0, n, _CHUNK)]
+    with _cf.ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(fn, sls))
 
 C_LIGHT = 0.00299792458  # GeV / (cm T) per unit charge
 
@@ -101,57 +123,61 @@ def truth_crossings(truth: dict, det: Detector):
     Returns pos[L,3,n], mom[L,3,n] (float64, unrounded) and reached[L,n]
     (bool; False where the circle never reaches the layer).
     """
-    vx, vy, vz = truth["vx"], truth["vy"], truth["vz"]
-    px, py, pz = truth["px"], truth["py"], truth["pz"]
-    q = truth["q"].astype(np.float64)
-    n = vx.shape[0]
+    n = truth["vx"].shape[0]
     L = det.n_layers
-    k = C_LIGHT * q * det.bz
-    pt = np.hypot(px, py)
-    R = pt / np.abs(k)
-    cx = vx + py / k
-    cy = vy - px / k
-    d = np.hypot(cx, cy)
-    # d^2 - R^2 without cancellation: |v + w|^2 - |w|^2 = |v|^2 + 2 v.w
-    rho0sq = vx * vx + vy * vy
-    d2mR2 = rho0sq + 2.0 * (vx * py - vy * px) / k
-    ux, uy = cx / d, cy / d
     pos = np.zeros((L, 3, n))
     mom = np.zeros((L, 3, n))
     reached = np.zeros((L, n), dtype=bool)
-    r0x, r0y = vx - cx, vy - cy  # vertex relative to the circle centre
-    for li, r in enumerate(det.radii):
-        a = (r * r + d2mR2) / (2.0 * d)
-        h2 = r * r - a * a
-        ok = h2 >= 0.0
-        h = np.sqrt(np.where(ok, h2, 0.0))
-        best_s = np.full(n, np.inf)
-        best_x = np.zeros(n)
-        best_y = np.zeros(n)
-        for sgn in (1.0, -1.0):
-            X = a * ux - sgn * h * uy
-            Y = a * uy + sgn * h * ux
-            rx, ry = X - cx, Y - cy
-            cross = r0x * ry - r0y * rx
-            dot = r0x * rx + r0y * ry
-            dlt = np.arctan2(cross, dot)
-            # k > 0 turns clockwise (negative angle), k < 0 counter-clockwise
-            ang = np.where(k > 0, np.where(dlt <= 0, dlt, dlt - 2 * math.pi),
-                           np.where(dlt >= 0, dlt, dlt + 2 * math.pi))
-            s = np.abs(ang) * R
-            better = s < best_s
-            best_s = np.where(better, s, best_s)
-            best_x = np.where(better, X, best_x)
-            best_y = np.where(better, Y, best_y)
-        theta = -k * best_s / pt
-        c, sn = np.cos(theta), np.sin(theta)
-        pos[li, 0] = best_x
-        pos[li, 1] = best_y
-        pos[li, 2] = vz + best_s * pz / pt
-        mom[li, 0] = px * c - py * sn
-        mom[li, 1] = py * c + px * sn
-        mom[li, 2] = pz
-        reached[li] = ok
+
+    def work(sl):
+        vx, vy, vz = truth["vx"][sl], truth["vy"][sl], truth["vz"][sl]
+        px, py, pz = truth["px"][sl], truth["py"][sl], truth["pz"][sl]
+        q = truth["q"][sl].astype(np.float64)
+        k = C_LIGHT * q * det.bz
+        pt = np.hypot(px, py)
+        R = pt / np.abs(k)
+        cx = vx + py / k
+        cy = vy - px / k
+        d = np.hypot(cx, cy)
+        # d^2 - R^2 without cancellation: |v + w|^2 - |w|^2 = |v|^2 + 2 v.w
+        d2mR2 = vx * vx + vy * vy + 2.0 * (vx * py - vy * px) / k
+        ux, uy = cx / d, cy / d
+        r0x, r0y = vx - cx, vy - cy  # vertex relative to the circle centre
+        m = vx.shape[0]
+        for li, r in enumerate(det.radii):
+            a = (r * r + d2mR2) / (2.0 * d)
+            h2 = r * r - a * a
+            ok = h2 >= 0.0
+            h = np.sqrt(np.where(ok, h2, 0.0))
+            best_s = np.full(m, np.inf)
+            best_x = np.zeros(m)
+            best_y = np.zeros(m)
+            for sgn in (1.0, -1.0):
+                X = a * ux - sgn * h * uy
+                Y = a * uy + sgn * h * ux
+                rx, ry = X - cx, Y - cy
+                cross = r0x * ry - r0y * rx
+                dot = r0x * rx + r0y * ry
+                dlt = np.arctan2(cross, dot)
+                # k > 0 turns clockwise (negative angle), k < 0 counter-clockwise
+                ang = np.where(k > 0, np.where(dlt <= 0, dlt, dlt - 2 * math.pi),
+                               np.where(dlt >= 0, dlt, dlt + 2 * math.pi))
+                s = np.abs(ang) * R
+                better = s < best_s
+                best_s = np.where(better, s, best_s)
+                best_x = np.where(better, X, best_x)
+                best_y = np.where(better, Y, best_y)
+            theta = -k * best_s / pt
+            c, sn = np.cos(theta), np.sin(theta)
+            pos[li, 0, sl] = best_x
+            pos[li, 1, sl] = best_y
+            pos[li, 2, sl] = vz + best_s * pz / pt
+            mom[li, 0, sl] = px * c - py * sn
+            mom[li, 1, sl] = py * c + px * sn
+            mom[li, 2, sl] = pz
+            reached[li, sl] = ok
+
+    _chunked(work, n)
     return pos, mom, reached
 
 
@@ -164,10 +190,16 @@ def smear_hits(rng: np.random.Generator, pos, det: Detector):
     L, _, n = pos.shape
     hits = np.zeros_like(pos)
     for li, r in enumerate(det.radii):
-        phi = np.arctan2(pos[li, 1], pos[li, 0]) + rng.normal(0.0, det.sigma_rphi, n) / r
-        hits[li, 0] = r * np.cos(phi)
-        hits[li, 1] = r * np.sin(phi)
-        hits[li, 2] = pos[li, 2] + rng.normal(0.0, det.sigma_z, n)
+        dphi = rng.normal(0.0, det.sigma_rphi, n) / r
+        dz = rng.normal(0.0, det.sigma_z, n)
+
+        def work(sl, li=li, r=r, dphi=dphi, dz=dz):
+            phi = np.arctan2(pos[li, 1, sl], pos[li, 0, sl]) + dphi[sl]
+            hits[li, 0, sl] = r * np.cos(phi)
+            hits[li, 1, sl] = r * np.sin(phi)
+            hits[li, 2, sl] = pos[li, 2, sl] + dz[sl]
+
+        _chunked(work, n)
     return f32(hits)
 
 
