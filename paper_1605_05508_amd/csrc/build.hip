@@ -9,11 +9,11 @@
 //           bins inside a window that no compatible hit can lie outside of,
 //           keep the candidate's best records (a bookkeeping list) -- no
 //           candidate is copied here;
-//   select  one 16-lane group per seed: merge the candidates' sorted record
-//           lists with wave shuffles to the best max_cands by the ranking
-//           (more hits, lower chi2, lower parent rank, lower hit index, a
-//           missed layer last), then each selected record's lane clones its
-//           parent's propagated state and applies the Kalman update;
+//   merge   one lane per seed: merge the candidates' sorted record lists to
+//           the best max_cands by the ranking (more hits, lower chi2, lower
+//           parent rank, lower hit index, a missed layer last);
+//   clone   one lane per selected record: clone its parent's propagated
+//           state and apply the Kalman update with the record's hit;
 //   final   one lane per seed: the best survivor or ended candidate, hit
 //           indices recovered by walking the per-layer (parent, hit) records.
 //
@@ -31,7 +31,6 @@
 
 namespace ktf {
 
-constexpr int kGroup = 16;  // lanes per seed in the select step (>= KTF_MAX_CANDS)
 constexpr double kPi = 3.14159265358979323846;
 
 template <typename T> struct BuildNewton;
@@ -59,6 +58,7 @@ struct BuildArgs {
   int32_t* bin_cur;        // [n_groups][n_bins]
   int32_t* hit_bin;        // [n_hits]
   int32_t* perm;           // [n_hits]: local index of the hit at each binned position
+  int32_t* perm_raw;       // [n_hits]: the same before ordering within bins
   void* hb;                // [3][n_hits]: binned coordinates
   // candidates (double buffered), propagated parents, records
   double* cpos[2];
@@ -72,6 +72,7 @@ struct BuildArgs {
   double* rchi;            // [max_cands][S]
   int32_t* rhit;           // [max_cands][S]
   int32_t* rcount;         // [S]: records, -1 ended (no reach), -2 ended (missed too often)
+  int32_t* sel;            // [max_cands][sp]: selected (parent | record << 8)
   int32_t* hist;           // [L][max_cands][2][sp]
   int32_t* count;          // [L][sp]
   // best ended candidate per seed
@@ -138,35 +139,49 @@ __global__ void bin_count_kernel(BuildArgs a) {
 }
 
 // one block per (event, layer): exclusive scan of the bin counts into the CSR
-// offsets, and the cursor reset to each bin's start
+// offsets, and the cursor reset to each bin's start.  The block walks the
+// bins in coalesced chunks of 1024; each chunk is scanned with wave
+// shuffles, the wave totals through LDS, and a running carry.
 constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(BuildArgs a) {
-  __shared__ int32_t part[kScanThreads];
+  __shared__ int32_t wsum[kScanThreads / 64];
   const int g = blockIdx.x;
   const int nb = a.n_bins;
   int32_t* cnt = a.bin_cur + (int64_t)g * nb;
   int32_t* off = a.bin_off + (int64_t)g * (nb + 1);
-  const int per = (nb + kScanThreads - 1) / kScanThreads;
-  const int b0 = threadIdx.x * per;
-  const int b1 = min(nb, b0 + per);
-  int32_t s = 0;
-  for (int b = b0; b < b1; ++b) s += cnt[b];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int d = 1; d < kScanThreads; d <<= 1) {  // Hillis-Steele inclusive scan
-    const int32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int nw = kScanThreads / 64;
+  int32_t carry = 0;
+  for (int base = 0; base < nb; base += kScanThreads) {
+    const int b = base + threadIdx.x;
+    const int32_t v = b < nb ? cnt[b] : 0;
+    int32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    part[threadIdx.x] += v;
+    if (wave == 0) {
+      int32_t t = lane < nw ? wsum[lane] : 0;
+#pragma unroll
+      for (int d = 1; d < nw; d <<= 1) {
+        const int32_t y = __shfl_up(t, d, 64);
+        if (lane >= d) t += y;
+      }
+      if (lane < nw) wsum[lane] = t;
+    }
+    __syncthreads();
+    const int32_t excl = carry + (wave > 0 ? wsum[wave - 1] : 0) + x - v;
+    if (b < nb) {
+      off[b] = excl;
+      cnt[b] = excl;
+    }
+    carry += wsum[nw - 1];
     __syncthreads();
   }
-  int32_t run = part[threadIdx.x] - s;  // exclusive prefix of this thread's range
-  for (int b = b0; b < b1; ++b) {
-    const int32_t c = cnt[b];
-    off[b] = run;
-    cnt[b] = run;
-    run += c;
-  }
-  if (threadIdx.x == kScanThreads - 1) off[nb] = part[kScanThreads - 1];
+  if (threadIdx.x == 0) off[nb] = carry;
 }
 
 __global__ void bin_scatter_kernel(BuildArgs a) {
@@ -175,40 +190,32 @@ __global__ void bin_scatter_kernel(BuildArgs a) {
   const int g = find_event(a.hit_off, a.n_groups, j);
   const int b = a.hit_bin[j];
   const int32_t pos = atomicAdd(&a.bin_cur[(int64_t)g * a.n_bins + b], 1);
-  a.perm[a.hit_off[g] + pos] = (int32_t)(j - a.hit_off[g]);
+  a.perm_raw[a.hit_off[g] + pos] = (int32_t)(j - a.hit_off[g]);
 }
 
-// one lane per (event, layer, bin): order the bin's hits by original index
-// (the scatter's atomics left them in arrival order) and copy their
-// coordinates into binned order
+// one lane per hit: its place within its bin is the number of the bin's
+// hits with a smaller original index (the scatter's atomics left the bin in
+// arrival order), which orders every bin by original index; the hit's
+// coordinates are copied to that binned position
 template <typename TS>
-__global__ void bin_sort_kernel(BuildArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)a.n_groups * a.n_bins) return;
-  const int g = (int)(t / a.n_bins);
-  const int b = (int)(t - (int64_t)g * a.n_bins);
+__global__ void bin_rank_kernel(BuildArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_hits) return;
+  const int g = find_event(a.hit_off, a.n_groups, j);
+  const int b = a.hit_bin[j];
   const int32_t* off = a.bin_off + (int64_t)g * (a.n_bins + 1);
-  const int32_t lo = off[b], hi = off[b + 1];
-  if (lo == hi) return;
   const int64_t base = a.hit_off[g];
-  int32_t* p = a.perm + base;
-  for (int32_t i = lo + 1; i < hi; ++i) {  // insertion sort, bins hold a few hits
-    const int32_t v = p[i];
-    int32_t k = i - 1;
-    while (k >= lo && p[k] > v) {
-      p[k + 1] = p[k];
-      --k;
-    }
-    p[k + 1] = v;
-  }
+  const int32_t lo = off[b], hi = off[b + 1];
+  const int32_t jl = (int32_t)(j - base);
+  int32_t rank = 0;
+  for (int32_t k = lo; k < hi; ++k) rank += a.perm_raw[base + k] < jl ? 1 : 0;
+  const int64_t dst = base + lo + rank;
+  a.perm[dst] = jl;
   const TS* h = static_cast<const TS*>(a.hits);
   TS* o = static_cast<TS*>(a.hb);
-  for (int32_t i = lo; i < hi; ++i) {
-    const int64_t src = base + p[i];
-    o[base + i] = h[src];
-    o[a.n_hits + base + i] = h[a.hp + src];
-    o[2 * a.n_hits + base + i] = h[2 * a.hp + src];
-  }
+  o[dst] = h[j];
+  o[a.n_hits + dst] = h[a.hp + j];
+  o[2 * a.n_hits + dst] = h[2 * a.hp + j];
 }
 
 // ------------------------------------------------------------- candidates
@@ -446,43 +453,6 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
 }
 
 // ----------------------------------------------------------------- select
-// ranking key: more hits, lower chi2, lower parent, lower hit (missed last)
-struct Key {
-  int nh;
-  double chi2;
-  int parent;
-  uint32_t hit;
-  bool valid;
-};
-
-__device__ __forceinline__ bool key_less(const Key& x, const Key& y) {
-  if (x.valid != y.valid) return x.valid;
-  if (!x.valid) return false;
-  if (x.nh != y.nh) return x.nh > y.nh;
-  if (x.chi2 != y.chi2) return x.chi2 < y.chi2;
-  if (x.parent != y.parent) return x.parent < y.parent;
-  return x.hit < y.hit;
-}
-
-__device__ __forceinline__ Key shfl_key(const Key& k, int src_lane_xor) {
-  Key o;
-  o.nh = __shfl_xor(k.nh, src_lane_xor, kGroup);
-  o.chi2 = __shfl_xor(k.chi2, src_lane_xor, kGroup);
-  o.parent = __shfl_xor(k.parent, src_lane_xor, kGroup);
-  o.hit = (uint32_t)__shfl_xor((int)k.hit, src_lane_xor, kGroup);
-  o.valid = __shfl_xor((int)k.valid, src_lane_xor, kGroup) != 0;
-  return o;
-}
-
-__device__ __forceinline__ Key group_min(Key k) {
-#pragma unroll
-  for (int d = kGroup / 2; d >= 1; d >>= 1) {
-    const Key o = shfl_key(k, d);
-    if (key_less(o, k)) k = o;
-  }
-  return k;
-}
-
 // final-choice key: more hits, lower chi2, earlier end, lower rank
 __device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, int nh2, double c2,
                                            int e2, int r2) {
@@ -492,104 +462,120 @@ __device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, i
   return r1 < r2;
 }
 
-template <typename TS, typename TP>
-__global__ __launch_bounds__(256) void build_select_kernel(BuildArgs a, int l, int cur) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = (int)(gt % kGroup);
-  const int64_t s = gt / kGroup;
-  const bool seed_ok = s < a.n_seeds;
-  const int NC = a.g.max_cands;
-  const int L = a.g.n_layers;
-  const int nxt = cur ^ 1;
-  const int nlive = seed_ok ? a.count[(int64_t)(l - 1) * a.sp + s] : 0;
-  const bool par = lane < nlive;
-  const int64_t pslot = (int64_t)lane * a.sp + s;
-  int rc = 0, nh = 0, nm = 0;
-  uint32_t pst = 0;
-  double pchi2 = 0.0;
-  if (par) {
-    rc = a.rcount[pslot];
-    const uint32_t m = a.cmeta[cur][pslot];
-    nh = meta_nh(m);
-    nm = meta_nm(m);
-    pst = meta_st(m) | (rc == -1 ? kNoReach : 0u);
-    pchi2 = a.cchi2[cur][pslot];
-  }
+// One lane per seed.  The parents' record lists are each sorted by (chi2,
+// hit); the current head of every list sits in LDS (one column per lane, so
+// the dynamic parent index costs no registers) and the best head by the
+// ranking (more hits, lower chi2, lower parent, lower hit; missed layer
+// last) is taken max_cands times.  Parents that ended this layer compete
+// for the seed's best ended candidate.  Rows are rank-major, so lane s of a
+// wave reads consecutive seeds: coalesced.
+constexpr int kMergeThreads = 128;
 
-  // ended parents: the best of them may become the seed's best ended one
-  {
-    Key ek;
-    ek.valid = par && rc < 0;
-    ek.nh = nh;
-    ek.chi2 = pchi2;
-    ek.parent = lane;
-    ek.hit = 0;
-    const Key best = group_min(ek);
-    if (best.valid && lane == best.parent) {
-      const int be = a.bend[s];
-      const bool better = be < 0 || final_less(nh, pchi2, l, lane, meta_nh(a.bmeta[s]), a.bchi2[s],
-                                               be, a.brank[s]);
-      if (better) {
-        TrackState<TP> x;
-        TP P[21];
-        load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, pslot, x, P);
-        store_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
-        a.bchi2[s] = pchi2;
-        a.bmeta[s] = pack_meta(nh, nm, pst);
-        a.bend[s] = l;
-        a.brank[s] = lane;
+template <typename TS>
+__global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a, int l, int cur) {
+  __shared__ double hchi_s[KTF_MAX_CANDS][kMergeThreads];
+  __shared__ int32_t hhit_s[KTF_MAX_CANDS][kMergeThreads];
+  __shared__ int32_t info_s[KTF_MAX_CANDS][kMergeThreads];  // rc | head << 8 | nh << 16
+  const int tid = threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * kMergeThreads + tid;
+  if (s >= a.n_seeds) return;
+  const int NC = a.g.max_cands;
+  const int64_t sp = a.sp, S = a.S;
+  const int nlive = a.count[(int64_t)(l - 1) * sp + s];
+  int e_best = -1, e_nh = 0;
+  double e_chi = 0.0;
+  for (int r = 0; r < nlive; ++r) {
+    const int64_t slot = (int64_t)r * sp + s;
+    const int rc = a.rcount[slot];
+    const int nh = meta_nh(a.cmeta[cur][slot]);
+    info_s[r][tid] = (rc > 0 ? rc : 0) | (nh << 16);
+    if (rc > 0) {
+      hchi_s[r][tid] = a.rchi[slot];
+      hhit_s[r][tid] = a.rhit[slot];
+    } else {
+      const double c = a.cchi2[cur][slot];
+      if (e_best < 0 || nh > e_nh || (nh == e_nh && c < e_chi)) {
+        e_best = r;
+        e_nh = nh;
+        e_chi = c;
       }
     }
   }
-
-  // merge the parents' sorted record lists into the best NC
-  int head = 0;
-  int my_parent = -1, my_rec = -1;
+  if (e_best >= 0) {
+    const int be = a.bend[s];
+    if (be < 0 || final_less(e_nh, e_chi, l, e_best, meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s])) {
+      // element-wise copy of the ended candidate (rare; keeps registers low)
+      const int64_t slot = (int64_t)e_best * sp + s;
+      for (int c = 0; c < 3; ++c) a.bpos[c * sp + s] = a.cpos[cur][c * S + slot];
+      const TS* mo = static_cast<const TS*>(a.cmom[cur]);
+      const TS* co = static_cast<const TS*>(a.ccov[cur]);
+      TS* bm = static_cast<TS*>(a.bmom);
+      TS* bc = static_cast<TS*>(a.bcov);
+      for (int c = 0; c < 3; ++c) bm[c * sp + s] = mo[c * S + slot];
+      for (int c = 0; c < 21; ++c) bc[c * sp + s] = co[c * S + slot];
+      const uint32_t m = a.cmeta[cur][slot];
+      a.bchi2[s] = e_chi;
+      a.bmeta[s] = pack_meta(e_nh, meta_nm(m), meta_st(m) | (a.rcount[slot] == -1 ? kNoReach : 0u));
+      a.bend[s] = l;
+      a.brank[s] = e_best;
+    }
+  }
   int nsel = 0;
-  for (int kk = 0; kk < NC; ++kk) {
-    Key key;
-    key.valid = par && rc > 0 && head < rc;
-    if (key.valid) {
-      const int32_t h = a.rhit[(int64_t)head * a.S + pslot];
-      key.chi2 = a.rchi[(int64_t)head * a.S + pslot];
-      key.nh = h >= 0 ? nh + 1 : nh;
-      key.hit = (uint32_t)h;
-      key.parent = lane;
-    } else {
-      key.nh = 0;
-      key.chi2 = 0.0;
-      key.hit = 0;
-      key.parent = 0;
+  for (int k = 0; k < NC; ++k) {
+    int w = -1, wnh = 0;
+    double wchi = 0.0;
+    for (int r = 0; r < nlive; ++r) {
+      const int info = info_s[r][tid];
+      const int rc = info & 0xff, head = (info >> 8) & 0xff;
+      if (head >= rc) continue;
+      const int knh = (info >> 16) + (hhit_s[r][tid] >= 0 ? 1 : 0);
+      const double c = hchi_s[r][tid];
+      if (w < 0 || knh > wnh || (knh == wnh && c < wchi)) {
+        w = r;
+        wnh = knh;
+        wchi = c;
+      }
     }
-    const Key w = group_min(key);
-    if (!w.valid) break;
-    // the winner's record index: the winning lane's head before advancing
-    const int wave_lane = (int)(threadIdx.x & 63);
-    const int widx = __shfl(head, (wave_lane & ~(kGroup - 1)) + w.parent, 64);
-    if (lane == kk) {
-      my_parent = w.parent;
-      my_rec = widx;
+    if (w < 0) break;
+    const int info = info_s[w][tid];
+    const int rc = info & 0xff, head = (info >> 8) & 0xff;
+    a.sel[(int64_t)k * sp + s] = w | (head << 8);
+    info_s[w][tid] = (info & ~0xff00) | ((head + 1) << 8);
+    if (head + 1 < rc) {
+      const int64_t ri = (int64_t)(head + 1) * S + (int64_t)w * sp + s;
+      hchi_s[w][tid] = a.rchi[ri];
+      hhit_s[w][tid] = a.rhit[ri];
     }
-    if (lane == w.parent) ++head;
     ++nsel;
   }
-  if (!seed_ok) return;
-  if (lane == 0) a.count[(int64_t)l * a.sp + s] = nsel;
-  if (lane >= nsel) return;
+  a.count[(int64_t)l * sp + s] = nsel;
+}
 
-  // clone + update: child `lane` from its parent's propagated state
-  const int64_t ps = (int64_t)my_parent * a.sp + s;
-  const int32_t h = a.rhit[(int64_t)my_rec * a.S + ps];
-  const double c2 = a.rchi[(int64_t)my_rec * a.S + ps];
+// One lane per child slot (rank-major): clone the selected record's parent
+// from its propagated state and apply the Kalman update with the record's
+// hit (a missed layer keeps the propagated state).
+template <typename TS, typename TP>
+__global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int cur) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.S) return;
+  const int64_t sp = a.sp, S = a.S;
+  const int k = (int)(t / sp);
+  const int64_t s = t - (int64_t)k * sp;
+  if (s >= a.n_seeds) return;
+  if (k >= a.count[(int64_t)l * sp + s]) return;
+  const int nxt = cur ^ 1;
+  const int L = a.g.n_layers, NC = a.g.max_cands;
+  const int32_t sel = a.sel[(int64_t)k * sp + s];
+  const int parent = sel & 0xff, rec = sel >> 8;
+  const int64_t ps = (int64_t)parent * sp + s;
+  const int32_t h = a.rhit[(int64_t)rec * S + ps];
+  const double c2 = a.rchi[(int64_t)rec * S + ps];
   const uint32_t pm = a.cmeta[cur][ps];
   TrackState<TP> xp;
   TP Pp[21];
-  load_cand<TS, TP>(a.ppos, a.pmom, a.pcov, a.S, ps, xp, Pp);
-  TrackState<TP> x = xp;
-  TP P[21];
-#pragma unroll
-  for (int c = 0; c < 21; ++c) P[c] = Pp[c];
+  load_cand<TS, TP>(a.ppos, a.pmom, a.pcov, S, ps, xp, Pp);
   int cnh = meta_nh(pm), cnm = meta_nm(pm);
+  const int64_t cs = (int64_t)k * sp + s;
   if (h >= 0) {
     const int e = find_event(a.seed_off, a.n_events, s);
     const int64_t hi = a.hit_off[e * L + l] + h;
@@ -597,17 +583,19 @@ __global__ __launch_bounds__(256) void build_select_kernel(BuildArgs a, int l, i
     const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
     Residual R;
     residual(xp, Pp, m, hit_res(a), R);  // scored positive definite already
+    TrackState<TP> x;
+    TP P[21];
     apply_update(xp, Pp, R, x, P);
+    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, cs, x, P);
     ++cnh;
   } else {
+    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, cs, xp, Pp);
     ++cnm;
   }
-  const int64_t cs = (int64_t)lane * a.sp + s;
-  store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], a.S, cs, x, P);
   a.cchi2[nxt][cs] = c2;
   a.cmeta[nxt][cs] = pack_meta(cnh, cnm, meta_st(pm));
-  a.hist[((int64_t)l * NC + lane) * 2 * a.sp + 0 * a.sp + s] = my_parent;
-  a.hist[((int64_t)l * NC + lane) * 2 * a.sp + 1 * a.sp + s] = h;
+  a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = parent;
+  a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = h;
 }
 
 // ------------------------------------------------------------------ final
@@ -695,7 +683,8 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
     hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_groups), dim3(kScanThreads), 0, st, a);
     if (a.n_hits > 0)
       hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(a.n_hits, bs)), dim3(bs), 0, st, a);
-    hipLaunchKernelGGL((bin_sort_kernel<TS>), dim3(nblk(nbins_all, bs)), dim3(bs), 0, st, a);
+    if (a.n_hits > 0)
+      hipLaunchKernelGGL((bin_rank_kernel<TS>), dim3(nblk(a.n_hits, bs)), dim3(bs), 0, st, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || bins_only || a.n_seeds == 0) return e;
@@ -703,8 +692,9 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   int cur = 0;
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     hipLaunchKernelGGL((build_score_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
-    hipLaunchKernelGGL((build_select_kernel<TS, TP>), dim3(nblk(a.n_seeds * kGroup, bs)), dim3(bs), 0,
+    hipLaunchKernelGGL((build_merge_kernel<TS>), dim3(nblk(a.n_seeds, kMergeThreads)), dim3(kMergeThreads), 0,
                        st, a, l, cur);
+    hipLaunchKernelGGL((build_clone_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
     cur ^= 1;
   }
   hipLaunchKernelGGL((build_final_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
@@ -799,9 +789,10 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     return hip_fail(c, e, "bin workspace");
   a.bin_off = static_cast<int32_t*>(c->b_off.p);
   a.bin_cur = a.bin_off + (size_t)a.n_groups * (nb + 1);
-  if ((e = c->b_perm.ensure(sizeof(int32_t) * 2 * (size_t)nhits)) != hipSuccess) return hip_fail(c, e, "bin workspace");
+  if ((e = c->b_perm.ensure(sizeof(int32_t) * 3 * (size_t)nhits)) != hipSuccess) return hip_fail(c, e, "bin workspace");
   a.perm = static_cast<int32_t*>(c->b_perm.p);
   a.hit_bin = a.perm + nhits;
+  a.perm_raw = a.hit_bin + nhits;
   if ((e = c->b_binned.ensure(ts * 3 * (size_t)nhits)) != hipSuccess) return hip_fail(c, e, "bin workspace");
   a.hb = c->b_binned.p;
   if (bins_only) return KTF_OK;
@@ -831,7 +822,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.pcov = p;
   }
   const int NC = cfg.max_cands;
-  if ((e = c->b_rec.ensure((size_t)S * (NC * 12 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
+  if ((e = c->b_rec.ensure((size_t)S * (NC * 12 + 4 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
   {
     char* p = static_cast<char*>(c->b_rec.p);
     a.rchi = reinterpret_cast<double*>(p);
@@ -839,6 +830,8 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.rhit = reinterpret_cast<int32_t*>(p);
     p += (size_t)S * NC * 4;
     a.rcount = reinterpret_cast<int32_t*>(p);
+    p += (size_t)S * 4;
+    a.sel = reinterpret_cast<int32_t*>(p);
   }
   const int64_t sp = std::max<int64_t>(a.sp, 1);
   if ((e = c->b_best.ensure((size_t)sp * (3 * 8 + 24 * ts + 8 + 4 + 4 + 4))) != hipSuccess)

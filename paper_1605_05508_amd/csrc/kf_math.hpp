@@ -396,10 +396,12 @@ KTF_HD void apply_update(const TrackState<T>& xp, const T Pp[21], const Residual
     K[i][0] = k0;
     K[i][1] = k1;
     K[i][2] = k2;
-    D[i][0] = b0 - 0.5 * (k0 * S[0] + k1 * S[1] + k2 * S[2]);
-    D[i][1] = b1 - 0.5 * (k0 * S[1] + k1 * S[3] + k2 * S[4]);
-    D[i][2] = b2 - 0.5 * (k0 * S[2] + k1 * S[4] + k2 * S[5]);
-    const double dx = k0 * R.r[0] + k1 * R.r[1] + k2 * R.r[2];
+    // D = B - (K S)/2, as fused multiply-adds on the halved gain
+    const double h0 = -0.5 * k0, h1 = -0.5 * k1, h2 = -0.5 * k2;
+    D[i][0] = fma(h0, S[0], fma(h1, S[1], fma(h2, S[2], b0)));
+    D[i][1] = fma(h0, S[1], fma(h1, S[3], fma(h2, S[4], b1)));
+    D[i][2] = fma(h0, S[2], fma(h1, S[4], fma(h2, S[5], b2)));
+    const double dx = fma(k0, R.r[0], fma(k1, R.r[1], k2 * R.r[2]));
     if (i < 3)
       x.pos[i] = xp.pos[i] + dx;
     else
@@ -411,7 +413,10 @@ KTF_HD void apply_update(const TrackState<T>& xp, const T Pp[21], const Residual
     for (int j = i; j < 6; ++j) {
       double acc = (double)Pp[pidx(i, j)];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc -= K[i][c] * D[j][c] + D[i][c] * K[j][c];
+      for (int c = 0; c < 3; ++c) {
+        acc = fma(-K[i][c], D[j][c], acc);
+        acc = fma(-D[i][c], K[j][c], acc);
+      }
       P[pidx(i, j)] = (T)acc;
     }
   }
