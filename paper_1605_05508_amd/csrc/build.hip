@@ -59,6 +59,12 @@ struct BuildArgs {
   int32_t* hit_bin;        // [n_hits]
   int32_t* perm;           // [n_hits]: local index of the hit at each binned position
   int32_t* perm_raw;       // [n_hits]: the same before ordering within bins
+  int32_t* sev;            // [sp]: event of each seed
+  int32_t* cseed[2];       // [S]: seed of each dense candidate row
+  int32_t* cstart[2];      // [sp]: first dense row of each seed's candidates
+  int32_t* sel_parent;     // [S]: per child row, its parent's row
+  int32_t* sel_rec;        // [S]: per child row, the parent's record it takes
+  unsigned* ccount;        // [n_layers]: number of candidate rows after each layer
   void* hb;                // [3][n_hits]: binned coordinates
   // candidates (double buffered), propagated parents, records
   double* cpos[2];
@@ -70,9 +76,9 @@ struct BuildArgs {
   void* pmom;
   void* pcov;
   double* rchi;            // [max_cands][S]
-  int32_t* rhit;           // [max_cands][S]
+  int32_t* rhit;           // [max_cands][S]: original hit index
+  int32_t* rpos;           // [max_cands][S]: binned position of the hit
   int32_t* rcount;         // [S]: records, -1 ended (no reach), -2 ended (missed too often)
-  int32_t* sel;            // [max_cands][sp]: selected (parent | record << 8)
   int32_t* hist;           // [L][max_cands][2][sp]
   int32_t* count;          // [L][sp]
   // best ended candidate per seed
@@ -218,6 +224,96 @@ __global__ void bin_rank_kernel(BuildArgs a) {
   o[2 * a.n_hits + dst] = h[2 * a.hp + j];
 }
 
+// One block per (event, layer) with the whole bin histogram in LDS: count
+// the hits per bin with LDS atomics, scan the counts into the CSR offsets,
+// scatter the hits through an LDS cursor, then order every bin by original
+// index (a hit's place is the number of its bin's hits with a smaller index)
+// and copy the coordinates into binned order.  Used when the bin table fits
+// in LDS; the multi-kernel path above covers larger tables.
+constexpr int kBinThreads = 1024;
+constexpr int kLdsBins = 32768;
+template <typename TS>
+__global__ __launch_bounds__(kBinThreads) void bin_group_kernel(BuildArgs a) {
+  __shared__ int32_t hist[kLdsBins];
+  __shared__ int32_t wsum[kBinThreads / 64];
+  const int g = blockIdx.x;
+  const int nb = a.n_bins;
+  const int tid = threadIdx.x;
+  const int64_t base = a.hit_off[g];
+  const int32_t n = (int32_t)(a.hit_off[g + 1] - base);
+  int32_t* off = a.bin_off + (int64_t)g * (nb + 1);
+  const TS* h = static_cast<const TS*>(a.hits);
+  for (int b = tid; b < nb; b += kBinThreads) hist[b] = 0;
+  __syncthreads();
+  for (int32_t j = tid; j < n; j += kBinThreads) {
+    const int64_t gj = base + j;
+    const int b = hit_bin_of((double)h[gj], (double)h[a.hp + gj], (double)h[2 * a.hp + gj], a.g.z_half,
+                             a.g.n_zbins, a.g.n_phibins);
+    a.hit_bin[gj] = b;
+    atomicAdd(&hist[b], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the counts (coalesced chunks, wave shuffles)
+  const int lane = tid & 63, wave = tid >> 6;
+  constexpr int nw = kBinThreads / 64;
+  int32_t carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += kBinThreads) {
+    const int b = b0 + tid;
+    const int32_t v = b < nb ? hist[b] : 0;
+    int32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+      int32_t t = lane < nw ? wsum[lane] : 0;
+#pragma unroll
+      for (int d = 1; d < nw; d <<= 1) {
+        const int32_t y = __shfl_up(t, d, 64);
+        if (lane >= d) t += y;
+      }
+      if (lane < nw) wsum[lane] = t;
+    }
+    __syncthreads();
+    const int32_t excl = carry + (wave > 0 ? wsum[wave - 1] : 0) + x - v;
+    if (b < nb) {
+      off[b] = excl;
+      hist[b] = excl;
+    }
+    carry += wsum[nw - 1];
+    __syncthreads();
+  }
+  if (tid == 0) off[nb] = carry;
+  for (int32_t j = tid; j < n; j += kBinThreads) {
+    const int b = a.hit_bin[base + j];
+    const int32_t pos = atomicAdd(&hist[b], 1);
+    a.perm_raw[base + pos] = j;
+  }
+  __syncthreads();
+  TS* o = static_cast<TS*>(a.hb);
+  for (int32_t j = tid; j < n; j += kBinThreads) {
+    const int64_t gj = base + j;
+    const int b = a.hit_bin[gj];
+    const int32_t lo = off[b], hi = off[b + 1];
+    int32_t rank = 0;
+    for (int32_t k = lo; k < hi; ++k) rank += a.perm_raw[base + k] < j ? 1 : 0;
+    const int64_t dst = base + lo + rank;
+    a.perm[dst] = j;
+    o[dst] = h[gj];
+    o[a.n_hits + dst] = h[a.hp + gj];
+    o[2 * a.n_hits + dst] = h[2 * a.hp + gj];
+  }
+}
+
+// event of every seed, once per build
+__global__ void seed_event_kernel(BuildArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < a.n_seeds) a.sev[s] = find_event(a.seed_off, a.n_events, s);
+}
+
 // ------------------------------------------------------------- candidates
 template <typename TS, typename TP>
 __device__ __forceinline__ void load_cand(const double* pos, const void* mom, const void* cov,
@@ -249,77 +345,108 @@ __device__ __forceinline__ HitRes hit_res(const BuildArgs& a) {
   return HitRes{a.g.hr.sr2, a.g.hr.srphi2, a.g.hr.sz2};
 }
 
+// Candidates are stored densely per layer: the live candidates of a layer
+// occupy rows 0 .. n-1 of the current buffer, each seed's candidates are
+// contiguous (cstart[s] .. cstart[s] + count - 1, in rank order), and every
+// per-candidate field is its own row.  So neighbouring lanes always touch
+// neighbouring rows, whatever the rank.  Rows are reserved with one atomic
+// per wave (a wave prefix sum of the lanes' counts; lane 63 reserves the
+// wave's range).  The placement of a seed's range depends on scheduling; the
+// per-seed arithmetic and results do not.  Every lane of the wave must call
+// this; returns the lane's first row.
+__device__ __forceinline__ int64_t reserve_rows(unsigned* counter, int n) {
+  const int lane = threadIdx.x & 63;
+  int x = n;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  const int total = __shfl(x, 63, 64);
+  unsigned base = 0;
+  if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned)total);
+  base = __shfl(base, 63, 64);
+  return (int64_t)base + (x - n);
+}
+
 // seed phase: fit each seed over the seed layers with its own hits
 template <typename TS, typename TP>
 __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n_seeds) return;
+  const bool valid = s < a.n_seeds;
   const int L = a.g.n_layers, NSL = a.g.n_seed_layers;
-  const int e = find_event(a.seed_off, a.n_events, s);
-  const TS* st = static_cast<const TS*>(a.seed_state);
-  const TS* cv = static_cast<const TS*>(a.seed_cov);
   TrackState<TP> x;
   TP P[21];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * a.sp + s];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * a.sp + s];
-#pragma unroll
-  for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * a.sp + s];
-  const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
-  const HitRes hr = hit_res(a);
-  const TS* hits = static_cast<const TS*>(a.hits);
   double chi2 = 0.0;
   int nh = 0;
   uint32_t status = 0;
   int reached = 0;
-  for (int l = 0; l < NSL; ++l) {
-    TrackState<TP> xp;
-    Jac<TP> F;
-    if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], l == 0, xp, F)) {
-      status |= kNoReach;
-      break;
-    }
-    reached = l + 1;
-    TP Pp[21];
-    cov_propagate(P, F, Pp);
-    const int g = e * L + l;
-    const int32_t h0 = a.seed_hit[l * a.sp + s];
-    // an index outside the layer's hit list counts as no hit
-    const int32_t h = (h0 >= 0 && h0 < a.hit_off[g + 1] - a.hit_off[g]) ? h0 : -1;
-    int32_t used = -1;
-    x = xp;
+  if (valid) {
+    const int e = a.sev[s];
+    const TS* st = static_cast<const TS*>(a.seed_state);
+    const TS* cv = static_cast<const TS*>(a.seed_cov);
 #pragma unroll
-    for (int c = 0; c < 21; ++c) P[c] = Pp[c];
-    if (h >= 0) {
-      const int64_t hi = a.hit_off[g] + h;
-      const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
-      Residual R;
-      if (residual(xp, Pp, m, hr, R)) {
-        apply_update(xp, Pp, R, x, P);
-        chi2 += R.chi2;
-        ++nh;
-        used = h;
-      } else {
-        status |= kSNotPD;
+    for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * a.sp + s];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * a.sp + s];
+#pragma unroll
+    for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * a.sp + s];
+    const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
+    const HitRes hr = hit_res(a);
+    const TS* hits = static_cast<const TS*>(a.hits);
+    for (int l = 0; l < NSL; ++l) {
+      TrackState<TP> xp;
+      Jac<TP> F;
+      if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], l == 0, xp, F)) {
+        status |= kNoReach;
+        break;
       }
+      reached = l + 1;
+      TP Pp[21];
+      cov_propagate(P, F, Pp);
+      const int g = e * L + l;
+      const int32_t h0 = a.seed_hit[l * a.sp + s];
+      // an index outside the layer's hit list counts as no hit
+      const int32_t h = (h0 >= 0 && h0 < a.hit_off[g + 1] - a.hit_off[g]) ? h0 : -1;
+      int32_t used = -1;
+      x = xp;
+#pragma unroll
+      for (int c = 0; c < 21; ++c) P[c] = Pp[c];
+      if (h >= 0) {
+        const int64_t hi = a.hit_off[g] + h;
+        const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
+        Residual R;
+        if (residual(xp, Pp, m, hr, R)) {
+          apply_update(xp, Pp, R, x, P);
+          chi2 += R.chi2;
+          ++nh;
+          used = h;
+        } else {
+          status |= kSNotPD;
+        }
+      }
+      a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 0 * a.sp + s] = 0;
+      a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 1 * a.sp + s] = used;
     }
-    a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 0 * a.sp + s] = 0;
-    a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 1 * a.sp + s] = used;
+    for (int l = 0; l < NSL; ++l) a.count[(int64_t)l * a.sp + s] = l < reached ? 1 : 0;
+    if (reached < NSL) {  // the seed itself ended: it is the best ended candidate
+      store_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
+      a.bchi2[s] = chi2;
+      a.bmeta[s] = pack_meta(nh, 0, status);
+      a.bend[s] = reached;
+      a.brank[s] = 0;
+    } else {
+      a.bend[s] = -1;
+    }
   }
-  for (int l = 0; l < NSL; ++l) a.count[(int64_t)l * a.sp + s] = l < reached ? 1 : 0;
-  store_cand<TS, TP>(a.cpos[0], a.cmom[0], a.ccov[0], a.S, s, x, P);
-  a.cchi2[0][s] = chi2;
-  a.cmeta[0][s] = pack_meta(nh, 0, status);
-  if (reached < NSL) {  // the seed itself ended: it is the best ended candidate
-    store_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
-    a.bchi2[s] = chi2;
-    a.bmeta[s] = pack_meta(nh, 0, status);
-    a.bend[s] = reached;
-    a.brank[s] = 0;
-    a.count[(int64_t)(NSL - 1) * a.sp + s] = 0;
-  } else {
-    a.bend[s] = -1;
+  const int alive = valid && reached == NSL ? 1 : 0;
+  const int64_t row = reserve_rows(&a.ccount[NSL - 1], alive);
+  if (alive) {
+    a.cstart[0][s] = (int32_t)row;
+    store_cand<TS, TP>(a.cpos[0], a.cmom[0], a.ccov[0], a.S, row, x, P);
+    a.cchi2[0][row] = chi2;
+    a.cmeta[0][row] = pack_meta(nh, 0, status);
+    a.cseed[0][row] = (int32_t)s;
   }
 }
 
@@ -329,33 +456,30 @@ __device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32
   return c1 < c2 || (c1 == c2 && (uint32_t)h1 < (uint32_t)h2);
 }
 
+// One lane per live candidate (dense row c of the current buffer).
 template <typename TS, typename TP>
 __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, int cur) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.S) return;
-  const int rank = (int)(t / a.sp);
-  const int64_t s = t - (int64_t)rank * a.sp;
-  if (s >= a.n_seeds) return;
-  const int nlive = a.count[(int64_t)(l - 1) * a.sp + s];
-  if (rank >= nlive) return;
-  const int64_t slot = t;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)a.ccount[l - 1]) return;
+  const int64_t s = a.cseed[cur][c];
   const int L = a.g.n_layers, NC = a.g.max_cands;
-  const int e = find_event(a.seed_off, a.n_events, s);
+  const int64_t S = a.S;
+  const int e = a.sev[s];
   TrackState<TP> x;
   TP P[21];
-  load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, slot, x, P);
-  const uint32_t meta = a.cmeta[cur][slot];
-  const double pchi2 = a.cchi2[cur][slot];
+  load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], S, c, x, P);
+  const uint32_t meta = a.cmeta[cur][c];
+  const double pchi2 = a.cchi2[cur][c];
   const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
   TrackState<TP> xp;
   Jac<TP> F;
   if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], false, xp, F)) {
-    a.rcount[slot] = -1;
+    a.rcount[c] = -1;
     return;
   }
   TP Pp[21];
   cov_propagate(P, F, Pp);
-  store_cand<TS, TP>(a.ppos, a.pmom, a.pcov, a.S, slot, xp, Pp);
+  store_cand<TS, TP>(a.ppos, a.pmom, a.pcov, S, c, xp, Pp);
 
   // search window: for any unit vector u, chi2 < cut implies
   // |u.d| < sqrt(cut u^T S u) (Cauchy-Schwarz in the S^-1 metric); with u
@@ -395,6 +519,7 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
   int nrec = 0;
   double* rchi = a.rchi;
   int32_t* rhit = a.rhit;
+  int32_t* rpos = a.rpos;
   for (int zb = zlo; zb <= zhi; ++zb) {
     // up to two contiguous runs of phi bins (wrap-around)
     int runs[2][2];
@@ -423,33 +548,34 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
         const double c2 = pchi2 + R.chi2;
         const int32_t hid = a.perm[hj];
         // insert into the sorted list of at most NC records
-        if (nrec == NC && !rec_less(c2, hid, rchi[(int64_t)(NC - 1) * a.S + slot],
-                                    rhit[(int64_t)(NC - 1) * a.S + slot]))
+        if (nrec == NC && !rec_less(c2, hid, rchi[(int64_t)(NC - 1) * S + c], rhit[(int64_t)(NC - 1) * S + c]))
           continue;
         int pos = nrec < NC ? nrec : NC - 1;
-        while (pos > 0 && rec_less(c2, hid, rchi[(int64_t)(pos - 1) * a.S + slot],
-                                   rhit[(int64_t)(pos - 1) * a.S + slot])) {
-          rchi[(int64_t)pos * a.S + slot] = rchi[(int64_t)(pos - 1) * a.S + slot];
-          rhit[(int64_t)pos * a.S + slot] = rhit[(int64_t)(pos - 1) * a.S + slot];
+        while (pos > 0 && rec_less(c2, hid, rchi[(int64_t)(pos - 1) * S + c], rhit[(int64_t)(pos - 1) * S + c])) {
+          rchi[(int64_t)pos * S + c] = rchi[(int64_t)(pos - 1) * S + c];
+          rhit[(int64_t)pos * S + c] = rhit[(int64_t)(pos - 1) * S + c];
+          rpos[(int64_t)pos * S + c] = rpos[(int64_t)(pos - 1) * S + c];
           --pos;
         }
-        rchi[(int64_t)pos * a.S + slot] = c2;
-        rhit[(int64_t)pos * a.S + slot] = hid;
+        rchi[(int64_t)pos * S + c] = c2;
+        rhit[(int64_t)pos * S + c] = hid;
+        rpos[(int64_t)pos * S + c] = (int32_t)hj;
         if (nrec < NC) ++nrec;
       }
     }
   }
   if (nrec == 0) {
     if (meta_nm(meta) < a.g.max_missed) {
-      rchi[slot] = pchi2;
-      rhit[slot] = -1;
+      rchi[c] = pchi2;
+      rhit[c] = -1;
+      rpos[c] = -1;
       nrec = 1;
     } else {
-      a.rcount[slot] = -2;
+      a.rcount[c] = -2;
       return;
     }
   }
-  a.rcount[slot] = nrec;
+  a.rcount[c] = nrec;
 }
 
 // ----------------------------------------------------------------- select
@@ -466,9 +592,9 @@ __device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, i
 // hit); the current head of every list sits in LDS (one column per lane, so
 // the dynamic parent index costs no registers) and the best head by the
 // ranking (more hits, lower chi2, lower parent, lower hit; missed layer
-// last) is taken max_cands times.  Parents that ended this layer compete
-// for the seed's best ended candidate.  Rows are rank-major, so lane s of a
-// wave reads consecutive seeds: coalesced.
+// last) is taken max_cands times.  The kept records become the seed's
+// children, placed in a contiguous range of the next buffer.  Parents that
+// ended this layer compete for the seed's best ended candidate.
 constexpr int kMergeThreads = 128;
 
 template <typename TS>
@@ -476,24 +602,26 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   __shared__ double hchi_s[KTF_MAX_CANDS][kMergeThreads];
   __shared__ int32_t hhit_s[KTF_MAX_CANDS][kMergeThreads];
   __shared__ int32_t info_s[KTF_MAX_CANDS][kMergeThreads];  // rc | head << 8 | nh << 16
+  __shared__ int32_t pick_s[KTF_MAX_CANDS][kMergeThreads];  // parent | record << 8
   const int tid = threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * kMergeThreads + tid;
-  if (s >= a.n_seeds) return;
   const int NC = a.g.max_cands;
   const int64_t sp = a.sp, S = a.S;
-  const int nlive = a.count[(int64_t)(l - 1) * sp + s];
+  const int nxt = cur ^ 1;
+  const int nlive = s < a.n_seeds ? a.count[(int64_t)(l - 1) * sp + s] : 0;
+  const int64_t pbase = nlive > 0 ? a.cstart[cur][s] : 0;
   int e_best = -1, e_nh = 0;
   double e_chi = 0.0;
   for (int r = 0; r < nlive; ++r) {
-    const int64_t slot = (int64_t)r * sp + s;
-    const int rc = a.rcount[slot];
-    const int nh = meta_nh(a.cmeta[cur][slot]);
+    const int64_t p = pbase + r;
+    const int rc = a.rcount[p];
+    const int nh = meta_nh(a.cmeta[cur][p]);
     info_s[r][tid] = (rc > 0 ? rc : 0) | (nh << 16);
     if (rc > 0) {
-      hchi_s[r][tid] = a.rchi[slot];
-      hhit_s[r][tid] = a.rhit[slot];
+      hchi_s[r][tid] = a.rchi[p];
+      hhit_s[r][tid] = a.rhit[p];
     } else {
-      const double c = a.cchi2[cur][slot];
+      const double c = a.cchi2[cur][p];
       if (e_best < 0 || nh > e_nh || (nh == e_nh && c < e_chi)) {
         e_best = r;
         e_nh = nh;
@@ -501,21 +629,21 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       }
     }
   }
-  if (e_best >= 0) {
+  if (e_best >= 0) {  // only for real seeds: nlive is 0 otherwise
     const int be = a.bend[s];
     if (be < 0 || final_less(e_nh, e_chi, l, e_best, meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s])) {
       // element-wise copy of the ended candidate (rare; keeps registers low)
-      const int64_t slot = (int64_t)e_best * sp + s;
-      for (int c = 0; c < 3; ++c) a.bpos[c * sp + s] = a.cpos[cur][c * S + slot];
+      const int64_t p = pbase + e_best;
+      for (int c = 0; c < 3; ++c) a.bpos[c * sp + s] = a.cpos[cur][c * S + p];
       const TS* mo = static_cast<const TS*>(a.cmom[cur]);
       const TS* co = static_cast<const TS*>(a.ccov[cur]);
       TS* bm = static_cast<TS*>(a.bmom);
       TS* bc = static_cast<TS*>(a.bcov);
-      for (int c = 0; c < 3; ++c) bm[c * sp + s] = mo[c * S + slot];
-      for (int c = 0; c < 21; ++c) bc[c * sp + s] = co[c * S + slot];
-      const uint32_t m = a.cmeta[cur][slot];
+      for (int c = 0; c < 3; ++c) bm[c * sp + s] = mo[c * S + p];
+      for (int c = 0; c < 21; ++c) bc[c * sp + s] = co[c * S + p];
+      const uint32_t m = a.cmeta[cur][p];
       a.bchi2[s] = e_chi;
-      a.bmeta[s] = pack_meta(e_nh, meta_nm(m), meta_st(m) | (a.rcount[slot] == -1 ? kNoReach : 0u));
+      a.bmeta[s] = pack_meta(e_nh, meta_nm(m), meta_st(m) | (a.rcount[p] == -1 ? kNoReach : 0u));
       a.bend[s] = l;
       a.brank[s] = e_best;
     }
@@ -539,63 +667,65 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     if (w < 0) break;
     const int info = info_s[w][tid];
     const int rc = info & 0xff, head = (info >> 8) & 0xff;
-    a.sel[(int64_t)k * sp + s] = w | (head << 8);
+    pick_s[k][tid] = w | (head << 8);
+    a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = w;
+    a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = hhit_s[w][tid];
     info_s[w][tid] = (info & ~0xff00) | ((head + 1) << 8);
     if (head + 1 < rc) {
-      const int64_t ri = (int64_t)(head + 1) * S + (int64_t)w * sp + s;
+      const int64_t ri = (int64_t)(head + 1) * S + pbase + w;
       hchi_s[w][tid] = a.rchi[ri];
       hhit_s[w][tid] = a.rhit[ri];
     }
     ++nsel;
   }
-  a.count[(int64_t)l * sp + s] = nsel;
+  const int64_t first = reserve_rows(&a.ccount[l], nsel);
+  if (s < a.n_seeds) {
+    a.count[(int64_t)l * sp + s] = nsel;
+    if (nsel > 0) a.cstart[nxt][s] = (int32_t)first;
+  }
+  for (int k = 0; k < nsel; ++k) {
+    const int pk = pick_s[k][tid];
+    a.sel_parent[first + k] = (int32_t)(pbase + (pk & 0xff));
+    a.sel_rec[first + k] = pk >> 8;
+    a.cseed[nxt][first + k] = (int32_t)s;
+  }
 }
 
-// One lane per child slot (rank-major): clone the selected record's parent
-// from its propagated state and apply the Kalman update with the record's
-// hit (a missed layer keeps the propagated state).
+// One lane per child (dense row of the next buffer): clone the selected
+// record's parent from its propagated state and apply the Kalman update with
+// the record's hit (a missed layer keeps the propagated state).
 template <typename TS, typename TP>
 __global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int cur) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.S) return;
-  const int64_t sp = a.sp, S = a.S;
-  const int k = (int)(t / sp);
-  const int64_t s = t - (int64_t)k * sp;
-  if (s >= a.n_seeds) return;
-  if (k >= a.count[(int64_t)l * sp + s]) return;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)a.ccount[l]) return;
   const int nxt = cur ^ 1;
-  const int L = a.g.n_layers, NC = a.g.max_cands;
-  const int32_t sel = a.sel[(int64_t)k * sp + s];
-  const int parent = sel & 0xff, rec = sel >> 8;
-  const int64_t ps = (int64_t)parent * sp + s;
-  const int32_t h = a.rhit[(int64_t)rec * S + ps];
-  const double c2 = a.rchi[(int64_t)rec * S + ps];
-  const uint32_t pm = a.cmeta[cur][ps];
+  const int64_t S = a.S;
+  const int64_t p = a.sel_parent[c];
+  const int rec = a.sel_rec[c];
+  const int32_t h = a.rhit[(int64_t)rec * S + p];
+  const double c2 = a.rchi[(int64_t)rec * S + p];
+  const uint32_t pm = a.cmeta[cur][p];
   TrackState<TP> xp;
   TP Pp[21];
-  load_cand<TS, TP>(a.ppos, a.pmom, a.pcov, S, ps, xp, Pp);
+  load_cand<TS, TP>(a.ppos, a.pmom, a.pcov, S, p, xp, Pp);
   int cnh = meta_nh(pm), cnm = meta_nm(pm);
-  const int64_t cs = (int64_t)k * sp + s;
   if (h >= 0) {
-    const int e = find_event(a.seed_off, a.n_events, s);
-    const int64_t hi = a.hit_off[e * L + l] + h;
-    const TS* hits = static_cast<const TS*>(a.hits);
-    const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
+    const int64_t hp = a.rpos[(int64_t)rec * S + p];
+    const TS* hb = static_cast<const TS*>(a.hb);
+    const double m[3] = {(double)hb[hp], (double)hb[a.n_hits + hp], (double)hb[2 * a.n_hits + hp]};
     Residual R;
     residual(xp, Pp, m, hit_res(a), R);  // scored positive definite already
     TrackState<TP> x;
     TP P[21];
     apply_update(xp, Pp, R, x, P);
-    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, cs, x, P);
+    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, c, x, P);
     ++cnh;
   } else {
-    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, cs, xp, Pp);
+    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, c, xp, Pp);
     ++cnm;
   }
-  a.cchi2[nxt][cs] = c2;
-  a.cmeta[nxt][cs] = pack_meta(cnh, cnm, meta_st(pm));
-  a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = parent;
-  a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = h;
+  a.cchi2[nxt][c] = c2;
+  a.cmeta[nxt][c] = pack_meta(cnh, cnm, meta_st(pm));
 }
 
 // ------------------------------------------------------------------ final
@@ -606,13 +736,13 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
   const int L = a.g.n_layers;
   const int NC = a.g.max_cands;
   const int nalive = a.count[(int64_t)(L - 1) * a.sp + s];
+  const int64_t base = nalive > 0 ? a.cstart[cur][s] : 0;
   int best_r = -1;
   int bnh = 0;
   double bc2 = 0.0;
   for (int r = 0; r < nalive; ++r) {
-    const int64_t slot = (int64_t)r * a.sp + s;
-    const int nh = meta_nh(a.cmeta[cur][slot]);
-    const double c2 = a.cchi2[cur][slot];
+    const int nh = meta_nh(a.cmeta[cur][base + r]);
+    const double c2 = a.cchi2[cur][base + r];
     if (best_r < 0 || final_less(nh, c2, L, r, bnh, bc2, L, best_r)) {
       best_r = r;
       bnh = nh;
@@ -637,10 +767,9 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
     meta = a.bmeta[s];
     c2 = a.bchi2[s];
   } else {
-    const int64_t slot = (int64_t)rank * a.sp + s;
-    load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, slot, x, P);
-    meta = a.cmeta[cur][slot];
-    c2 = a.cchi2[cur][slot];
+    load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, base + rank, x, P);
+    meta = a.cmeta[cur][base + rank];
+    c2 = a.cchi2[cur][base + rank];
   }
   // walk the (parent, hit) records back from the end layer
   for (int l = L - 1; l >= end_layer; --l) a.o_hit[(int64_t)l * a.sp + s] = -1;
@@ -676,7 +805,9 @@ template <typename TS, typename TP>
 static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) {
   const int bs = 256;
   const int64_t nbins_all = (int64_t)a.n_groups * a.n_bins;
-  if (nbins_all > 0) {
+  if (nbins_all > 0 && a.n_bins <= kLdsBins) {
+    hipLaunchKernelGGL((bin_group_kernel<TS>), dim3(a.n_groups), dim3(kBinThreads), 0, st, a);
+  } else if (nbins_all > 0) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nbins_all, bs)), dim3(bs), 0, st, a.bin_cur, nbins_all, 0);
     if (a.n_hits > 0)
       hipLaunchKernelGGL((bin_count_kernel<TS>), dim3(nblk(a.n_hits, bs)), dim3(bs), 0, st, a);
@@ -688,6 +819,9 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || bins_only || a.n_seeds == 0) return e;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t*>(a.ccount),
+                     (int64_t)a.g.n_layers, 0);
+  hipLaunchKernelGGL(seed_event_kernel, dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   hipLaunchKernelGGL((build_seed_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   int cur = 0;
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
@@ -720,6 +854,9 @@ static int validate_batch(ktf_ctx* c, const ktf_event_batch* ev) {
   const int64_t ns = ev->seed_off[ev->n_events];
   const int64_t nh = ev->hit_off[G];
   if (ev->seed_pitch < ns || ev->hit_pitch < nh) return fail(c, KTF_EINVAL, "ktf_build: pitch < size");
+  if (nh > INT32_MAX) return fail(c, KTF_EINVAL, "ktf_build: more than 2^31 hits in one batch");
+  if ((int64_t)c->cfg.max_cands * ev->seed_pitch > INT32_MAX)
+    return fail(c, KTF_EINVAL, "ktf_build: max_cands x seed_pitch exceeds 2^31 candidate slots");
   if (ns > 0 && (!ev->seed_state || !ev->seed_cov || !ev->charge || !ev->seed_hit))
     return fail(c, KTF_EINVAL, "ktf_build: null seed buffer");
   if (nh > 0 && !ev->hits) return fail(c, KTF_EINVAL, "ktf_build: null hits");
@@ -822,19 +959,19 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.pcov = p;
   }
   const int NC = cfg.max_cands;
-  if ((e = c->b_rec.ensure((size_t)S * (NC * 12 + 4 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
+  if ((e = c->b_rec.ensure((size_t)S * (NC * 16 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
   {
     char* p = static_cast<char*>(c->b_rec.p);
     a.rchi = reinterpret_cast<double*>(p);
     p += (size_t)S * NC * 8;
     a.rhit = reinterpret_cast<int32_t*>(p);
     p += (size_t)S * NC * 4;
+    a.rpos = reinterpret_cast<int32_t*>(p);
+    p += (size_t)S * NC * 4;
     a.rcount = reinterpret_cast<int32_t*>(p);
-    p += (size_t)S * 4;
-    a.sel = reinterpret_cast<int32_t*>(p);
   }
   const int64_t sp = std::max<int64_t>(a.sp, 1);
-  if ((e = c->b_best.ensure((size_t)sp * (3 * 8 + 24 * ts + 8 + 4 + 4 + 4))) != hipSuccess)
+  if ((e = c->b_best.ensure((size_t)sp * (3 * 8 + 24 * ts + 8 + 4 + 4 + 4 + 4))) != hipSuccess)
     return hip_fail(c, e, "workspace");
   {
     char* p = static_cast<char*>(c->b_best.p);
@@ -851,6 +988,20 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.bend = reinterpret_cast<int32_t*>(p);
     p += (size_t)sp * 4;
     a.brank = reinterpret_cast<int32_t*>(p);
+    p += (size_t)sp * 4;
+    a.sev = reinterpret_cast<int32_t*>(p);
+  }
+  if ((e = c->b_list.ensure((size_t)S * 4 * 4 + (size_t)sp * 2 * 4 + 64 * 4)) != hipSuccess)
+    return hip_fail(c, e, "list workspace");
+  {
+    int32_t* p = static_cast<int32_t*>(c->b_list.p);
+    a.cseed[0] = p;
+    a.cseed[1] = p + S;
+    a.sel_parent = p + 2 * S;
+    a.sel_rec = p + 3 * S;
+    a.cstart[0] = p + 4 * S;
+    a.cstart[1] = p + 4 * S + sp;
+    a.ccount = reinterpret_cast<unsigned*>(p + 4 * S + 2 * sp);
   }
   return KTF_OK;
 }
