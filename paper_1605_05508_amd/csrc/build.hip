@@ -597,12 +597,23 @@ __device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, i
 // ended this layer compete for the seed's best ended candidate.
 constexpr int kMergeThreads = 128;
 
+// LDS per lane and kept candidate: head chi2 (8), head hit (4), list info
+// (4: rc | head << 8 | nh << 16), pick (4: parent | record << 8); sized at
+// launch for max_cands so that small beams get more resident waves.
+constexpr int kMergeLdsPerCand = 20;
+
 template <typename TS>
 __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a, int l, int cur) {
-  __shared__ double hchi_s[KTF_MAX_CANDS][kMergeThreads];
-  __shared__ int32_t hhit_s[KTF_MAX_CANDS][kMergeThreads];
-  __shared__ int32_t info_s[KTF_MAX_CANDS][kMergeThreads];  // rc | head << 8 | nh << 16
-  __shared__ int32_t pick_s[KTF_MAX_CANDS][kMergeThreads];  // parent | record << 8
+  extern __shared__ char merge_lds[];
+  const int NCs = a.g.max_cands;
+  double* hchi_b = reinterpret_cast<double*>(merge_lds);
+  int32_t* hhit_b = reinterpret_cast<int32_t*>(hchi_b + NCs * kMergeThreads);
+  int32_t* info_b = hhit_b + NCs * kMergeThreads;
+  int32_t* pick_b = info_b + NCs * kMergeThreads;
+#define hchi_s(r) hchi_b[(r) * kMergeThreads + tid]
+#define hhit_s(r) hhit_b[(r) * kMergeThreads + tid]
+#define info_s(r) info_b[(r) * kMergeThreads + tid]
+#define pick_s(r) pick_b[(r) * kMergeThreads + tid]
   const int tid = threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * kMergeThreads + tid;
   const int NC = a.g.max_cands;
@@ -616,10 +627,10 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     const int64_t p = pbase + r;
     const int rc = a.rcount[p];
     const int nh = meta_nh(a.cmeta[cur][p]);
-    info_s[r][tid] = (rc > 0 ? rc : 0) | (nh << 16);
+    info_s(r) = (rc > 0 ? rc : 0) | (nh << 16);
     if (rc > 0) {
-      hchi_s[r][tid] = a.rchi[p];
-      hhit_s[r][tid] = a.rhit[p];
+      hchi_s(r) = a.rchi[p];
+      hhit_s(r) = a.rhit[p];
     } else {
       const double c = a.cchi2[cur][p];
       if (e_best < 0 || nh > e_nh || (nh == e_nh && c < e_chi)) {
@@ -653,11 +664,11 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     int w = -1, wnh = 0;
     double wchi = 0.0;
     for (int r = 0; r < nlive; ++r) {
-      const int info = info_s[r][tid];
+      const int info = info_s(r);
       const int rc = info & 0xff, head = (info >> 8) & 0xff;
       if (head >= rc) continue;
-      const int knh = (info >> 16) + (hhit_s[r][tid] >= 0 ? 1 : 0);
-      const double c = hchi_s[r][tid];
+      const int knh = (info >> 16) + (hhit_s(r) >= 0 ? 1 : 0);
+      const double c = hchi_s(r);
       if (w < 0 || knh > wnh || (knh == wnh && c < wchi)) {
         w = r;
         wnh = knh;
@@ -665,16 +676,16 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       }
     }
     if (w < 0) break;
-    const int info = info_s[w][tid];
+    const int info = info_s(w);
     const int rc = info & 0xff, head = (info >> 8) & 0xff;
-    pick_s[k][tid] = w | (head << 8);
+    pick_s(k) = w | (head << 8);
     a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = w;
-    a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = hhit_s[w][tid];
-    info_s[w][tid] = (info & ~0xff00) | ((head + 1) << 8);
+    a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = hhit_s(w);
+    info_s(w) = (info & ~0xff00) | ((head + 1) << 8);
     if (head + 1 < rc) {
       const int64_t ri = (int64_t)(head + 1) * S + pbase + w;
-      hchi_s[w][tid] = a.rchi[ri];
-      hhit_s[w][tid] = a.rhit[ri];
+      hchi_s(w) = a.rchi[ri];
+      hhit_s(w) = a.rhit[ri];
     }
     ++nsel;
   }
@@ -684,11 +695,15 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     if (nsel > 0) a.cstart[nxt][s] = (int32_t)first;
   }
   for (int k = 0; k < nsel; ++k) {
-    const int pk = pick_s[k][tid];
+    const int pk = pick_s(k);
     a.sel_parent[first + k] = (int32_t)(pbase + (pk & 0xff));
     a.sel_rec[first + k] = pk >> 8;
     a.cseed[nxt][first + k] = (int32_t)s;
   }
+#undef hchi_s
+#undef hhit_s
+#undef info_s
+#undef pick_s
 }
 
 // One lane per child (dense row of the next buffer): clone the selected
@@ -826,8 +841,8 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   int cur = 0;
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     hipLaunchKernelGGL((build_score_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
-    hipLaunchKernelGGL((build_merge_kernel<TS>), dim3(nblk(a.n_seeds, kMergeThreads)), dim3(kMergeThreads), 0,
-                       st, a, l, cur);
+    hipLaunchKernelGGL((build_merge_kernel<TS>), dim3(nblk(a.n_seeds, kMergeThreads)), dim3(kMergeThreads),
+                       (size_t)a.g.max_cands * kMergeThreads * kMergeLdsPerCand, st, a, l, cur);
     hipLaunchKernelGGL((build_clone_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
     cur ^= 1;
   }
@@ -1038,9 +1053,12 @@ int build_impl(ktf_ctx* c, const ktf_event_batch* ev, ktf_build_out* out, hipStr
       return hip_fail(c, e, "count workspace");
     a.count = static_cast<int32_t*>(c->b_misc.p);
   }
-  // (parent, hit) records start as "none" so that unused ranks read -1
-  const int64_t nh = (int64_t)L * NC * 2 * sp;
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nh, 256)), dim3(256), 0, st, a.hist, nh, -1);
+  // the caller's copy of the (parent, hit) records reads -1 for unused
+  // ranks; the internal one is only ever read along written paths
+  if (out->cand_hist) {
+    const int64_t nh = (int64_t)L * NC * 2 * sp;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nh, 256)), dim3(256), 0, st, a.hist, nh, -1);
+  }
   hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk((int64_t)L * sp, 256)), dim3(256), 0, st, a.count,
                      (int64_t)L * sp, 0);
   a.o_hit = out->hit_idx;
