@@ -34,8 +34,8 @@ namespace ktf {
 constexpr double kPi = 3.14159265358979323846;
 
 template <typename T> struct BuildNewton;
-template <> struct BuildNewton<double> { static constexpr int n = 4; };
-template <> struct BuildNewton<float> { static constexpr int n = 3; };
+template <> struct BuildNewton<double> { static constexpr int n = 3; };
+template <> struct BuildNewton<float> { static constexpr int n = 2; };
 
 struct BuildArgs {
   BuildGeom g;

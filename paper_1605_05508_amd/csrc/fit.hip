@@ -21,8 +21,8 @@
 namespace ktf {
 
 template <typename T> struct NewtonIters;
-template <> struct NewtonIters<double> { static constexpr int n = 4; };
-template <> struct NewtonIters<float> { static constexpr int n = 3; };
+template <> struct NewtonIters<double> { static constexpr int n = 3; };
+template <> struct NewtonIters<float> { static constexpr int n = 2; };
 
 // Storage type TS, propagation type TP.
 template <typename TS, typename TP>

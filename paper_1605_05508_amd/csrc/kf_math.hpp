@@ -36,8 +36,22 @@ KTF_HD constexpr int pidx(int i, int j) {  // packed index, i <= j
 }
 KTF_HD constexpr int sidx(int i, int j) { return i <= j ? pidx(i, j) : pidx(j, i); }
 
+// double reciprocal: hardware estimate refined by two Newton-Raphson steps
+// (each doubles the correct bits), in place of the IEEE division sequence
+KTF_HD double rcp_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
 template <typename T> KTF_HD T rcp(T x);
-template <> KTF_HD double rcp<double>(double x) { return 1.0 / x; }
+template <> KTF_HD double rcp<double>(double x) { return rcp_nr(x); }
 template <> KTF_HD float rcp<float>(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rcpf(x);  // 1 ulp
@@ -60,6 +74,10 @@ template <> KTF_HD void ksincos<float>(float x, float* s, float* c) { sincosf(x,
 // Small angles use the Maclaurin series (no cancellation, no division);
 // larger ones the trigonometric forms.
 // ---------------------------------------------------------------------------
+template <typename T> struct NewtonTol;
+template <> struct NewtonTol<float> { static constexpr float v = 1e-6f; };
+template <> struct NewtonTol<double> { static constexpr double v = 1e-13; };
+
 template <typename T> struct SeriesLen;
 template <> struct SeriesLen<float> { static constexpr int n = 5; };
 template <> struct SeriesLen<double> { static constexpr int n = 9; };
@@ -211,15 +229,24 @@ KTF_HD bool propagate(const TrackState<T>& x, T k, double r, bool nearest, Track
     s = (nearest && ((s2 < T(0) ? -s2 : s2) < (s1 < T(0) ? -s1 : s1))) ? s2 : s1;
   }
   Transported<T> t;
-#pragma unroll
-  for (int it = 0; it < NITER; ++it) {
+  T ds = T(0);
+  auto newton_step = [&]() {
     transport(x, k, ipt, s, t);
     const double dx = (double)t.d[0], dy = (double)t.d[1];
     const double g = c0 + (2.0 * x.pos[0] + dx) * dx + (2.0 * x.pos[1] + dy) * dy;
     const T xe = (T)(x.pos[0] + dx), ye = (T)(x.pos[1] + dy);
     const T gp = T(2) * (xe * t.mom[0] + ye * t.mom[1]) * ipt;
-    s = s - (T)g * rcp(gp);
-  }
+    ds = (T)g * rcp(gp);
+    s = s - ds;
+  };
+#pragma unroll
+  for (int it = 0; it < NITER; ++it) newton_step();
+  // Newton converges quadratically from the straight-line root; a long or
+  // strongly curved step may need more: continue while the last step was
+  // still above the storage precision (rarely taken)
+  const T tol = NewtonTol<T>::v * (T(1) + (s < T(0) ? -s : s));
+#pragma unroll 1
+  for (int it = 0; it < 3 && (ds < T(0) ? -ds : ds) > tol; ++it) newton_step();
   transport(x, k, ipt, s, t);
   ok = ok && (nearest || s > T(0));
 #pragma unroll
@@ -346,7 +373,7 @@ template <typename T>
 KTF_HD bool residual(const TrackState<T>& xp, const T Pp[21], const double m[3],
                      const HitRes& hr, Residual& o) {
   const double rho2 = m[0] * m[0] + m[1] * m[1];
-  const double irho2 = 1.0 / rho2;
+  const double irho2 = rcp_nr(rho2);
   const double xx = m[0] * m[0] * irho2, yy = m[1] * m[1] * irho2, xy = m[0] * m[1] * irho2;
   const double V00 = hr.sr2 * xx + hr.srphi2 * yy;
   const double V01 = (hr.sr2 - hr.srphi2) * xy;
@@ -366,7 +393,7 @@ KTF_HD bool residual(const TrackState<T>& xp, const T Pp[21], const double m[3],
   const double c22 = S00 * S11 - S01 * S01;
   const double det = S00 * c00 + S01 * c01 + S02 * c02;
   const bool pd = S00 > 0.0 && c22 > 0.0 && det > 0.0;
-  const double idet = 1.0 / det;
+  const double idet = rcp_nr(det);
   o.Si[0] = c00 * idet; o.Si[1] = c01 * idet; o.Si[2] = c02 * idet;
   o.Si[3] = c11 * idet; o.Si[4] = c12 * idet; o.Si[5] = c22 * idet;
   const double Sr0 = o.Si[0] * o.r[0] + o.Si[1] * o.r[1] + o.Si[2] * o.r[2];
