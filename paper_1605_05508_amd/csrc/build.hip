@@ -9,18 +9,18 @@
 //           bins inside a window that no compatible hit can lie outside of,
 //           keep the candidate's best records (a bookkeeping list) -- no
 //           candidate is copied here;
-//   merge   one lane per seed: merge the candidates' sorted record lists to
-//           the best max_cands by the ranking (more hits, lower chi2, lower
+//   merge   a lane group per seed: merge the candidates' sorted record
+//           lists to the best max_cands by the ranking (more hits, lower chi2, lower
 //           parent rank, lower hit index, a missed layer last);
 //   clone   one lane per selected record: clone its parent's propagated
 //           state and apply the Kalman update with the record's hit;
 //   final   one lane per seed: the best survivor or ended candidate, hit
 //           indices recovered by walking the per-layer (parent, hit) records.
 //
-// Layout: candidate slots are rank-major (slot = rank * seed_pitch + seed)
-// so waves of high ranks, mostly empty, retire at once; every per-slot
-// field is its own structure-of-arrays row.  Positions are kept in double,
-// momentum and covariance in the storage precision.
+// Layout: candidates live in dense rows (one structure-of-arrays row per
+// field), split into 64 regions with a row counter each; a seed's candidates
+// are contiguous and in rank order.  Positions are kept in double, momentum
+// and covariance in the storage precision.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,6 +33,13 @@ namespace ktf {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// Candidate rows are split into kRegions regions of RS rows, each with its
+// own row counter (kCtrStride ints apart, one 128-byte line each), so that
+// row reservations spread over many addresses: same-address atomics
+// serialise in the memory system.
+constexpr int kRegions = 64;
+constexpr int kCtrStride = 32;
+
 template <typename T> struct BuildNewton;
 template <> struct BuildNewton<double> { static constexpr int n = 3; };
 template <> struct BuildNewton<float> { static constexpr int n = 2; };
@@ -43,7 +50,8 @@ struct BuildArgs {
   int32_t n_groups;        // n_events * n_layers
   int32_t n_bins;          // n_zbins * n_phibins
   int64_t n_seeds, sp;     // seeds, seed pitch
-  int64_t S;               // candidate slots = max_cands * sp
+  int64_t S;               // candidate rows = kRegions * RS
+  int64_t RS;              // rows per region
   int64_t n_hits;          // total hits
   int64_t hp;              // hit pitch
   const int64_t* seed_off; // device [n_events+1]
@@ -64,7 +72,7 @@ struct BuildArgs {
   int32_t* cstart[2];      // [sp]: first dense row of each seed's candidates
   int32_t* sel_parent;     // [S]: per child row, its parent's row
   int32_t* sel_rec;        // [S]: per child row, the parent's record it takes
-  unsigned* ccount;        // [n_layers]: number of candidate rows after each layer
+  unsigned* ccount;        // [n_layers][kRegions][kCtrStride]: rows used per region after each layer
   void* hb;                // [3][n_hits]: binned coordinates
   // candidates (double buffered), propagated parents, records
   double* cpos[2];
@@ -350,23 +358,47 @@ __device__ __forceinline__ HitRes hit_res(const BuildArgs& a) {
 // contiguous (cstart[s] .. cstart[s] + count - 1, in rank order), and every
 // per-candidate field is its own row.  So neighbouring lanes always touch
 // neighbouring rows, whatever the rank.  Rows are reserved with one atomic
-// per wave (a wave prefix sum of the lanes' counts; lane 63 reserves the
-// wave's range).  The placement of a seed's range depends on scheduling; the
-// per-seed arithmetic and results do not.  Every lane of the wave must call
-// this; returns the lane's first row.
-__device__ __forceinline__ int64_t reserve_rows(unsigned* counter, int n) {
-  const int lane = threadIdx.x & 63;
+// per block (a block prefix sum of the threads' counts; same-address atomics
+// serialise in L2, so a batch of many seeds wants as few of them as
+// possible).  The placement of a seed's range depends on scheduling; the
+// per-seed arithmetic and results do not.  Every thread of the block calls
+// this; wtot is LDS scratch of (blockDim / 64 + 1) ints.  Returns the
+// thread's first row.
+__device__ __forceinline__ int64_t block_reserve(unsigned* counter, int n, int* wtot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int x = n;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const int y = __shfl_up(x, d, 64);
     if (lane >= d) x += y;
   }
-  const int total = __shfl(x, 63, 64);
-  unsigned base = 0;
-  if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned)total);
-  base = __shfl(base, 63, 64);
-  return (int64_t)base + (x - n);
+  if (lane == 63) wtot[wave] = x;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int t = wtot[w];
+    before += w < wave ? t : 0;
+    total += t;
+  }
+  if (threadIdx.x == 0) wtot[nw] = total > 0 ? (int)atomicAdd(counter, (unsigned)total) : 0;
+  __syncthreads();
+  return (int64_t)(unsigned)wtot[nw] + before + (x - n);
+}
+
+__device__ __forceinline__ unsigned* region_ctr(const BuildArgs& a, int l, int r) {
+  return a.ccount + ((int64_t)l * kRegions + r) * kCtrStride;
+}
+
+// Row of this thread for a launch of S / blockDim blocks over the rows
+// (RS a multiple of blockDim): consecutive blocks take the same chunk of
+// consecutive regions, so the rows in flight together belong to seeds close
+// in index (same events, same bins in cache).  Returns whether the row holds
+// a live candidate after layer l.
+__device__ __forceinline__ bool block_row(const BuildArgs& a, int l, int64_t& c) {
+  const int r = (int)(blockIdx.x % kRegions);
+  const int64_t local = (int64_t)(blockIdx.x / kRegions) * blockDim.x + threadIdx.x;
+  c = r * a.RS + local;
+  return local < (int64_t)*region_ctr(a, l, r);
 }
 
 // seed phase: fit each seed over the seed layers with its own hits
@@ -439,8 +471,10 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
       a.bend[s] = -1;
     }
   }
+  __shared__ int wtot[256 / 64 + 1];
   const int alive = valid && reached == NSL ? 1 : 0;
-  const int64_t row = reserve_rows(&a.ccount[NSL - 1], alive);
+  const int reg = blockIdx.x & (kRegions - 1);
+  const int64_t row = reg * a.RS + block_reserve(region_ctr(a, NSL - 1, reg), alive, wtot);
   if (alive) {
     a.cstart[0][s] = (int32_t)row;
     store_cand<TS, TP>(a.cpos[0], a.cmom[0], a.ccov[0], a.S, row, x, P);
@@ -459,8 +493,8 @@ __device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32
 // One lane per live candidate (dense row c of the current buffer).
 template <typename TS, typename TP>
 __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, int cur) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (int64_t)a.ccount[l - 1]) return;
+  int64_t c;
+  if (!block_row(a, l - 1, c)) return;
   const int64_t s = a.cseed[cur][c];
   const int L = a.g.n_layers, NC = a.g.max_cands;
   const int64_t S = a.S;
@@ -588,122 +622,199 @@ __device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, i
   return r1 < r2;
 }
 
-// One lane per seed.  The parents' record lists are each sorted by (chi2,
-// hit); the current head of every list sits in LDS (one column per lane, so
-// the dynamic parent index costs no registers) and the best head by the
-// ranking (more hits, lower chi2, lower parent, lower hit; missed layer
-// last) is taken max_cands times.  The kept records become the seed's
-// children, placed in a contiguous range of the next buffer.  Parents that
-// ended this layer compete for the seed's best ended candidate.
-constexpr int kMergeThreads = 128;
+// Four lanes per seed (a quad): lane q owns the seed's parents q, q + 4, ...
+// (PPL = ceil(max_cands / 4) slots) and holds each one's record-list head
+// (chi2, hit) in registers, with the next three records prefetched in the
+// same pass of independent loads.  The max_cands best heads by the ranking
+// (more hits, lower chi2, lower parent, lower hit; a missed layer counts no
+// hit) are taken one at a time: each lane's best slot, then the quad's best
+// by two DPP exchanges, so the dependent chain per pick stays in registers.
+// Parents that ended this layer compete for the seed's best ended candidate
+// the same way.  The kept records become the seed's children: contiguous
+// rows of the next buffer, in pick order, reserved for the whole block at
+// once.
+constexpr int kMergeThreads = 256;
+constexpr int kMergeSeeds = kMergeThreads / 4;
 
-// LDS per lane and kept candidate: head chi2 (8), head hit (4), list info
-// (4: rc | head << 8 | nh << 16), pick (4: parent | record << 8); sized at
-// launch for max_cands so that small beams get more resident waves.
-constexpr int kMergeLdsPerCand = 20;
+// a record-list head as ranked by the merge: key = 0 for none, else the hit
+// count it gives plus one; pj = parent << 8 | record
+struct MHead {
+  int key;
+  double c;
+  int pj;
+  int hit;
+};
 
-template <typename TS>
+__device__ __forceinline__ bool mhead_better(const MHead& x, const MHead& y) {
+  return x.key > y.key || (x.key == y.key && (x.c < y.c || (x.c == y.c && (x.pj >> 8) < (y.pj >> 8))));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+// best of the quad; every lane ends with the same head (a strict total
+// order: parents are distinct)
+__device__ __forceinline__ void quad_best(MHead& h) {
+  {
+    const int64_t cb = __double_as_longlong(h.c);
+    MHead o{dpp_i<0xB1>(h.key), __longlong_as_double(((int64_t)dpp_i<0xB1>((int)(cb >> 32)) << 32) |
+                                                     (uint32_t)dpp_i<0xB1>((int)cb)),
+            dpp_i<0xB1>(h.pj), dpp_i<0xB1>(h.hit)};  // lanes q ^ 1
+    if (mhead_better(o, h)) h = o;
+  }
+  {
+    const int64_t cb = __double_as_longlong(h.c);
+    MHead o{dpp_i<0x4E>(h.key), __longlong_as_double(((int64_t)dpp_i<0x4E>((int)(cb >> 32)) << 32) |
+                                                     (uint32_t)dpp_i<0x4E>((int)cb)),
+            dpp_i<0x4E>(h.pj), dpp_i<0x4E>(h.hit)};  // lanes q ^ 2
+    if (mhead_better(o, h)) h = o;
+  }
+}
+
+template <typename TS, int PPL>
 __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a, int l, int cur) {
-  extern __shared__ char merge_lds[];
-  const int NCs = a.g.max_cands;
-  double* hchi_b = reinterpret_cast<double*>(merge_lds);
-  int32_t* hhit_b = reinterpret_cast<int32_t*>(hchi_b + NCs * kMergeThreads);
-  int32_t* info_b = hhit_b + NCs * kMergeThreads;
-  int32_t* pick_b = info_b + NCs * kMergeThreads;
-#define hchi_s(r) hchi_b[(r) * kMergeThreads + tid]
-#define hhit_s(r) hhit_b[(r) * kMergeThreads + tid]
-#define info_s(r) info_b[(r) * kMergeThreads + tid]
-#define pick_s(r) pick_b[(r) * kMergeThreads + tid]
-  const int tid = threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * kMergeThreads + tid;
+  __shared__ int wtot[kMergeThreads / 64 + 1];
+  __shared__ int pick_s[kMergeSeeds][4 * PPL];  // parent | record << 8
+  __shared__ int phit_s[kMergeSeeds][4 * PPL];
   const int NC = a.g.max_cands;
+  const int tid = threadIdx.x;
+  const int q = tid & 3, ls = tid >> 2;
   const int64_t sp = a.sp, S = a.S;
-  const int nxt = cur ^ 1;
-  const int nlive = s < a.n_seeds ? a.count[(int64_t)(l - 1) * sp + s] : 0;
-  const int64_t pbase = nlive > 0 ? a.cstart[cur][s] : 0;
-  int e_best = -1, e_nh = 0;
-  double e_chi = 0.0;
-  for (int r = 0; r < nlive; ++r) {
-    const int64_t p = pbase + r;
-    const int rc = a.rcount[p];
-    const int nh = meta_nh(a.cmeta[cur][p]);
-    info_s(r) = (rc > 0 ? rc : 0) | (nh << 16);
-    if (rc > 0) {
-      hchi_s(r) = a.rchi[p];
-      hhit_s(r) = a.rhit[p];
+  const int64_t s = (int64_t)blockIdx.x * kMergeSeeds + ls;
+  const bool real = s < a.n_seeds;
+  int nlive = 0;
+  int64_t pbase = 0;
+  if (real) {  // cstart is only meaningful for a seed with candidates
+    nlive = a.count[(int64_t)(l - 1) * sp + s];
+    pbase = a.cstart[cur][s];
+  }
+  int rc[PPL], nh[PPL], hd[PPL], hh[PPL], pre_h[PPL][3];
+  double pchi[PPL], hc[PPL], pre_c[PPL][3];
+#pragma unroll
+  for (int u = 0; u < PPL; ++u) {
+    const int j = q + 4 * u;
+    const int64_t p = pbase + j;
+    rc[u] = 0;
+    nh[u] = 0;
+    hd[u] = 0;
+    pchi[u] = 0.0;
+    hc[u] = 0.0;
+    hh[u] = -1;
+    if (j < nlive) {  // record 0 is read with the count and used only if rc > 0
+      rc[u] = a.rcount[p];
+      nh[u] = meta_nh(a.cmeta[cur][p]);
+      pchi[u] = a.cchi2[cur][p];
+      hc[u] = a.rchi[p];
+      hh[u] = a.rhit[p];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PPL; ++u) {
+    const int64_t p = pbase + q + 4 * u;
+    if (rc[u] > 1) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const int64_t ri = (int64_t)min(v + 1, rc[u] - 1) * S + p;
+        pre_c[u][v] = a.rchi[ri];
+        pre_h[u][v] = a.rhit[ri];
+      }
     } else {
-      const double c = a.cchi2[cur][p];
-      if (e_best < 0 || nh > e_nh || (nh == e_nh && c < e_chi)) {
-        e_best = r;
-        e_nh = nh;
-        e_chi = c;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        pre_c[u][v] = 0.0;
+        pre_h[u][v] = -1;
       }
     }
   }
-  if (e_best >= 0) {  // only for real seeds: nlive is 0 otherwise
+  // best ended parent (quad-uniform result)
+  MHead eb{0, 0.0, 0, 0};
+#pragma unroll
+  for (int u = 0; u < PPL; ++u) {
+    const int j = q + 4 * u;
+    const MHead h{(j < nlive && rc[u] <= 0) ? nh[u] + 1 : 0, pchi[u], j << 8, 0};
+    if (u == 0 || mhead_better(h, eb)) eb = h;
+  }
+  quad_best(eb);
+  if (eb.key > 0) {
+    const int e_nh = eb.key - 1, ej = eb.pj >> 8;
     const int be = a.bend[s];
-    if (be < 0 || final_less(e_nh, e_chi, l, e_best, meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s])) {
-      // element-wise copy of the ended candidate (rare; keeps registers low)
-      const int64_t p = pbase + e_best;
-      for (int c = 0; c < 3; ++c) a.bpos[c * sp + s] = a.cpos[cur][c * S + p];
+    if (be < 0 || final_less(e_nh, eb.c, l, ej, meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s])) {
+      // the quad copies the ended candidate element by element
+      const int64_t pe = pbase + ej;
       const TS* mo = static_cast<const TS*>(a.cmom[cur]);
       const TS* co = static_cast<const TS*>(a.ccov[cur]);
       TS* bm = static_cast<TS*>(a.bmom);
       TS* bc = static_cast<TS*>(a.bcov);
-      for (int c = 0; c < 3; ++c) bm[c * sp + s] = mo[c * S + p];
-      for (int c = 0; c < 21; ++c) bc[c * sp + s] = co[c * S + p];
-      const uint32_t m = a.cmeta[cur][p];
-      a.bchi2[s] = e_chi;
-      a.bmeta[s] = pack_meta(e_nh, meta_nm(m), meta_st(m) | (a.rcount[p] == -1 ? kNoReach : 0u));
-      a.bend[s] = l;
-      a.brank[s] = e_best;
-    }
-  }
-  int nsel = 0;
-  for (int k = 0; k < NC; ++k) {
-    int w = -1, wnh = 0;
-    double wchi = 0.0;
-    for (int r = 0; r < nlive; ++r) {
-      const int info = info_s(r);
-      const int rc = info & 0xff, head = (info >> 8) & 0xff;
-      if (head >= rc) continue;
-      const int knh = (info >> 16) + (hhit_s(r) >= 0 ? 1 : 0);
-      const double c = hchi_s(r);
-      if (w < 0 || knh > wnh || (knh == wnh && c < wchi)) {
-        w = r;
-        wnh = knh;
-        wchi = c;
+      for (int e = q; e < 27; e += 4) {
+        if (e < 3)
+          a.bpos[e * sp + s] = a.cpos[cur][e * S + pe];
+        else if (e < 6)
+          bm[(e - 3) * sp + s] = mo[(e - 3) * S + pe];
+        else
+          bc[(e - 6) * sp + s] = co[(e - 6) * S + pe];
+      }
+      if (q == 0) {
+        const uint32_t m = a.cmeta[cur][pe];
+        a.bchi2[s] = eb.c;
+        a.bmeta[s] = pack_meta(e_nh, meta_nm(m), meta_st(m) | (a.rcount[pe] == -1 ? kNoReach : 0u));
+        a.bend[s] = l;
+        a.brank[s] = ej;
       }
     }
-    if (w < 0) break;
-    const int info = info_s(w);
-    const int rc = info & 0xff, head = (info >> 8) & 0xff;
-    pick_s(k) = w | (head << 8);
-    a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = w;
-    a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = hhit_s(w);
-    info_s(w) = (info & ~0xff00) | ((head + 1) << 8);
-    if (head + 1 < rc) {
-      const int64_t ri = (int64_t)(head + 1) * S + pbase + w;
-      hchi_s(w) = a.rchi[ri];
-      hhit_s(w) = a.rhit[ri];
+  }
+  // k-way merge of the parents' lists
+  int nsel = 0;
+  for (int k = 0; k < NC; ++k) {
+    MHead w{0, 0.0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+      const MHead h{hd[u] < rc[u] ? nh[u] + (hh[u] >= 0 ? 1 : 0) + 1 : 0, hc[u], ((q + 4 * u) << 8) | hd[u],
+                    hh[u]};
+      if (u == 0 || mhead_better(h, w)) w = h;
+    }
+    quad_best(w);
+    if (w.key == 0) break;  // quad-uniform
+    if (q == 0) {
+      pick_s[ls][k] = w.pj;
+      phit_s[ls][k] = w.hit;
+    }
+    const int wj = w.pj >> 8;
+    if ((wj & 3) == q) {  // the owner lane advances that parent's head
+#pragma unroll
+      for (int u = 0; u < PPL; ++u) {
+        if ((wj >> 2) == u) {
+          const int nx = ++hd[u];
+          if (nx < rc[u]) {
+            if (nx < 4) {
+              hc[u] = nx == 1 ? pre_c[u][0] : nx == 2 ? pre_c[u][1] : pre_c[u][2];
+              hh[u] = nx == 1 ? pre_h[u][0] : nx == 2 ? pre_h[u][1] : pre_h[u][2];
+            } else {
+              hc[u] = a.rchi[(int64_t)nx * S + pbase + wj];
+              hh[u] = a.rhit[(int64_t)nx * S + pbase + wj];
+            }
+          }
+        }
+      }
     }
     ++nsel;
   }
-  const int64_t first = reserve_rows(&a.ccount[l], nsel);
-  if (s < a.n_seeds) {
+  const int reg = blockIdx.x & (kRegions - 1);
+  const int local = (int)block_reserve(region_ctr(a, l, reg), q == 0 ? nsel : 0, wtot);
+  const int64_t first = reg * a.RS + dpp_i<0x00>(local);  // lane 0 of the quad
+  if (real && q == 0) {
     a.count[(int64_t)l * sp + s] = nsel;
-    if (nsel > 0) a.cstart[nxt][s] = (int32_t)first;
+    if (nsel > 0) a.cstart[cur ^ 1][s] = (int32_t)first;
   }
-  for (int k = 0; k < nsel; ++k) {
-    const int pk = pick_s(k);
-    a.sel_parent[first + k] = (int32_t)(pbase + (pk & 0xff));
-    a.sel_rec[first + k] = pk >> 8;
-    a.cseed[nxt][first + k] = (int32_t)s;
+  for (int k = q; k < nsel; k += 4) {
+    const int pk = pick_s[ls][k];
+    a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = pk >> 8;
+    a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = phit_s[ls][k];
+    a.sel_parent[first + k] = (int32_t)(pbase + (pk >> 8));
+    a.sel_rec[first + k] = pk & 0xff;
+    a.cseed[cur ^ 1][first + k] = (int32_t)s;
   }
-#undef hchi_s
-#undef hhit_s
-#undef info_s
-#undef pick_s
 }
 
 // One lane per child (dense row of the next buffer): clone the selected
@@ -711,8 +822,8 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
 // the record's hit (a missed layer keeps the propagated state).
 template <typename TS, typename TP>
 __global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int cur) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (int64_t)a.ccount[l]) return;
+  int64_t c;
+  if (!block_row(a, l, c)) return;
   const int nxt = cur ^ 1;
   const int64_t S = a.S;
   const int64_t p = a.sel_parent[c];
@@ -816,6 +927,32 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
 // -------------------------------------------------------------- host side
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Rows per region: enough for the blocks that reserve in one region (blocks
+// go to regions round robin), for the seed kernel (256 seeds of one row
+// each per block) and for the merge (kMergeSeeds seeds of up to max_cands
+// rows each per block); a multiple of 256 rows (the row-kernel block).
+static int64_t region_rows(int64_t n_seeds, int nc) {
+  const int64_t sb = kMergeSeeds;
+  const int64_t per_merge = (((n_seeds + sb - 1) / sb + kRegions - 1) / kRegions) * sb * nc;
+  const int64_t per_seed = (((n_seeds + 255) / 256 + kRegions - 1) / kRegions) * 256;
+  const int64_t r = std::max<int64_t>(std::max(per_merge, per_seed), 1);
+  return (r + 255) / 256 * 256;
+}
+
+template <typename TS>
+static void launch_merge(const BuildArgs& a, int l, int cur, hipStream_t st) {
+  const dim3 grid(nblk(a.n_seeds, kMergeSeeds)), block(kMergeThreads);
+  const int ppl = (a.g.max_cands + 3) / 4;  // parents per lane
+  if (ppl <= 1)
+    hipLaunchKernelGGL((build_merge_kernel<TS, 1>), grid, block, 0, st, a, l, cur);
+  else if (ppl == 2)
+    hipLaunchKernelGGL((build_merge_kernel<TS, 2>), grid, block, 0, st, a, l, cur);
+  else if (ppl == 3)
+    hipLaunchKernelGGL((build_merge_kernel<TS, 3>), grid, block, 0, st, a, l, cur);
+  else
+    hipLaunchKernelGGL((build_merge_kernel<TS, 4>), grid, block, 0, st, a, l, cur);
+}
+
 template <typename TS, typename TP>
 static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) {
   const int bs = 256;
@@ -834,15 +971,15 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || bins_only || a.n_seeds == 0) return e;
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t*>(a.ccount),
-                     (int64_t)a.g.n_layers, 0);
+  const int64_t nctr = (int64_t)a.g.n_layers * kRegions * kCtrStride;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nctr, bs)), dim3(bs), 0, st, reinterpret_cast<int32_t*>(a.ccount),
+                     nctr, 0);
   hipLaunchKernelGGL(seed_event_kernel, dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   hipLaunchKernelGGL((build_seed_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   int cur = 0;
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     hipLaunchKernelGGL((build_score_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
-    hipLaunchKernelGGL((build_merge_kernel<TS>), dim3(nblk(a.n_seeds, kMergeThreads)), dim3(kMergeThreads),
-                       (size_t)a.g.max_cands * kMergeThreads * kMergeLdsPerCand, st, a, l, cur);
+    launch_merge<TS>(a, l, cur, st);
     hipLaunchKernelGGL((build_clone_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
     cur ^= 1;
   }
@@ -870,8 +1007,9 @@ static int validate_batch(ktf_ctx* c, const ktf_event_batch* ev) {
   const int64_t nh = ev->hit_off[G];
   if (ev->seed_pitch < ns || ev->hit_pitch < nh) return fail(c, KTF_EINVAL, "ktf_build: pitch < size");
   if (nh > INT32_MAX) return fail(c, KTF_EINVAL, "ktf_build: more than 2^31 hits in one batch");
-  if ((int64_t)c->cfg.max_cands * ev->seed_pitch > INT32_MAX)
-    return fail(c, KTF_EINVAL, "ktf_build: max_cands x seed_pitch exceeds 2^31 candidate slots");
+  if ((int64_t)c->cfg.max_cands * ev->seed_pitch > INT32_MAX ||
+      region_rows(ns, c->cfg.max_cands) * kRegions > INT32_MAX)
+    return fail(c, KTF_EINVAL, "ktf_build: more than 2^31 candidate rows");
   if (ns > 0 && (!ev->seed_state || !ev->seed_cov || !ev->charge || !ev->seed_hit))
     return fail(c, KTF_EINVAL, "ktf_build: null seed buffer");
   if (nh > 0 && !ev->hits) return fail(c, KTF_EINVAL, "ktf_build: null hits");
@@ -901,7 +1039,8 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.n_bins = cfg.n_zbins * cfg.n_phibins;
   a.n_seeds = ev->seed_off[ev->n_events];
   a.sp = ev->seed_pitch;
-  a.S = (int64_t)cfg.max_cands * a.sp;
+  a.RS = region_rows(a.n_seeds, cfg.max_cands);
+  a.S = a.RS * kRegions;
   a.n_hits = ev->hit_off[a.n_groups];
   a.hp = ev->hit_pitch;
   a.hits = ev->hits;
@@ -1006,7 +1145,8 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     p += (size_t)sp * 4;
     a.sev = reinterpret_cast<int32_t*>(p);
   }
-  if ((e = c->b_list.ensure((size_t)S * 4 * 4 + (size_t)sp * 2 * 4 + 64 * 4)) != hipSuccess)
+  const size_t ctr_at = ((size_t)S * 4 + (size_t)sp * 2 + kCtrStride - 1) / kCtrStride * kCtrStride;
+  if ((e = c->b_list.ensure((ctr_at + (size_t)L * kRegions * kCtrStride) * 4)) != hipSuccess)
     return hip_fail(c, e, "list workspace");
   {
     int32_t* p = static_cast<int32_t*>(c->b_list.p);
@@ -1016,7 +1156,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.sel_rec = p + 3 * S;
     a.cstart[0] = p + 4 * S;
     a.cstart[1] = p + 4 * S + sp;
-    a.ccount = reinterpret_cast<unsigned*>(p + 4 * S + 2 * sp);
+    a.ccount = reinterpret_cast<unsigned*>(p + ctr_at);
   }
   return KTF_OK;
 }
