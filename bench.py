@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 # FP64; an FMA counts 2).  See the measurement section of the design notes.
 FLOP_PROP_PER_LAYER = 860      # path solve (3 Newton steps), transport, Jacobian, F P F^T
 FLOP_UPD_PER_LAYER = 585       # V, S, S^-1, chi2, gain, state, Joseph covariance
+FLOP_FPF_PER_LAYER = 378       # the F P F^T part of the propagation (189 FMA)
 PEAK_FP32 = 157.3e12           # MI355X vector FP32 (datasheet, packed issue)
 PEAK_FP64 = 78.6e12            # MI355X vector FP64
 HBM_PEAK = 8.0e12              # bytes/s
@@ -291,6 +292,12 @@ def profile_run(args):
     print(json.dumps({"ms_per_step": ms, "seeds": bs.n_seeds}))
 
 
+def mixed_frac(f32_per_layer, f64_per_layer, L, n, ms):
+    """Achieved over peak for a launch doing the given FP32 and FP64 flops."""
+    f32, f64 = f32_per_layer * L * n, f64_per_layer * L * n
+    return (f32 / PEAK_FP32 + f64 / PEAK_FP64) / (ms * 1e-3)
+
+
 def timed_loop(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -351,6 +358,8 @@ def main():
     print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
     ctx.autotune_fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], out=out32)
     ctx.autotune_fit(d64["state"], d64["cov"], d64["q"], d64["hits"], d64["valid"], out=out64)
+    out32p = ctx.alloc_fit_out(n, d32["state"].shape[1], torch.float32)
+    ctx.autotune_fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], out=out32p, prec="fp32p")
     torch.cuda.synchronize()
 
     def run32(mode="auto"):
@@ -359,20 +368,27 @@ def main():
     def run64(mode="auto"):
         ctx.fit(d64["state"], d64["cov"], d64["q"], d64["hits"], d64["valid"], mode=mode, out=out64)
 
+    def run32p(mode="auto"):
+        ctx.fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], mode=mode, out=out32p,
+                prec="fp32p")
+
     print("[bench] timing FP32-bulk fused fit", file=sys.stderr, flush=True)
     ms, wall_ms = timed_loop(run32, args.steps, args.warmup, torch)
     k_ms = per_launch_ms(run32, 10, torch)
 
     print("[bench] timing FP64 fused, graph sweeps", file=sys.stderr, flush=True)
     ms64, _ = timed_loop(run64, max(3, args.steps // 2), 2, torch)
+    ms32p, _ = timed_loop(run32p, max(3, args.steps // 2), 2, torch)
     ms32_sw, _ = timed_loop(lambda: run32("sweep_graph"), max(3, args.steps // 2), 2, torch)
     ms64_sw, _ = timed_loop(lambda: run64("sweep_graph"), max(3, args.steps // 2), 2, torch)
 
     # results of the timed configurations, for the error report
     run32()
     run64()
+    run32p()
     torch.cuda.synchronize()
     g32 = {k: v.cpu().numpy()[..., :n] for k, v in out32.items()}
+    g32p = {k: v.cpu().numpy()[..., :n] for k, v in out32p.items()}
     g64 = {k: v.cpu().numpy()[..., :n] for k, v in out64.items()}
 
     # roofline of the dominant kernel (the fused FP32-bulk fit)
@@ -419,6 +435,11 @@ def main():
         "fp64_plain": {"tracks_per_s": round(n / (ms64 * 1e-3)), "ms": round(ms64, 4),
                        "launch": ctx.tuned_shape("fp64", n)},
         "speedup_fp32b_over_fp64": round(ms64 / ms, 3),
+        "fp32_prop": {"tracks_per_s": round(n / (ms32p * 1e-3)), "ms": round(ms32p, 4),
+                      "roofline_frac": round(mixed_frac(FLOP_PROP_PER_LAYER - FLOP_FPF_PER_LAYER,
+                                                        FLOP_UPD_PER_LAYER + FLOP_FPF_PER_LAYER, L, n, ms32p), 4),
+                      "launch": ctx.tuned_shape("fp32p", n),
+                      "precision": "float state propagation, double covariance (F P F^T and update)"},
         "sweep_graph": sweep,
         "wall_ms_per_step": round(wall_ms, 4),
     }
@@ -442,15 +463,19 @@ def main():
                                   "sample": f"first {m} of the {n} tracks, FP64 scalar C, "
                                             f"{cores} threads, wall {t_cpu:.2f} s"}
         # accuracy of both GPU paths on the oracle's sample
-        from tests.helpers import fp32_errors, pulls
+        from tests.helpers import fp32_errors, param_rel_errors, pulls
         acc = {}
-        for name, g in (("fp32b", g32), ("fp64", g64)):
+        ptv = np.hypot(o["state"][3], o["state"][4])
+        for name, g in (("fp32b", g32), ("fp32p", g32p), ("fp64", g64)):
             gs = {k: v[..., :m] for k, v in g.items()}
             e_pos, e_mom = fp32_errors(gs, o, 40.0)
             pg = pulls(gs["state"], gs["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
             po = pulls(o["state"], o["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
             acc[name] = {"e_pos_max": float(e_pos.max()), "e_mom_max": float(e_mom.max()),
                          "e_mom_p999": float(np.quantile(e_mom, 0.999)),
+                         "e_rel_max": float(param_rel_errors(gs, o).max()),
+                         "e_mom_max_by_pt": {f"{lo:g}-{hi:g}": float(e_mom[(ptv >= lo) & (ptv < hi)].max(initial=0.0))
+                                             for lo, hi in ((0.5, 2), (2, 10), (10, 30), (30, 100))},
                          "pull_rms_ratio": {kk: round(float(np.sqrt(np.mean(pg[kk] ** 2)) /
                                                             np.sqrt(np.mean(po[kk] ** 2))), 5)
                                             for kk in pg},

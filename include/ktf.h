@@ -19,7 +19,7 @@
  *  - Device arrays are structure-of-arrays, element-major: component c of
  *    track i is at [c * pitch + i], pitch >= n (a multiple of 64 keeps
  *    loads aligned).  Element type is double for KTF_FP64 and float for
- *    KTF_FP32_BULK unless a field says otherwise.
+ *    KTF_FP32_BULK and KTF_FP32_PROP unless a field says otherwise.
  *  - Every pointer named "device" must be device memory of the current HIP
  *    device; "host" pointers are ordinary host memory.  The caller owns all
  *    buffers it passes; the library owns its context, its workspace and its
@@ -58,10 +58,16 @@ extern "C" {
 #define KTF_ST_NONFINITE 4u  /* non-finite state or covariance: track stops       */
 
 typedef enum {
-  KTF_FP64 = 0,      /* everything in double                                     */
-  KTF_FP32_BULK = 1  /* float storage, float propagation (path solve, transport,
-                        Jacobian, F P F^T); the update (S, S^-1, chi2, gain,
-                        state and Joseph covariance update) in double            */
+  KTF_FP64 = 0,       /* everything in double                                    */
+  KTF_FP32_BULK = 1,  /* float storage, float propagation (path solve, transport,
+                         Jacobian, F P F^T); the update (S, S^-1, chi2, gain,
+                         state and Joseph covariance update) in double           */
+  KTF_FP32_PROP = 2   /* float storage and float state propagation (path solve,
+                         transport, Jacobian); the covariance is kept in double
+                         between layers, so F P F^T and the update run in double.
+                         Fused and persistent fits only (a sweep keeps the
+                         covariance in HBM in the storage type: KTF_EINVAL);
+                         not accepted by ktf_build or ktf_submit               */
 } ktf_precision;
 
 typedef enum {

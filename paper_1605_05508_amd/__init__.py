@@ -17,11 +17,11 @@ LIB_PATH = os.path.join(HERE, "libktf.so")
 
 OK, EINVAL, ENOMEM, EAGAIN, ENOTFOUND, EDEVICE = 0, -1, -2, -3, -4, -5
 ST_NO_REACH, ST_S_NOT_PD, ST_NONFINITE = 1, 2, 4
-FP64, FP32_BULK = 0, 1
+FP64, FP32_BULK, FP32_PROP = 0, 1, 2
 FIT_AUTO, FIT_FUSED, FIT_PERSISTENT, FIT_SWEEP, FIT_SWEEP_GRAPH = 0, 1, 2, 3, 4
 MODES = {"auto": FIT_AUTO, "fused": FIT_FUSED, "persistent": FIT_PERSISTENT,
          "sweep": FIT_SWEEP, "sweep_graph": FIT_SWEEP_GRAPH}
-PRECS = {"fp64": FP64, "fp32b": FP32_BULK}
+PRECS = {"fp64": FP64, "fp32b": FP32_BULK, "fp32p": FP32_PROP}
 MAX_LAYERS = 32
 
 EXPORTS = ["ktf_create", "ktf_destroy", "ktf_last_error", "ktf_fit", "ktf_autotune_fit",
@@ -178,9 +178,14 @@ class Context:
             raise KtfError(rc, f"{what}: {msg.decode() if msg else ''}")
 
     # ---------------------------------------------------------------- fit
-    def _fit_structs(self, state, cov, q, hits, valid, out):
+    def _fit_structs(self, state, cov, q, hits, valid, out, prec=None):
         torch = _torch()
-        prec = FP64 if state.dtype == torch.float64 else FP32_BULK
+        if prec is None:
+            prec = FP64 if state.dtype == torch.float64 else FP32_BULK
+        else:
+            prec = PRECS[prec]
+            if (prec == FP64) != (state.dtype == torch.float64):
+                raise ValueError("precision and storage dtype disagree")
         n = q.shape[0]
         pitch = state.shape[1]
         fin = _FitIn(n, pitch, prec, _ptr(state), _ptr(cov), _ptr(q), _ptr(hits), _ptr(valid))
@@ -197,24 +202,25 @@ class Context:
                     nupd=torch.empty(pitch, dtype=torch.int32, device=dev),
                     status=torch.empty(pitch, dtype=torch.int32, device=dev))
 
-    def fit(self, state, cov, q, hits, valid=None, *, mode="auto", out=None, stream=None):
+    def fit(self, state, cov, q, hits, valid=None, *, mode="auto", out=None, stream=None, prec=None):
         """Enqueue a fit.  state [6, pitch], cov [21, pitch] (float64 for the FP64
-        path, float32 for FP32-bulk), q int8 [pitch] (first n = len(q) are
-        tracks), hits [L, 3, pitch] same dtype, valid uint8 [L, pitch] or None."""
-        torch = _torch()
+        path, float32 for the float-storage paths), q int8 [pitch] (first n =
+        len(q) are tracks), hits [L, 3, pitch] same dtype, valid uint8 [L, pitch]
+        or None.  prec: None (from the dtype: 'fp64' or 'fp32b') or 'fp32p'
+        (float state propagation, double covariance; fused modes only)."""
         self._validate_fit(state, cov, q, hits, valid)
         if out is None:
             out = self.alloc_fit_out(q.shape[0], state.shape[1], state.dtype)
-        fin, fout = self._fit_structs(state, cov, q, hits, valid, out)
+        fin, fout = self._fit_structs(state, cov, q, hits, valid, out, prec)
         self._check(self._lib.ktf_fit(self._h, C.byref(fin), C.byref(fout), MODES[mode],
                                       _stream_handle(stream)), "ktf_fit")
         return out
 
-    def autotune_fit(self, state, cov, q, hits, valid=None, *, out=None, stream=None):
+    def autotune_fit(self, state, cov, q, hits, valid=None, *, out=None, stream=None, prec=None):
         self._validate_fit(state, cov, q, hits, valid)
         if out is None:
             out = self.alloc_fit_out(q.shape[0], state.shape[1], state.dtype)
-        fin, fout = self._fit_structs(state, cov, q, hits, valid, out)
+        fin, fout = self._fit_structs(state, cov, q, hits, valid, out, prec)
         self._check(self._lib.ktf_autotune_fit(self._h, C.byref(fin), C.byref(fout),
                                                _stream_handle(stream)), "ktf_autotune_fit")
         return out

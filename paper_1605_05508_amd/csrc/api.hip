@@ -56,7 +56,7 @@ static int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* o
   if (!c || !in || !out) return fail(c, KTF_EINVAL, "ktf_fit: null argument");
   if (in->n < 0 || in->pitch < in->n)
     return fail(c, KTF_EINVAL, "ktf_fit: n=%lld pitch=%lld", (long long)in->n, (long long)in->pitch);
-  if (in->prec != KTF_FP64 && in->prec != KTF_FP32_BULK)
+  if (in->prec != KTF_FP64 && in->prec != KTF_FP32_BULK && in->prec != KTF_FP32_PROP)
     return fail(c, KTF_EINVAL, "ktf_fit: unknown precision %d", (int)in->prec);
   if (in->n > 0 && (!in->seed_state || !in->seed_cov || !in->charge || !in->hits || !out->state ||
                     !out->cov || !out->chi2 || !out->n_upd || !out->status))
@@ -210,7 +210,10 @@ int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mod
     case KTF_FIT_FUSED: break;
     case KTF_FIT_PERSISTENT: persistent = true; break;
     case KTF_FIT_SWEEP:
-    case KTF_FIT_SWEEP_GRAPH: break;
+    case KTF_FIT_SWEEP_GRAPH:
+      if (in->prec == KTF_FP32_PROP)
+        return fail(c, KTF_EINVAL, "ktf_fit: KTF_FP32_PROP keeps the covariance in registers; use a fused mode");
+      break;
     default: return fail(c, KTF_EINVAL, "ktf_fit: unknown mode %d", (int)mode);
   }
   return run_fit(c, a, in->prec, mode, bs, persistent, st);

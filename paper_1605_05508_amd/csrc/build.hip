@@ -53,6 +53,7 @@ struct BuildArgs {
   int64_t S;               // candidate rows = kRegions * RS
   int64_t RS;              // rows per region
   int64_t n_hits;          // total hits
+  int64_t max_group;       // most hits in one (event, layer)
   int64_t hp;              // hit pitch
   const int64_t* seed_off; // device [n_events+1]
   const int64_t* hit_off;  // device [n_groups+1]
@@ -313,6 +314,138 @@ __global__ __launch_bounds__(kBinThreads) void bin_group_kernel(BuildArgs a) {
     o[dst] = h[gj];
     o[a.n_hits + dst] = h[a.hp + gj];
     o[2 * a.n_hits + dst] = h[2 * a.hp + gj];
+  }
+}
+
+// Packed variant for groups of at most kPackMaxHits hits (the usual case):
+// counts, offsets and cursors are 16-bit halves of 32-bit LDS words (64 KB
+// for 32,768 bins) and the unordered scatter stays in LDS as 16-bit local
+// indices, so ordering each bin by original index reads LDS only.  Each
+// thread takes its hits kBinBatch at a time with their loads issued
+// together, so a phase costs one memory round trip per batch.
+constexpr int kPackMaxHits = 32768;
+constexpr int kBinBatch = 8;
+template <typename TS>
+__global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
+  __shared__ uint32_t cnt[kLdsBins / 2];  // bin b in half b & 1 of word b >> 1
+  __shared__ uint16_t permr[kPackMaxHits];
+  __shared__ int32_t wsum[kBinThreads / 64];
+  const int g = blockIdx.x;
+  const int nb = a.n_bins, nwords = (nb + 1) >> 1;
+  const int tid = threadIdx.x;
+  const int64_t base = a.hit_off[g];
+  const int32_t n = (int32_t)(a.hit_off[g + 1] - base);
+  int32_t* off = a.bin_off + (int64_t)g * (nb + 1);
+  const TS* h = static_cast<const TS*>(a.hits);
+  for (int w = tid; w < nwords; w += kBinThreads) cnt[w] = 0;
+  __syncthreads();
+  // count
+  for (int32_t j0 = 0; j0 < n; j0 += kBinBatch * kBinThreads) {
+    TS x[kBinBatch], y[kBinBatch], z[kBinBatch];
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t j = j0 + u * kBinThreads + tid;
+      x[u] = y[u] = z[u] = TS(0);
+      if (j < n) {
+        x[u] = h[base + j];
+        y[u] = h[a.hp + base + j];
+        z[u] = h[2 * a.hp + base + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t j = j0 + u * kBinThreads + tid;
+      if (j < n) {
+        const int b = hit_bin_of((double)x[u], (double)y[u], (double)z[u], a.g.z_half, a.g.n_zbins,
+                                 a.g.n_phibins);
+        a.hit_bin[base + j] = b;
+        atomicAdd(&cnt[b >> 1], 1u << ((b & 1) * 16));
+      }
+    }
+  }
+  __syncthreads();
+  // exclusive scan: each thread a contiguous run of words, then the block
+  const int per = (nwords + kBinThreads - 1) / kBinThreads;
+  const int w0 = min(nwords, tid * per), w1 = min(nwords, w0 + per);
+  int32_t sum = 0;
+  for (int w = w0; w < w1; ++w) {
+    const uint32_t v = cnt[w];
+    sum += (int32_t)((v & 0xffffu) + (v >> 16));
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  constexpr int nw = kBinThreads / 64;
+  int32_t x = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int32_t run = x - sum;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+  for (int w = w0; w < w1; ++w) {
+    const uint32_t v = cnt[w];
+    const uint32_t lo = v & 0xffffu;
+    cnt[w] = (uint32_t)run | ((uint32_t)(run + (int32_t)lo) << 16);
+    run += (int32_t)(lo + (v >> 16));
+  }
+  __syncthreads();
+  for (int b = tid; b < nb; b += kBinThreads) off[b] = (int32_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
+  if (tid == 0) off[nb] = n;
+  __syncthreads();
+  // scatter through the cursors (a bin's cursor ends at the next offset)
+  for (int32_t j0 = 0; j0 < n; j0 += kBinBatch * kBinThreads) {
+    int bb[kBinBatch];
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t j = j0 + u * kBinThreads + tid;
+      bb[u] = j < n ? a.hit_bin[base + j] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t j = j0 + u * kBinThreads + tid;
+      if (j < n) {
+        const int sh = (bb[u] & 1) * 16;
+        const uint32_t pos = (atomicAdd(&cnt[bb[u] >> 1], 1u << sh) >> sh) & 0xffffu;
+        permr[pos] = (uint16_t)j;
+      }
+    }
+  }
+  __syncthreads();
+  // order every bin by original index and copy the coordinates
+  TS* o = static_cast<TS*>(a.hb);
+  for (int32_t j0 = 0; j0 < n; j0 += kBinBatch * kBinThreads) {
+    int bb[kBinBatch];
+    TS x[kBinBatch], y[kBinBatch], z[kBinBatch];
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t j = j0 + u * kBinThreads + tid;
+      bb[u] = 0;
+      x[u] = y[u] = z[u] = TS(0);
+      if (j < n) {
+        bb[u] = a.hit_bin[base + j];
+        x[u] = h[base + j];
+        y[u] = h[a.hp + base + j];
+        z[u] = h[2 * a.hp + base + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t j = j0 + u * kBinThreads + tid;
+      if (j < n) {
+        const int b = bb[u];
+        const int32_t hi = (int32_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
+        const int32_t lo = b > 0 ? (int32_t)((cnt[(b - 1) >> 1] >> (((b - 1) & 1) * 16)) & 0xffffu) : 0;
+        int32_t rank = 0;
+        for (int32_t k = lo; k < hi; ++k) rank += permr[k] < j ? 1 : 0;
+        const int64_t dst = base + lo + rank;
+        a.perm[dst] = j;
+        o[dst] = x[u];
+        o[a.n_hits + dst] = y[u];
+        o[2 * a.n_hits + dst] = z[u];
+      }
+    }
   }
 }
 
@@ -957,7 +1090,9 @@ template <typename TS, typename TP>
 static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) {
   const int bs = 256;
   const int64_t nbins_all = (int64_t)a.n_groups * a.n_bins;
-  if (nbins_all > 0 && a.n_bins <= kLdsBins) {
+  if (nbins_all > 0 && a.n_bins <= kLdsBins && a.max_group <= kPackMaxHits) {
+    hipLaunchKernelGGL((bin_group16_kernel<TS>), dim3(a.n_groups), dim3(kBinThreads), 0, st, a);
+  } else if (nbins_all > 0 && a.n_bins <= kLdsBins) {
     hipLaunchKernelGGL((bin_group_kernel<TS>), dim3(a.n_groups), dim3(kBinThreads), 0, st, a);
   } else if (nbins_all > 0) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nbins_all, bs)), dim3(bs), 0, st, a.bin_cur, nbins_all, 0);
@@ -1042,6 +1177,9 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.RS = region_rows(a.n_seeds, cfg.max_cands);
   a.S = a.RS * kRegions;
   a.n_hits = ev->hit_off[a.n_groups];
+  a.max_group = 0;
+  for (int g = 0; g < a.n_groups; ++g)
+    a.max_group = std::max<int64_t>(a.max_group, ev->hit_off[g + 1] - ev->hit_off[g]);
   a.hp = ev->hit_pitch;
   a.hits = ev->hits;
   a.seed_state = ev->seed_state;

@@ -24,20 +24,21 @@ template <typename T> struct NewtonIters;
 template <> struct NewtonIters<double> { static constexpr int n = 3; };
 template <> struct NewtonIters<float> { static constexpr int n = 2; };
 
-// Storage type TS, propagation type TP.
-template <typename TS, typename TP>
+// Storage type TS, propagation type TP (state, path solve, transport,
+// Jacobian), covariance type TC (registers, F P F^T and update).
+template <typename TS, typename TP, typename TC>
 __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
   const int64_t p = a.pitch;
   const TS* st = static_cast<const TS*>(a.state);
   const TS* cv = static_cast<const TS*>(a.cov);
   TrackState<TP> x;
-  TP P[21];
+  TC P[21];
 #pragma unroll
   for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * p + i];
 #pragma unroll
   for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * p + i];
 #pragma unroll
-  for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * p + i];
+  for (int c = 0; c < 21; ++c) P[c] = (TC)cv[c * p + i];
   const TP k = (TP)(kCLight * (double)a.q[i] * a.bz);
   const int L = a.n_layers;
   uint32_t vmask = 0;
@@ -72,7 +73,7 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
       status |= kNoReach;
       break;
     }
-    TP Pp[21];
+    TC Pp[21];
     cov_propagate(P, F, Pp);
     bool used = false;
     if ((vmask >> l) & 1u) {
@@ -109,15 +110,15 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
   a.status[i] = status;
 }
 
-template <typename TS, typename TP, int BS>
+template <typename TS, typename TP, typename TC, int BS>
 __global__ __launch_bounds__(BS) void fit_fused_kernel(FitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < a.n) fit_one_track<TS, TP>(a, i);
+  if (i < a.n) fit_one_track<TS, TP, TC>(a, i);
 }
 
 // Persistent blocks: every block loops taking the next tile of BS tracks
 // from counters[0]; all waves leave once the tile index passes tile_count.
-template <typename TS, typename TP, int BS>
+template <typename TS, typename TP, typename TC, int BS>
 __global__ __launch_bounds__(BS) void fit_persistent_kernel(FitArgs a) {
   __shared__ long long tile;
   for (;;) {
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(BS) void fit_persistent_kernel(FitArgs a) {
     __syncthreads();
     if (t >= a.tile_count) break;
     const int64_t i = t * BS + threadIdx.x;
-    if (i < a.n) fit_one_track<TS, TP>(a, i);
+    if (i < a.n) fit_one_track<TS, TP, TC>(a, i);
   }
 }
 
@@ -238,25 +239,25 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
   return hipGetLastError();
 }
 
-template <typename TS, typename TP, int BS>
+template <typename TS, typename TP, typename TC, int BS>
 static hipError_t launch_fused_bs(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
   if (persistent) {
-    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, BS>), dim3(pblocks), dim3(BS), 0, st, a);
+    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, TC, BS>), dim3(pblocks), dim3(BS), 0, st, a);
   } else {
     const int64_t nb = (a.n + BS - 1) / BS;
-    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, BS>), dim3((unsigned)nb), dim3(BS), 0, st, a);
+    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS>), dim3((unsigned)nb), dim3(BS), 0, st, a);
   }
   return hipGetLastError();
 }
 
-template <typename TS, typename TP>
+template <typename TS, typename TP, typename TC>
 static hipError_t launch_fused_t(const FitArgs& a, int bs, bool persistent, int pblocks,
                                  hipStream_t st) {
   switch (bs) {
-    case 64: return launch_fused_bs<TS, TP, 64>(a, persistent, pblocks, st);
-    case 128: return launch_fused_bs<TS, TP, 128>(a, persistent, pblocks, st);
-    case 256: return launch_fused_bs<TS, TP, 256>(a, persistent, pblocks, st);
-    case 512: return launch_fused_bs<TS, TP, 512>(a, persistent, pblocks, st);
+    case 64: return launch_fused_bs<TS, TP, TC, 64>(a, persistent, pblocks, st);
+    case 128: return launch_fused_bs<TS, TP, TC, 128>(a, persistent, pblocks, st);
+    case 256: return launch_fused_bs<TS, TP, TC, 256>(a, persistent, pblocks, st);
+    case 512: return launch_fused_bs<TS, TP, TC, 512>(a, persistent, pblocks, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -264,8 +265,9 @@ static hipError_t launch_fused_t(const FitArgs& a, int bs, bool persistent, int 
 hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, bool persistent,
                             int persistent_blocks, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  if (prec == KTF_FP64) return launch_fused_t<double, double>(a, bs, persistent, persistent_blocks, st);
-  return launch_fused_t<float, float>(a, bs, persistent, persistent_blocks, st);
+  if (prec == KTF_FP64) return launch_fused_t<double, double, double>(a, bs, persistent, persistent_blocks, st);
+  if (prec == KTF_FP32_PROP) return launch_fused_t<float, float, double>(a, bs, persistent, persistent_blocks, st);
+  return launch_fused_t<float, float, float>(a, bs, persistent, persistent_blocks, st);
 }
 
 hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hipStream_t st) {
@@ -283,22 +285,24 @@ hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hip
 
 namespace ktf {
 
-template <typename TS, typename TP>
+template <typename TS, typename TP, typename TC>
 static int occ_blocks(int bs) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (bs) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 64>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 128>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 256>, 256, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, 512>, 512, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 64>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 128>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 256>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 512>, 512, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;
 }
 
 int persistent_blocks(ktf_ctx*, ktf_precision prec, int bs) {
-  return prec == KTF_FP64 ? occ_blocks<double, double>(bs) : occ_blocks<float, float>(bs);
+  if (prec == KTF_FP64) return occ_blocks<double, double, double>(bs);
+  if (prec == KTF_FP32_PROP) return occ_blocks<float, float, double>(bs);
+  return occ_blocks<float, float, float>(bs);
 }
 
 }  // namespace ktf

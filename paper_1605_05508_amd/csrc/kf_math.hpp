@@ -303,13 +303,23 @@ KTF_HD bool propagate(const TrackState<T>& x, T k, double r, bool nearest, Track
   return ok;
 }
 
-// P' = F P F^T on packed storage using the Jacobian's structure.
+// P' = F P F^T on packed storage using the Jacobian's structure, in the
+// covariance's type T (the Jacobian may be of a narrower type J).
 // Index sets: transverse T = {0, 1, 3, 4} (block positions 0..3), z = 2,
 // pz = 5.
-template <typename T>
-KTF_HD void cov_propagate(const T P[21], const Jac<T>& F, T Po[21]) {
+template <typename T, typename J>
+KTF_HD void cov_propagate(const T P[21], const Jac<J>& FJ, T Po[21]) {
   constexpr int tix[4] = {0, 1, 3, 4};
-  const T fz[4] = {F.z0, F.z1, F.z3, F.z4};
+  struct {
+    T a[4][4];
+    T z5;
+  } F;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F.a[r][c] = (T)FJ.a[r][c];
+  F.z5 = (T)FJ.z5;
+  const T fz[4] = {(T)FJ.z0, (T)FJ.z1, (T)FJ.z3, (T)FJ.z4};
   // row by row: G_i = (F P)_i, then P'_ij = G_i . F_j for j >= i
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -369,8 +379,8 @@ struct Residual {
   double chi2;
 };
 
-template <typename T>
-KTF_HD bool residual(const TrackState<T>& xp, const T Pp[21], const double m[3],
+template <typename T, typename C>
+KTF_HD bool residual(const TrackState<T>& xp, const C Pp[21], const double m[3],
                      const HitRes& hr, Residual& o) {
   const double rho2 = m[0] * m[0] + m[1] * m[1];
   const double irho2 = rcp_nr(rho2);
@@ -403,13 +413,14 @@ KTF_HD bool residual(const TrackState<T>& xp, const T Pp[21], const double m[3],
   return pd;
 }
 
-// State and covariance update given the residual; writes into x, P (TP).
+// State and covariance update given the residual; writes into x (state
+// type T) and P (covariance type C).
 // Joseph form expanded: P+ = P' - K B^T - B K^T + K S K^T
 //                          = P' - K D^T - D K^T  with D = B - (K S)/2,
 // which needs only K and D per row (S symmetric).
-template <typename T>
-KTF_HD void apply_update(const TrackState<T>& xp, const T Pp[21], const Residual& R,
-                         TrackState<T>& x, T P[21]) {
+template <typename T, typename C>
+KTF_HD void apply_update(const TrackState<T>& xp, const C Pp[21], const Residual& R,
+                         TrackState<T>& x, C P[21]) {
   double K[6][3], D[6][3];
   const double* Si = R.Si;
   const double* S = R.S;
@@ -444,19 +455,19 @@ KTF_HD void apply_update(const TrackState<T>& xp, const T Pp[21], const Residual
         acc = fma(-K[i][c], D[j][c], acc);
         acc = fma(-D[i][c], K[j][c], acc);
       }
-      P[pidx(i, j)] = (T)acc;
+      P[pidx(i, j)] = (C)acc;
     }
   }
 }
 
-template <typename T>
-KTF_HD bool finite_state(const TrackState<T>& x, const T P[21]) {
-  T acc = (T)(x.pos[0] + x.pos[1] + x.pos[2]);
+template <typename T, typename C>
+KTF_HD bool finite_state(const TrackState<T>& x, const C P[21]) {
+  C acc = (C)(x.pos[0] + x.pos[1] + x.pos[2]);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) acc += x.mom[i];
+  for (int i = 0; i < 3; ++i) acc += (C)x.mom[i];
 #pragma unroll
   for (int i = 0; i < 21; ++i) acc += P[i];
-  return acc - acc == T(0);  // false for inf and nan
+  return acc - acc == C(0);  // false for inf and nan
 }
 
 }  // namespace ktf

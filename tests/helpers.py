@@ -78,6 +78,13 @@ def fp32_errors(g, o, radius):
     return e_pos, e_mom
 
 
+def param_rel_errors(g, o):
+    """Per track, the largest |a_i - b_i| / (|b_i| + sigma_i) over the six
+    parameters: the measure of the FP64 tolerance, applied to FP32 bulk."""
+    sig = sigma_diag(o["cov"])
+    return (np.abs(g["state"] - o["state"]) / (np.abs(o["state"]) + sig)).max(axis=0)
+
+
 def pulls(state, cov, truth_pos, truth_mom):
     """Tangential, z, px, py, pz pulls at the last layer vs the truth crossing."""
     d = state - np.concatenate([truth_pos, truth_mom])

@@ -45,9 +45,21 @@ def oracle_batch(orc, bs, **kw):
     return cat
 
 
-def test_bins_match_oracle(k, orc):
-    bs = small_batch(1, 3, 400, n_layers=6)
-    ctx = ctx_for(k, bs.det)
+@pytest.mark.parametrize("case", ["packed", "wide_group", "many_bins"])
+def test_bins_match_oracle(k, orc, case):
+    """The three binning paths: groups of at most 32,768 hits (16-bit LDS
+    tables), a group above that (32-bit LDS table), and a table of more than
+    32,768 bins (multi-kernel path)."""
+    nz, nphi = 64, 512
+    if case == "packed":
+        bs = small_batch(1, 3, 400, n_layers=6)
+    elif case == "wide_group":
+        bs = small_batch(2, 1, 30_000, n_layers=4)
+        assert np.diff(bs.hit_off).max() > 32_768
+    else:
+        bs = small_batch(3, 2, 300, n_layers=4)
+        nz = 128
+    ctx = ctx_for(k, bs.det, n_zbins=nz, n_phibins=nphi)
     for prec in ("fp64", "fp32b"):
         d = build_inputs(bs, prec, hit_pad=64)
         offs, perm = ctx.bin_hits(d)
@@ -57,7 +69,7 @@ def test_bins_match_oracle(k, orc):
             for l in range(L):
                 g = e * L + l
                 h = bs.layer_hits(e, l)
-                oo, op = orc.bin_layer(h, 100.0, 64, 512)
+                oo, op = orc.bin_layer(h, 100.0, nz, nphi)
                 a, b = bs.hit_off[g], bs.hit_off[g + 1]
                 assert np.array_equal(offs[g], oo), (prec, e, l)
                 assert np.array_equal(perm[a:b], op), (prec, e, l)
