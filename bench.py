@@ -85,9 +85,10 @@ def parse():
     ap.add_argument("--profile", choices=["fit", "sweep", "build", "copy"], default=None,
                     help="only one timed loop, for rocprofv3 runs (copy: a plain copy of "
                          "known size to calibrate the HBM byte counters)")
-    ap.add_argument("--workload", choices=["fit", "uneven"], default="fit",
+    ap.add_argument("--workload", choices=["fit", "uneven", "dense_events"], default="fit",
                     help="fit: the headline line; uneven: events of uneven size in one "
-                         "launch versus per-event launches")
+                         "launch versus per-event launches; dense_events: building on "
+                         "20,000-track events, combinatorial and best-hit")
     ap.add_argument("--no-build", action="store_true", help="skip the building measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-events", type=int, default=200)
@@ -166,31 +167,59 @@ def serving_measurement(ktf, tg, n_events, rates):
     return out
 
 
-def build_measurement(ctx_cls, tg, torch, reps=5, orc=None):
+def build_efficiency(hit, true_idx, nsl=3):
+    """Track efficiency: seeds whose every layer took exactly their own hit
+    (or none where they have none).  Hit efficiency: built layers (beyond
+    the seed layers) with a true hit where the seed took it.  Fake rate:
+    taken hits that are not the seed's own."""
+    h, t = hit[nsl:], true_idx[nsl:]
+    has = t >= 0
+    took = h >= 0
+    return {"all_hits_true_fraction": round(float((hit == true_idx).all(axis=0).mean()), 4),
+            "hit_efficiency": round(float((h == t)[has].mean()), 4),
+            "fake_hit_rate": round(float((h != t)[took].mean()), 5)}
+
+
+def time_build(ctx, d, o, reps, torch):
+    ctx.build(d, out=o)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ctx.build(d, out=o)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def build_measurement(ctx_cls, tg, torch, reps=5, orc=None, bs=None, precs=("fp32b", "fp64")):
     """Combinatorial building of 100 events x 5,000 tracks (17 layers, 20%
     noise hits, 64 x 512 bins, 10 candidates, chi2 < 30, one missed layer)
-    in one batch."""
+    in one batch, and best-hit building (one candidate per seed) on the same
+    events."""
     from tests.helpers import build_inputs
-    bs = tg.config3()
+    bs = tg.config3() if bs is None else bs
     ctx = ctx_cls.for_detector(bs.det)
     out = {"events": bs.n_events, "seeds": bs.n_seeds, "hits": int(bs.hits.shape[1])}
-    for prec in ("fp32b", "fp64"):
+    for prec in precs:
         d = build_inputs(bs, prec)
         o = ctx.build(d)
-        torch.cuda.synchronize()
-        s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
-            ctx.build(d, out=o)
-        e1.record(s)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = time_build(ctx, d, o, reps, torch)
         hit = o["hit_idx"].cpu().numpy()[:, :bs.n_seeds]
-        eff = float((hit == bs.true_idx).all(axis=0).mean())
         out[prec] = {"ms": round(ms, 3), "seeds_per_s": round(bs.n_seeds / (ms * 1e-3)),
                      "events_per_s": round(bs.n_events / (ms * 1e-3), 1),
-                     "all_hits_true_fraction": round(eff, 4)}
+                     **build_efficiency(hit, bs.true_idx)}
+        if prec == "fp32b":
+            ctx1 = ctx_cls.for_detector(bs.det, max_cands=1)
+            o1 = ctx1.build(d)
+            ms1 = time_build(ctx1, d, o1, reps, torch)
+            hit1 = o1["hit_idx"].cpu().numpy()[:, :bs.n_seeds]
+            out["fp32b_best_hit"] = {"ms": round(ms1, 3), "seeds_per_s": round(bs.n_seeds / (ms1 * 1e-3)),
+                                     "events_per_s": round(bs.n_events / (ms1 * 1e-3), 1),
+                                     **build_efficiency(hit1, bs.true_idx)}
+            del o1
+            ctx1.close()
         del d, o
     if orc is not None:
         m = 100
@@ -201,6 +230,25 @@ def build_measurement(ctx_cls, tg, torch, reps=5, orc=None):
                              "sample": f"{m} seeds of one event, brute force over every hit"}
     ctx.close()
     return out
+
+
+def dense_events_workload(args):
+    """Building on 25 events of 20,000 tracks (the occupancy of the paper's
+    building plots), 17 layers, 20% noise: combinatorial (10 candidates)
+    against best-hit (one candidate), FP32 bulk."""
+    import torch
+    import paper_1605_05508_amd as ktf
+    import trackgen as tg
+    print("[bench] generating 25 events x 20,000 tracks", file=sys.stderr, flush=True)
+    bs = tg.config3(n_events=25, n_tracks=20_000, seed=4)
+    print("[bench] building", file=sys.stderr, flush=True)
+    res = build_measurement(ktf.Context, tg, torch, bs=bs, precs=("fp32b",))
+    print(json.dumps({"metric": "built seeds/s on 20,000-track events, combinatorial vs best-hit",
+                      "value": res["fp32b"]["seeds_per_s"], "unit": "seeds/s", "n_gpus": 1,
+                      "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+                      "config": {"workload": "25 events x 20,000 tracks, 17 barrel layers, +20% noise hits, "
+                                             "64 x 512 bins, chi2 < 30, one missed layer"},
+                      "building": res}), flush=True)
 
 
 def uneven_workload(args):
@@ -342,6 +390,9 @@ def main():
     if args.workload == "uneven":
         uneven_workload(args)
         return
+    if args.workload == "dense_events":
+        dense_events_workload(args)
+        return
     import torch
     import paper_1605_05508_amd as ktf
     import trackgen as tg
@@ -397,12 +448,12 @@ def main():
     t_bound = f32 / PEAK_FP32 + f64 / PEAK_FP64
     mixed_peak = (f32 + f64) / t_bound
     achieved = (f32 + f64) / (k_ms * 1e-3)
-    traffic = measured_traffic("fit_fused_kernel<float,float>")
+    traffic = measured_traffic("fit_fused_kernel<float,float,float>")
     roof = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(mixed_peak / 1e12, 1),
             "unit": "TFLOP/s", "frac": round(achieved / mixed_peak, 4),
             "traffic": None if traffic is None else round(traffic / 1e6, 1),
             "traffic_unit": "MB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "fit_fused_kernel<float,float>", "kernel_ms": round(k_ms, 4),
+            "kernel": "fit_fused_kernel<float,float,float>", "kernel_ms": round(k_ms, 4),
             "flop_per_track": (FLOP_PROP_PER_LAYER + FLOP_UPD_PER_LAYER) * L,
             "hbm_GBps": round(fused_bytes_per_track(4, L) * n / (k_ms * 1e-3) / 1e9, 1)}
     sweep = {}

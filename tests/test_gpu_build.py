@@ -170,6 +170,24 @@ def test_config3_full_size_sampled(k, orc):
             assert ok, (e, s, layer)
 
 
+def test_dense_event_sampled(k, orc):
+    """One 20,000-track event (24,000 hits per layer, the occupancy of the
+    paper's building plots) with a beam of 10 and best-hit building (a beam
+    of one): sampled seeds exactly as the FP64 oracle."""
+    bs = tg.config3(n_events=1, n_tracks=20_000, seed=4)
+    rng = np.random.default_rng(6)
+    loc = rng.choice(bs.n_seeds, 60, replace=False)
+    d = build_inputs(bs, "fp64")
+    for nc in (10, 1):
+        ctx = ctx_for(k, bs.det, max_cands=nc)
+        g = host(ctx.build(d), bs.n_seeds)
+        o = orc.build_event(bs, 0, seeds=loc, max_cands=nc)
+        assert np.array_equal(g["hit_idx"][:, loc], o["hit_idx"]), nc
+        assert np.array_equal(g["nhits"][loc], o["nhits"]), nc
+        np.testing.assert_allclose(g["chi2"][loc], o["chi2"], rtol=1e-10)
+        ctx.close()
+
+
 def test_fp32_build_agrees_up_to_ties(k, orc):
     bs = small_batch(6, 2, 400, ghosts=True)
     ctx = ctx_for(k, bs.det)
