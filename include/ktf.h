@@ -146,8 +146,9 @@ typedef struct {
 int ktf_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, ktf_fit_mode mode,
             void *hip_stream);
 
-/* Time each launch shape of the fused fit (block size x plain/persistent) on
- * the given inputs and keep the fastest for this precision and size class;
+/* Time each launch shape of the fused fit (block size 64..512 x plain or
+ * persistent x a register budget of 1, 2 or 3 waves per SIMD) on the given
+ * inputs and keep the fastest for this precision and size class;
  * KTF_FIT_AUTO then uses it.  Runs synchronously on hip_stream and
  * overwrites out. */
 int ktf_autotune_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, void *hip_stream);

@@ -65,9 +65,9 @@ static int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* o
 }
 
 // blocks per CU for the persistent kernel, from the occupancy calculator
-int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs);
+int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves);
 
-static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode, int bs,
+static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode, int bs, int waves,
                    bool persistent, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (mode == KTF_FIT_SWEEP || mode == KTF_FIT_SWEEP_GRAPH) {
@@ -119,11 +119,11 @@ static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode,
       return hip_fail(c, e, "counters");
     a.counters = static_cast<unsigned long long*>(c->counters.p);
     a.tile_count = (a.n + bs - 1) / bs;
-    pblocks = persistent_blocks(c, prec, bs) * c->n_cu;
+    pblocks = persistent_blocks(c, prec, bs, waves) * c->n_cu;
     if (pblocks <= 0) pblocks = c->n_cu;
     if ((e = launch_fill_u64(a.counters, 1, 0ull, st)) != hipSuccess) return hip_fail(c, e, "fill");
   }
-  e = launch_fit_fused(a, prec, bs, persistent, pblocks, st);
+  e = launch_fit_fused(a, prec, bs, waves, persistent, pblocks, st);
   return e == hipSuccess ? KTF_OK : hip_fail(c, e, "fit launch");
 }
 
@@ -196,13 +196,14 @@ int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mod
   if (in->n == 0) return KTF_OK;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   FitArgs a = make_fit_args(c, in, out);
-  int bs = 256;
+  int bs = 256, waves = 1;
   bool persistent = false;
   switch (mode) {
     case KTF_FIT_AUTO: {
       auto it = c->tuned.find({(int)in->prec, size_class(in->n)});
       if (it != c->tuned.end()) {
         bs = it->second.block;
+        waves = it->second.waves;
         persistent = it->second.persistent;
       }
       break;
@@ -216,7 +217,7 @@ int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mod
       break;
     default: return fail(c, KTF_EINVAL, "ktf_fit: unknown mode %d", (int)mode);
   }
-  return run_fit(c, a, in->prec, mode, bs, persistent, st);
+  return run_fit(c, a, in->prec, mode, bs, waves, persistent, st);
 }
 
 int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* hip_stream) {
@@ -231,13 +232,15 @@ int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* h
   TunedShape best;
   best.ms = 1e30f;
   for (int bs : kBlockSizes) {
-    for (int pers = 0; pers < 2; ++pers) {
-      rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, pers != 0, st);  // warm-up
+    for (int w = 0; w < 2 * kWaveChoices && rc == 0; ++w) {
+      const int pers = w & 1, waves = 1 + w / 2;
+      rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, waves, pers != 0, st);  // warm-up
       if (rc) break;
       float tot = 0.f;
       const int reps = 3;
       (void)hipEventRecord(e0, st);
-      for (int r = 0; r < reps && rc == 0; ++r) rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, pers != 0, st);
+      for (int r = 0; r < reps && rc == 0; ++r)
+        rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, waves, pers != 0, st);
       (void)hipEventRecord(e1, st);
       if (rc) break;
       if (hipEventSynchronize(e1) != hipSuccess) {
@@ -249,8 +252,9 @@ int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* h
       if (ms < best.ms) {
         best.ms = ms;
         best.block = bs;
+        best.waves = waves;
         best.persistent = pers != 0;
-        best.persistent_blocks = pers ? persistent_blocks(c, in->prec, bs) : 0;
+        best.persistent_blocks = pers ? persistent_blocks(c, in->prec, bs, waves) : 0;
       }
     }
     if (rc) break;
@@ -266,10 +270,12 @@ int ktf_tuned_shape(ktf_ctx* c, ktf_precision prec, int64_t n, char* buf, size_t
   if (!c || !buf || len == 0) return KTF_EINVAL;
   auto it = c->tuned.find({(int)prec, size_class(n)});
   if (it == c->tuned.end()) {
-    snprintf(buf, len, "{\"block\": 256, \"persistent\": false, \"tuned\": false}");
+    snprintf(buf, len, "{\"block\": 256, \"waves_per_simd\": 1, \"persistent\": false, \"tuned\": false}");
   } else {
-    snprintf(buf, len, "{\"block\": %d, \"persistent\": %s, \"blocks_per_cu\": %d, \"ms\": %.4f, \"tuned\": true}",
-             it->second.block, it->second.persistent ? "true" : "false",
+    snprintf(buf, len,
+             "{\"block\": %d, \"waves_per_simd\": %d, \"persistent\": %s, \"blocks_per_cu\": %d, "
+             "\"ms\": %.4f, \"tuned\": true}",
+             it->second.block, it->second.waves, it->second.persistent ? "true" : "false",
              it->second.persistent_blocks, it->second.ms);
   }
   return KTF_OK;

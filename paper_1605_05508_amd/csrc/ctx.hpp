@@ -44,6 +44,7 @@ struct DevBuf {
 
 struct TunedShape {
   int block = 256;
+  int waves = 1;  // waves per SIMD the registers must allow (1: compiler's choice)
   bool persistent = false;
   int persistent_blocks = 0;
   float ms = 0.f;

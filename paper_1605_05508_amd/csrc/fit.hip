@@ -110,16 +110,18 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
   a.status[i] = status;
 }
 
-template <typename TS, typename TP, typename TC, int BS>
-__global__ __launch_bounds__(BS) void fit_fused_kernel(FitArgs a) {
+// W: the waves per SIMD the register allocation must allow (1 leaves it to
+// the compiler; more trades registers, and maybe spills, for latency hiding)
+template <typename TS, typename TP, typename TC, int BS, int W>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_fused_kernel(FitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < a.n) fit_one_track<TS, TP, TC>(a, i);
 }
 
 // Persistent blocks: every block loops taking the next tile of BS tracks
 // from counters[0]; all waves leave once the tile index passes tile_count.
-template <typename TS, typename TP, typename TC, int BS>
-__global__ __launch_bounds__(BS) void fit_persistent_kernel(FitArgs a) {
+template <typename TS, typename TP, typename TC, int BS, int W>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_persistent_kernel(FitArgs a) {
   __shared__ long long tile;
   for (;;) {
     if (threadIdx.x == 0) tile = (long long)atomicAdd(&a.counters[0], 1ull);
@@ -239,35 +241,47 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
   return hipGetLastError();
 }
 
-template <typename TS, typename TP, typename TC, int BS>
+template <typename TS, typename TP, typename TC, int BS, int W>
 static hipError_t launch_fused_bs(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
   if (persistent) {
-    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, TC, BS>), dim3(pblocks), dim3(BS), 0, st, a);
+    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, TC, BS, W>), dim3(pblocks), dim3(BS), 0, st, a);
   } else {
     const int64_t nb = (a.n + BS - 1) / BS;
-    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS>), dim3((unsigned)nb), dim3(BS), 0, st, a);
+    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS, W>), dim3((unsigned)nb), dim3(BS), 0, st, a);
   }
   return hipGetLastError();
 }
 
-template <typename TS, typename TP, typename TC>
-static hipError_t launch_fused_t(const FitArgs& a, int bs, bool persistent, int pblocks,
-                                 hipStream_t st) {
+template <typename TS, typename TP, typename TC, int W>
+static hipError_t launch_fused_w(const FitArgs& a, int bs, bool persistent, int pblocks, hipStream_t st) {
   switch (bs) {
-    case 64: return launch_fused_bs<TS, TP, TC, 64>(a, persistent, pblocks, st);
-    case 128: return launch_fused_bs<TS, TP, TC, 128>(a, persistent, pblocks, st);
-    case 256: return launch_fused_bs<TS, TP, TC, 256>(a, persistent, pblocks, st);
-    case 512: return launch_fused_bs<TS, TP, TC, 512>(a, persistent, pblocks, st);
+    case 64: return launch_fused_bs<TS, TP, TC, 64, W>(a, persistent, pblocks, st);
+    case 128: return launch_fused_bs<TS, TP, TC, 128, W>(a, persistent, pblocks, st);
+    case 256: return launch_fused_bs<TS, TP, TC, 256, W>(a, persistent, pblocks, st);
+    case 512: return launch_fused_bs<TS, TP, TC, 512, W>(a, persistent, pblocks, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, bool persistent,
+template <typename TS, typename TP, typename TC>
+static hipError_t launch_fused_t(const FitArgs& a, int bs, int waves, bool persistent, int pblocks,
+                                 hipStream_t st) {
+  switch (waves) {
+    case 1: return launch_fused_w<TS, TP, TC, 1>(a, bs, persistent, pblocks, st);
+    case 2: return launch_fused_w<TS, TP, TC, 2>(a, bs, persistent, pblocks, st);
+    case 3: return launch_fused_w<TS, TP, TC, 3>(a, bs, persistent, pblocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, int waves, bool persistent,
                             int persistent_blocks, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  if (prec == KTF_FP64) return launch_fused_t<double, double, double>(a, bs, persistent, persistent_blocks, st);
-  if (prec == KTF_FP32_PROP) return launch_fused_t<float, float, double>(a, bs, persistent, persistent_blocks, st);
-  return launch_fused_t<float, float, float>(a, bs, persistent, persistent_blocks, st);
+  if (prec == KTF_FP64)
+    return launch_fused_t<double, double, double>(a, bs, waves, persistent, persistent_blocks, st);
+  if (prec == KTF_FP32_PROP)
+    return launch_fused_t<float, float, double>(a, bs, waves, persistent, persistent_blocks, st);
+  return launch_fused_t<float, float, float>(a, bs, waves, persistent, persistent_blocks, st);
 }
 
 hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hipStream_t st) {
@@ -285,24 +299,34 @@ hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hip
 
 namespace ktf {
 
-template <typename TS, typename TP, typename TC>
-static int occ_blocks(int bs) {
+template <typename TS, typename TP, typename TC, int W>
+static int occ_blocks_w(int bs) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (bs) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 64>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 128>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 256>, 256, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 512>, 512, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 64, W>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 128, W>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 256, W>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 512, W>, 512, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;
 }
 
-int persistent_blocks(ktf_ctx*, ktf_precision prec, int bs) {
-  if (prec == KTF_FP64) return occ_blocks<double, double, double>(bs);
-  if (prec == KTF_FP32_PROP) return occ_blocks<float, float, double>(bs);
-  return occ_blocks<float, float, float>(bs);
+template <typename TS, typename TP, typename TC>
+static int occ_blocks(int bs, int waves) {
+  switch (waves) {
+    case 1: return occ_blocks_w<TS, TP, TC, 1>(bs);
+    case 2: return occ_blocks_w<TS, TP, TC, 2>(bs);
+    case 3: return occ_blocks_w<TS, TP, TC, 3>(bs);
+    default: return 0;
+  }
+}
+
+int persistent_blocks(ktf_ctx*, ktf_precision prec, int bs, int waves) {
+  if (prec == KTF_FP64) return occ_blocks<double, double, double>(bs, waves);
+  if (prec == KTF_FP32_PROP) return occ_blocks<float, float, double>(bs, waves);
+  return occ_blocks<float, float, float>(bs, waves);
 }
 
 }  // namespace ktf

@@ -62,7 +62,13 @@ template <> KTF_HD float rcp<float>(float x) {
 
 template <typename T> KTF_HD T ksqrt(T x);
 template <> KTF_HD double ksqrt<double>(double x) { return sqrt(x); }
-template <> KTF_HD float ksqrt<float>(float x) { return sqrtf(x); }
+template <> KTF_HD float ksqrt<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);  // hardware square root, 1 ulp (arguments are normal or 0)
+#else
+  return sqrtf(x);
+#endif
+}
 
 template <typename T> KTF_HD void ksincos(T x, T* s, T* c);
 template <> KTF_HD void ksincos<double>(double x, double* s, double* c) { sincos(x, s, c); }

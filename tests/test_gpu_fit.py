@@ -210,15 +210,19 @@ def test_empty_and_single(ctx10, orc):
 
 
 def test_autotune_keeps_results(ctx10):
+    """Whatever block size, persistence and register budget the autotuner
+    picks, the results are bitwise those of the default fused launch."""
     rng = np.random.default_rng(34)
     fs = tg.make_fit_set(rng, 20000, tg.barrel(10))
-    d = fit_inputs(fs, "fp32b")
-    ref = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="fused"), fs.n)
-    ctx10.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"])
-    assert '"tuned": true' in ctx10.tuned_shape("fp32b", fs.n)
-    g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="auto"), fs.n)
-    for key in ref:
-        assert np.array_equal(ref[key], g[key])
+    for prec in ("fp32b", "fp64", "fp32p"):
+        d = fit_inputs(fs, "fp64" if prec == "fp64" else "fp32b")
+        pp = None if prec == "fp32b" else prec
+        ref = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="fused", prec=pp), fs.n)
+        ctx10.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], prec=pp)
+        assert '"tuned": true' in ctx10.tuned_shape(prec, fs.n)
+        g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="auto", prec=pp), fs.n)
+        for key in ref:
+            assert np.array_equal(ref[key], g[key]), (prec, key, ctx10.tuned_shape(prec, fs.n))
 
 
 def test_bad_arguments_raise(ctx10):
