@@ -40,7 +40,8 @@ def build_lib(force: bool = True) -> str:
 
 class _Geom(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("radii", C.POINTER(C.c_double)), ("bz", C.c_double),
-                ("sigma_r", C.c_double), ("sigma_rphi", C.c_double), ("sigma_z", C.c_double)]
+                ("sigma_r", C.c_double), ("sigma_rphi", C.c_double), ("sigma_z", C.c_double),
+                ("x0", C.POINTER(C.c_double)), ("eloss", C.c_double), ("mass", C.c_double)]
 
 
 class _BuildParams(C.Structure):
@@ -68,11 +69,16 @@ def _d(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def _geom(det):
+def _geom(det, material=True):
+    """material=False fits as if the detector had no material (for tests
+    that show what ignoring it costs)."""
     radii = _d(det.radii)
+    x0 = getattr(det, "x0", 0.0)
+    x0 = _d(np.broadcast_to(np.asarray(x0, dtype=np.float64), (len(det.radii),))) \
+        if material and np.any(np.asarray(x0) > 0) else None
     g = _Geom(len(det.radii), _p(radii, C.c_double), det.bz, det.sigma_r, det.sigma_rphi,
-              det.sigma_z)
-    return g, radii  # keep radii alive
+              det.sigma_z, _p(x0, C.c_double), getattr(det, "eloss", 0.0), getattr(det, "mass", 0.13957))
+    return g, (radii, x0)  # keep the arrays alive
 
 
 def default_threads() -> int:
@@ -101,6 +107,16 @@ def propagate(x, q, bz, r, nearest=False):
                              C.c_int(1 if nearest else 0), _p(xo, C.c_double),
                              _p(F, C.c_double), C.byref(s))
     return xo, F.reshape(6, 6), s.value, rc
+
+
+def material(det, layer, x, P):
+    """Material of one layer (see orc_material): returns (x', P' [6,6])."""
+    g, keep = _geom(det)
+    xo = np.zeros(6)
+    Po = np.zeros(36)
+    lib().orc_material(C.byref(g), C.c_int(int(layer)), _p(_d(x), C.c_double),
+                       _p(_d(P).ravel(), C.c_double), _p(xo, C.c_double), _p(Po, C.c_double))
+    return xo, Po.reshape(6, 6)
 
 
 def cov_propagate(P, F):
@@ -155,14 +171,14 @@ def pack(P):
 
 # ------------------------------------------------------------------- fit
 
-def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None):
+def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=True):
     """Batched FP64 fit.  state[6,n], cov[21,n], q[n], hits[L,3,n], valid[L,n].
 
     Returns dict(state[6,n], cov[21,n], chi2[n], nupd[n], status[n]).
     """
     n = q.shape[0]
     L = len(det.radii)
-    g, radii = _geom(det)
+    g, radii = _geom(det, material)
     st = _d(np.asarray(state).T)
     cv = _d(np.asarray(cov).T)
     qq = np.ascontiguousarray(q, dtype=np.int8)
@@ -181,9 +197,9 @@ def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None):
     return dict(state=so.T.copy(), cov=co.T.copy(), chi2=c2, nupd=nu, status=stt)
 
 
-def fit(fs, nthreads=None):
+def fit(fs, nthreads=None, material=True):
     """Fit a trackgen.FitSet."""
-    return fit_arrays(fs.det, fs.state, fs.cov, fs.q, fs.hits, fs.valid, nthreads)
+    return fit_arrays(fs.det, fs.state, fs.cov, fs.q, fs.hits, fs.valid, nthreads, material)
 
 
 # ---------------------------------------------------------------- binning

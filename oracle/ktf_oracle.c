@@ -307,6 +307,50 @@ int orc_update(const double xp[6], const double Pp[36], const double m[3],
 
 /* --------------------------------------------------------------------- fit */
 
+void orc_material(const orc_geom *g, int l, const double x[6], const double P[36],
+                  double xo[6], double Po[36]) {
+  memcpy(xo, x, 6 * sizeof(double));
+  memcpy(Po, P, 36 * sizeof(double));
+  if (!g->x0 || g->x0[l] <= 0.0) return;
+  const double *p = x + 3;
+  const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  const double pmag = sqrt(p2);
+  const double r = sqrt(x[0] * x[0] + x[1] * x[1]);
+  const double pn = (x[0] * p[0] + x[1] * p[1]) / r; /* momentum along the normal */
+  const double t = g->x0[l] * pmag / fabs(pn);
+  const double m2 = g->mass * g->mass;
+  const double E = sqrt(p2 + m2);
+  const double beta = pmag / E;
+  const double theta0 = 0.0136 / (beta * pmag) * sqrt(t) * (1.0 + 0.038 * log(t / (beta * beta)));
+  /* process noise on the momentum block */
+  double Q[36] = {0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      Q[(3 + i) * 6 + 3 + j] = theta0 * theta0 * ((i == j ? p2 : 0.0) - p[i] * p[j]);
+  double A[36];
+  for (int i = 0; i < 36; ++i) A[i] = P[i] + Q[i];
+  /* mean energy loss: |p| -> g(|p|) = sqrt((E - eloss t)^2 - m^2) along the
+   * same direction, t held at its value for this state; its Jacobian on the
+   * momentum is f (I - u u^T) + g'(|p|) u u^T with u = p/|p|, f = g/|p| and
+   * g' = (E - eloss t) |p| / (g E) */
+  double f = 1.0, gp = 1.0;
+  if (g->eloss > 0.0) {
+    const double E2 = E - g->eloss * t;
+    const double gm = E2 > g->mass ? sqrt(E2 * E2 - m2) : 0.0;
+    f = gm / pmag;
+    gp = gm > 0.0 ? E2 * pmag / (gm * E) : 0.0;
+  }
+  double T[36] = {0}, Tt[36], TA[36];
+  for (int i = 0; i < 3; ++i) T[i * 6 + i] = 1.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      T[(3 + i) * 6 + 3 + j] = (i == j ? f : 0.0) + (gp - f) * p[i] * p[j] / p2;
+  transpose(T, Tt, 6, 6);
+  matmul(T, A, TA, 6, 6, 6);
+  matmul(TA, Tt, Po, 6, 6, 6);
+  for (int i = 0; i < 3; ++i) xo[3 + i] = f * x[3 + i];
+}
+
 int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], int q,
                   const double *hits, const uint8_t *valid,
                   double xo[6], double Po[21], double *chi2, int32_t *nupd,
@@ -324,12 +368,18 @@ int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], in
   int n = 0;
   uint32_t st = 0;
   for (int l = 0; l < L_end; ++l) {
-    double xp[6], F[36], Pp[36], s;
-    if (orc_propagate(x, q, g->bz, g->radii[l], l == 0, xp, F, &s)) {
+    double xp[6], F[36], Pp[36], s, xm[6], Pm[36];
+    if (l > 0) {
+      orc_material(g, l - 1, x, P, xm, Pm);
+    } else {
+      memcpy(xm, x, sizeof xm);
+      memcpy(Pm, P, sizeof Pm);
+    }
+    if (orc_propagate(xm, q, g->bz, g->radii[l], l == 0, xp, F, &s)) {
       st |= ORC_NO_REACH;
       break;
     }
-    orc_cov_propagate(P, F, Pp);
+    orc_cov_propagate(Pm, F, Pp);
     if (!valid || valid[l]) {
       const double *m = hits + 3 * l;
       double V[9], xn[6], Pn[36], c2;
@@ -525,14 +575,20 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
   int nlive = 1;
   int seed_reached = 0;
   for (int l = 0; l < NSL && l < L; ++l) {
-    double xp[6], F[36], Pp[36], s;
-    if (orc_propagate(c->x, q, g->bz, g->radii[l], l == 0, xp, F, &s)) {
+    double xp[6], F[36], Pp[36], s, xm[6], Pm[36];
+    if (l > 0) {
+      orc_material(g, l - 1, c->x, c->P, xm, Pm);
+    } else {
+      memcpy(xm, c->x, sizeof xm);
+      memcpy(Pm, c->P, sizeof Pm);
+    }
+    if (orc_propagate(xm, q, g->bz, g->radii[l], l == 0, xp, F, &s)) {
       c->status |= ORC_NO_REACH;
       nlive = 0;
       break;
     }
     seed_reached = l + 1;
-    orc_cov_propagate(c->P, F, Pp);
+    orc_cov_propagate(Pm, F, Pp);
     int h = seed_hit[l];
     memcpy(c->x, xp, sizeof xp);
     memcpy(c->P, Pp, sizeof Pp);
@@ -572,16 +628,17 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
     nrec = 0;
     for (int ci = 0; ci < nlive; ++ci) {
       orc_cand *p = &cur[ci];
-      double F[36];
+      double F[36], xm[6], Pm[36];
       double s;
       prop_ok[ci] = 0;
       int finished = 0;
-      if (orc_propagate(p->x, q, g->bz, g->radii[l], 0, prop[ci].x, F, &s)) {
+      orc_material(g, l - 1, p->x, p->P, xm, Pm);
+      if (orc_propagate(xm, q, g->bz, g->radii[l], 0, prop[ci].x, F, &s)) {
         p->status |= ORC_NO_REACH;
         finished = 1;
       } else {
         prop_ok[ci] = 1;
-        orc_cov_propagate(p->P, F, prop[ci].P);
+        orc_cov_propagate(Pm, F, prop[ci].P);
         int ncompat = 0;
         for (int64_t hi = h0; hi < h1; ++hi) {
           const double *m = hits + 3 * hi;

@@ -37,6 +37,10 @@ typedef struct {
   const double *radii;    /* [n_layers], increasing */
   double bz;              /* tesla */
   double sigma_r, sigma_rphi, sigma_z;  /* hit resolution (cm) */
+  const double *x0;       /* [n_layers] layer thickness in radiation lengths
+                             at normal incidence; NULL = no material */
+  double eloss;           /* mean energy loss per radiation length of path, GeV */
+  double mass;            /* particle mass hypothesis, GeV */
 } orc_geom;
 
 typedef struct {
@@ -57,6 +61,21 @@ int orc_propagate(const double x[6], int q, double bz, double r, int nearest,
 /* transport at a fixed transverse arc length s (no surface constraint) */
 void orc_transport(const double x[6], int q, double bz, double s, double xo[6]);
 
+/* material of layer l for a state x on that layer, applied when the track
+ * leaves the layer for the next one (paper Sec. 2: the filter is what lets
+ * multiple-scattering estimates enter the fit).  With t = x0[l] |p| / |p.n|
+ * the path through the layer in radiation lengths (n the radial normal):
+ * multiple scattering as process noise Q = theta0^2 (|p|^2 I - p p^T) on the
+ * momentum block, theta0 from the Highland formula for unit charge,
+ * theta0 = 0.0136 / (beta p) sqrt(t) (1 + 0.038 ln(t / beta^2)); then the
+ * mean energy loss eloss * t, which takes |p| to p' = sqrt((E - eloss t)^2
+ * - m^2) along the same direction; with T its Jacobian (identity on the
+ * position, f (I - u u^T) + (dp'/d|p|) u u^T on the momentum, u = p/|p|,
+ * f = p'/|p|, t held fixed): Po = T (P + Q) T^T.  A layer with x0 <= 0, or
+ * x0 == NULL, leaves state and covariance unchanged. */
+void orc_material(const orc_geom *g, int l, const double x[6], const double P[36],
+                  double xo[6], double Po[36]);
+
 /* F P F^T with full 6x6 matrices */
 void orc_cov_propagate(const double P[36], const double F[36], double Po[36]);
 
@@ -74,7 +93,8 @@ int orc_chi2(const double xp[6], const double Pp[36], const double m[3],
              const double V[9], double *chi2);
 
 /* fit of one track over hits[L][3] with valid[L] (NULL = all valid).  The
- * fit ends at the last layer with a valid hit.  P0 and Po are packed 21. */
+ * fit ends at the last layer with a valid hit.  P0 and Po are packed 21.
+ * Between layers l-1 and l the material of layer l-1 is applied first. */
 int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], int q,
                   const double *hits, const uint8_t *valid,
                   double xo[6], double Po[21], double *chi2, int32_t *nupd,

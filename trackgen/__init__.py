@@ -72,6 +72,9 @@ class Detector:
     sigma_rphi: float = 0.01
     sigma_z: float = 0.1
     sigma_r: float = 0.01  # radial hit variance used by the filter only; hits are not smeared radially
+    x0: float = 0.0        # thickness of every layer in radiation lengths at normal incidence
+    eloss: float = 0.0     # mean energy loss per radiation length of path (GeV)
+    mass: float = 0.13957  # particle mass (GeV), for beta in the scattering width and the energy loss
 
     @property
     def n_layers(self) -> int:
@@ -179,6 +182,108 @@ def truth_crossings(truth: dict, det: Detector):
 
     _chunked(work, n)
     return pos, mom, reached
+
+
+def _cross_layer(x, y, z, px, py, pz, k, r):
+    """First forward crossing of the helix from (x, y, z, p) with the cylinder
+    of radius r (the two-circle intersection of truth_crossings, from an
+    arbitrary start).  Returns x, y, z, px, py, pz at the crossing and ok."""
+    pt = np.hypot(px, py)
+    R = pt / np.abs(k)
+    cx = x + py / k
+    cy = y - px / k
+    d = np.hypot(cx, cy)
+    d2mR2 = x * x + y * y + 2.0 * (x * py - y * px) / k
+    ux, uy = cx / d, cy / d
+    r0x, r0y = x - cx, y - cy
+    a = (r * r + d2mR2) / (2.0 * d)
+    h2 = r * r - a * a
+    ok = h2 >= 0.0
+    h = np.sqrt(np.where(ok, h2, 0.0))
+    best_s = np.full(x.shape, np.inf)
+    best_x = np.zeros(x.shape)
+    best_y = np.zeros(x.shape)
+    for sgn in (1.0, -1.0):
+        X = a * ux - sgn * h * uy
+        Y = a * uy + sgn * h * ux
+        rx, ry = X - cx, Y - cy
+        cross = r0x * ry - r0y * rx
+        dot = r0x * rx + r0y * ry
+        dlt = np.arctan2(cross, dot)
+        ang = np.where(k > 0, np.where(dlt <= 0, dlt, dlt - 2 * math.pi),
+                       np.where(dlt >= 0, dlt, dlt + 2 * math.pi))
+        s = np.abs(ang) * R
+        better = s < best_s
+        best_s = np.where(better, s, best_s)
+        best_x = np.where(better, X, best_x)
+        best_y = np.where(better, Y, best_y)
+    theta = -k * best_s / pt
+    c, sn = np.cos(theta), np.sin(theta)
+    return best_x, best_y, z + best_s * pz / pt, px * c - py * sn, py * c + px * sn, pz, ok
+
+
+def scatter_layer(rng, x, y, px, py, pz, det: Detector):
+    """Cross one layer's material: rotate p by two independent Gaussian
+    angles of width theta0 (Highland formula, unit charge) in the plane
+    perpendicular to p, then remove the mean energy loss.  The path through
+    the layer is x0 |p| / |p.n| radiation lengths (n the radial normal)."""
+    p2 = px * px + py * py + pz * pz
+    p = np.sqrt(p2)
+    r = np.hypot(x, y)
+    t = det.x0 * p / np.abs((x * px + y * py) / r)
+    E = np.sqrt(p2 + det.mass ** 2)
+    beta = p / E
+    th0 = 0.0136 / (beta * p) * np.sqrt(t) * (1.0 + 0.038 * np.log(t / beta ** 2))
+    pt = np.hypot(px, py)
+    ex, ey, ez = px / p, py / p, pz / p
+    ux, uy, uz = py / pt, -px / pt, np.zeros_like(pt)   # unit, perpendicular to p and z
+    vx, vy, vz = ey * uz - ez * uy, ez * ux - ex * uz, ex * uy - ey * ux
+    a = rng.normal(0.0, 1.0, p.shape) * th0
+    b = rng.normal(0.0, 1.0, p.shape) * th0
+    dx, dy, dz = ex + a * ux + b * vx, ey + a * uy + b * vy, ez + a * uz + b * vz
+    dn = np.sqrt(dx * dx + dy * dy + dz * dz)
+    pm = p
+    if det.eloss > 0.0:
+        E2 = E - det.eloss * t
+        pm = np.where(E2 > det.mass, np.sqrt(np.maximum(E2 * E2 - det.mass ** 2, 0.0)), 0.0)
+    return pm * dx / dn, pm * dy / dn, pm * dz / dn
+
+
+def truth_crossings_material(truth: dict, det: Detector, rng: np.random.Generator):
+    """Layer by layer from the vertex: the helix to the next cylinder (closed
+    form), then that layer's material (scatter_layer) before going on.  The
+    crossing point and momentum on each layer are taken before its material.
+    Returns pos[L,3,n], mom[L,3,n], reached[L,n] like truth_crossings."""
+    n = truth["vx"].shape[0]
+    L = det.n_layers
+    pos = np.zeros((L, 3, n))
+    mom = np.zeros((L, 3, n))
+    reached = np.zeros((L, n), dtype=bool)
+    x, y, z = truth["vx"].copy(), truth["vy"].copy(), truth["vz"].copy()
+    px, py, pz = truth["px"].copy(), truth["py"].copy(), truth["pz"].copy()
+    k = C_LIGHT * truth["q"].astype(np.float64) * det.bz
+    alive = np.ones(n, dtype=bool)
+    for li, r in enumerate(det.radii):
+        if li > 0:
+            npx, npy, npz = scatter_layer(rng, x, y, px, py, pz, det)
+            px, py, pz = np.where(alive, npx, px), np.where(alive, npy, py), np.where(alive, npz, pz)
+            alive &= np.hypot(px, py) > 0.0
+        with np.errstate(invalid="ignore", divide="ignore"):
+            cx_, cy_, cz_, cpx, cpy, cpz, ok = _cross_layer(x, y, z, px, py, pz, k, r)
+        alive &= ok
+        reached[li] = alive
+        x, y, z = np.where(alive, cx_, x), np.where(alive, cy_, y), np.where(alive, cz_, z)
+        px, py, pz = np.where(alive, cpx, px), np.where(alive, cpy, py), np.where(alive, cpz, pz)
+        pos[li] = np.stack([x, y, z])
+        mom[li] = np.stack([px, py, pz])
+    return pos, mom, reached
+
+
+def crossings(truth: dict, det: Detector, rng: np.random.Generator):
+    """Truth crossings, through the layers' material when the detector has any."""
+    if det.x0 > 0.0:
+        return truth_crossings_material(truth, det, rng)
+    return truth_crossings(truth, det)
 
 
 def smear_hits(rng: np.random.Generator, pos, det: Detector):
@@ -334,7 +439,7 @@ class FitSet:
 def make_fit_set(rng, n, det: Detector, *, pt_range=(0.5, 10.0), pt_log=False,
                  seed_mode="smeared", drop_out_of_z=True):
     truth = sample_truth(rng, n, pt_range=pt_range, pt_log=pt_log)
-    pos, mom, reached = truth_crossings(truth, det)
+    pos, mom, reached = crossings(truth, det, rng)
     hits = smear_hits(rng, pos, det)
     valid = reached.copy()
     if drop_out_of_z:
@@ -471,7 +576,7 @@ def make_build_event(rng, n_tracks, det: Detector, *, noise_frac=0.2, seed_mode=
     phi uniform in [-pi, pi) and z uniform in [-z_half, z_half) on the cylinder.
     """
     truth = sample_truth(rng, n_tracks, pt_range=pt_range, pt_log=pt_log)
-    pos, mom, reached = truth_crossings(truth, det)
+    pos, mom, reached = crossings(truth, det, rng)
     hits_t = smear_hits(rng, pos, det)
     present = reached & (np.abs(pos[:, 2, :]) < det.z_half)
     L = det.n_layers
