@@ -85,10 +85,11 @@ def parse():
     ap.add_argument("--profile", choices=["fit", "sweep", "build", "copy"], default=None,
                     help="only one timed loop, for rocprofv3 runs (copy: a plain copy of "
                          "known size to calibrate the HBM byte counters)")
-    ap.add_argument("--workload", choices=["fit", "uneven", "dense_events"], default="fit",
+    ap.add_argument("--workload", choices=["fit", "uneven", "dense_events", "material"], default="fit",
                     help="fit: the headline line; uneven: events of uneven size in one "
                          "launch versus per-event launches; dense_events: building on "
-                         "20,000-track events, combinatorial and best-hit")
+                         "20,000-track events, combinatorial and best-hit; material: the "
+                         "fit at scale through layer material")
     ap.add_argument("--no-build", action="store_true", help="skip the building measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-events", type=int, default=200)
@@ -251,6 +252,55 @@ def dense_events_workload(args):
                       "building": res}), flush=True)
 
 
+def material_workload(args):
+    """1e6 tracks x 10 layers through 2% X0 layers with energy loss (multiple
+    scattering as process noise, mean energy loss): fused fit throughput in
+    the three precisions, against the FP64 oracle on a sample."""
+    import torch
+    import paper_1605_05508_amd as ktf
+    import trackgen as tg
+    from tests.helpers import fit_inputs, fp32_errors, pulls
+    print("[bench] generating tracks through material", file=sys.stderr, flush=True)
+    fs = tg.config2_material()
+    n, L = fs.n, fs.det.n_layers
+    ctx = ktf.Context.for_detector(fs.det)
+    res = {}
+    outs = {}
+    for prec in ("fp32b", "fp32p", "fp64"):
+        d = fit_inputs(fs, "fp64" if prec == "fp64" else "fp32b")
+        pp = None if prec == "fp32b" else prec
+        out = ctx.alloc_fit_out(n, d["state"].shape[1], d["state"].dtype)
+        ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out, prec=pp)
+        run = lambda: ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out, prec=pp)
+        ms, _ = timed_loop(run, args.steps, args.warmup, torch)
+        torch.cuda.synchronize()
+        outs[prec] = {k: v.cpu().numpy()[..., :n] for k, v in out.items()}
+        res[prec] = {"ms": round(ms, 4), "tracks_per_s": round(n / (ms * 1e-3)),
+                     "launch": ctx.tuned_shape(prec, n)}
+        del d, out
+    if not args.no_cpu:
+        import oracle
+        m = 100_000
+        sub = fs.subset(np.arange(m))
+        o = oracle.fit(sub)
+        po = pulls(o["state"], o["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
+        for prec, g in outs.items():
+            gs = {k: v[..., :m] for k, v in g.items()}
+            e_pos, e_mom = fp32_errors(gs, o, 40.0)
+            pg = pulls(gs["state"], gs["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
+            res[prec].update({"e_mom_max": float(e_mom.max()), "e_mom_p999": float(np.quantile(e_mom, 0.999)),
+                              "pull_rms_ratio": {kk: round(float(np.sqrt(np.mean(pg[kk] ** 2)) /
+                                                                 np.sqrt(np.mean(po[kk] ** 2))), 5) for kk in pg}})
+        res["oracle_pull_rms"] = {kk: round(float(np.sqrt(np.mean(v ** 2))), 4) for kk, v in po.items()}
+        res["oracle_sample"] = m
+    print(json.dumps({"metric": "fitted tracks/s through layer material", "value": res["fp32b"]["tracks_per_s"],
+                      "unit": "tracks/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32+f64",
+                      "data": "synthetic",
+                      "config": {"workload": "1,000,000 tracks, 10 barrel layers r=4..40 cm of 2% X0 each, "
+                                             "energy loss 0.036 GeV per X0, Bz=3.8 T, pT log-uniform 0.5-100 GeV"},
+                      "detail": res}), flush=True)
+
+
 def uneven_workload(args):
     """Events of uneven size: 2,000 events with log-normal track counts
     (median 3,000, sigma 0.8, clipped 50-50,000), 6-17 hits per track with
@@ -392,6 +442,9 @@ def main():
         return
     if args.workload == "dense_events":
         dense_events_workload(args)
+        return
+    if args.workload == "material":
+        material_workload(args)
         return
     import torch
     import paper_1605_05508_amd as ktf

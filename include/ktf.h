@@ -98,6 +98,20 @@ typedef struct {
   double chi2_cut;         /* a hit is compatible when its chi2 increment < cut  */
   uint64_t hbm_budget_bytes; /* serving: device bytes the in-flight events may use */
   int32_t max_inflight;    /* serving: events on the device at once              */
+  /* Material (Sec. 2: what the Kalman filter lets a fit take into account).
+   * When a track leaves layer l for the next one it crosses the layer's
+   * material: t = layer_x0[l] |p| / |p.n| radiation lengths (n the radial
+   * normal).  Multiple scattering enters as process noise on the momentum,
+   * theta0^2 (|p|^2 I - p p^T), theta0 from the Highland formula for unit
+   * charge, 0.0136 GeV / (beta p) sqrt(t) (1 + 0.038 ln(t / beta^2)) (meant
+   * for 1e-3 <= t <= 100); then the mean energy loss eloss_per_x0 * t moves
+   * |p| to sqrt((E - eloss t)^2 - m^2) along the same direction, with the
+   * covariance carried by the Jacobian of that map (t held fixed).  No
+   * material is applied before the first layer or after the last.        */
+  const double *layer_x0;  /* host [n_layers] thickness in radiation lengths at
+                              normal incidence, >= 0; NULL = no material       */
+  double eloss_per_x0;     /* mean energy loss per radiation length (GeV), >= 0 */
+  double mass;             /* particle mass hypothesis (GeV), > 0 when material */
 } ktf_config;
 
 /* Create a context on the current HIP device.  Returns KTF_EINVAL for an

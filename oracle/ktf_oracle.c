@@ -160,7 +160,9 @@ int orc_propagate(const double x[6], int q, double bz, double r, int nearest,
     if (gp == 0.0) return ORC_NO_REACH;
     double ds = g / gp;
     s -= ds;
-    if (fabs(ds) <= 1e-13) {
+    /* converged when the step is within 1e-12 (1 + |s|) cm: near grazing
+     * incidence g' is small and the rounding of g/g' alone reaches ~1e-13 */
+    if (fabs(ds) <= 1e-12 * (1.0 + fabs(s))) {
       converged = 1;
       break;
     }

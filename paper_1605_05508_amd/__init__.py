@@ -41,7 +41,8 @@ class _Config(C.Structure):
                 ("sigma_z", C.c_double), ("n_zbins", C.c_int32), ("n_phibins", C.c_int32),
                 ("max_cands", C.c_int32), ("max_missed", C.c_int32), ("n_seed_layers", C.c_int32),
                 ("chi2_cut", C.c_double), ("hbm_budget_bytes", C.c_uint64),
-                ("max_inflight", C.c_int32)]
+                ("max_inflight", C.c_int32), ("layer_x0", C.POINTER(C.c_double)),
+                ("eloss_per_x0", C.c_double), ("mass", C.c_double)]
 
 
 class _FitIn(C.Structure):
@@ -139,16 +140,25 @@ class Context:
     def __init__(self, radii: Sequence[float], *, bz=3.8, sigma_r=0.01, sigma_rphi=0.01,
                  sigma_z=0.1, z_half=100.0, n_zbins=64, n_phibins=512, max_cands=10,
                  max_missed=1, n_seed_layers=3, chi2_cut=30.0, hbm_budget_bytes=8 << 30,
-                 max_inflight=64):
+                 max_inflight=64, layer_x0=None, eloss_per_x0=0.0, mass=0.13957):
+        """layer_x0: per-layer material thickness in radiation lengths (a number
+        for all layers, a sequence, or None for no material)."""
         _torch()
         lib = load_library()
         self._lib = lib
         self.radii = [float(r) for r in radii]
         self.n_layers = len(self.radii)
         self._r = (C.c_double * max(1, self.n_layers))(*self.radii)
+        self._x0 = None
+        if layer_x0 is not None:
+            x0 = [float(layer_x0)] * self.n_layers if isinstance(layer_x0, (int, float)) else \
+                [float(v) for v in layer_x0]
+            if len(x0) != self.n_layers:
+                raise ValueError("layer_x0 needs one value per layer")
+            self._x0 = (C.c_double * self.n_layers)(*x0)
         cfg = _Config(self.n_layers, self._r, z_half, bz, sigma_r, sigma_rphi, sigma_z, n_zbins,
                       n_phibins, max_cands, max_missed, n_seed_layers, chi2_cut,
-                      int(hbm_budget_bytes), max_inflight)
+                      int(hbm_budget_bytes), max_inflight, self._x0, eloss_per_x0, mass)
         self.cfg = cfg
         h = C.c_void_p()
         rc = lib.ktf_create(C.byref(cfg), C.byref(h))
@@ -158,6 +168,9 @@ class Context:
 
     @classmethod
     def for_detector(cls, det, **kw):
+        x0 = getattr(det, "x0", 0.0)
+        if x0 > 0 and "layer_x0" not in kw:
+            kw.update(layer_x0=x0, eloss_per_x0=det.eloss, mass=det.mass)
         return cls(det.radii, bz=det.bz, sigma_r=det.sigma_r, sigma_rphi=det.sigma_rphi,
                    sigma_z=det.sigma_z, z_half=det.z_half, **kw)
 

@@ -43,6 +43,7 @@ FitArgs make_fit_args(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out) {
   a.hr.srphi2 = c->cfg.sigma_rphi * c->cfg.sigma_rphi;
   a.hr.sz2 = c->cfg.sigma_z * c->cfg.sigma_z;
   for (int l = 0; l < c->cfg.n_layers; ++l) a.radii[l] = c->radii[l];
+  a.mat = material_of(c);
   return a;
 }
 
@@ -145,10 +146,22 @@ int ktf_create(const ktf_config* cfg, ktf_ctx** out) {
       cfg->n_seed_layers < 1 || cfg->n_seed_layers > cfg->n_layers || cfg->n_zbins < 1 ||
       cfg->n_phibins < 1 || !(cfg->z_half > 0.0))
     return KTF_EINVAL;
+  bool material = false;
+  if (cfg->layer_x0) {
+    for (int l = 0; l < cfg->n_layers; ++l) {
+      if (!(cfg->layer_x0[l] >= 0.0) || !std::isfinite(cfg->layer_x0[l])) return KTF_EINVAL;
+      material = material || cfg->layer_x0[l] > 0.0;
+    }
+    if (material && (!(cfg->mass > 0.0) || !(cfg->eloss_per_x0 >= 0.0) || !std::isfinite(cfg->mass) ||
+                     !std::isfinite(cfg->eloss_per_x0)))
+      return KTF_EINVAL;
+  }
   ktf_ctx* c = new ktf_ctx();
   c->cfg = *cfg;
   c->radii.assign(cfg->layer_r, cfg->layer_r + cfg->n_layers);
   c->cfg.layer_r = c->radii.data();
+  if (material) c->x0.assign(cfg->layer_x0, cfg->layer_x0 + cfg->n_layers);
+  c->cfg.layer_x0 = material ? c->x0.data() : nullptr;
   hipError_t e = hipGetDevice(&c->device);
   hipDeviceProp_t prop;
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, c->device);

@@ -534,8 +534,10 @@ __device__ __forceinline__ bool block_row(const BuildArgs& a, int l, int64_t& c)
   return local < (int64_t)*region_ctr(a, l, r);
 }
 
-// seed phase: fit each seed over the seed layers with its own hits
-template <typename TS, typename TP>
+// seed phase: fit each seed over the seed layers with its own hits.  MAT:
+// the material of the layer being left goes onto a copy of the state, so
+// that a seed that cannot reach the next layer ends with its filtered state.
+template <typename TS, typename TP, bool MAT>
 __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = s < a.n_seeds;
@@ -562,13 +564,27 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
     for (int l = 0; l < NSL; ++l) {
       TrackState<TP> xp;
       Jac<TP> F;
-      if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], l == 0, xp, F)) {
-        status |= kNoReach;
-        break;
+      TP Pp[21];
+      if constexpr (MAT) {
+        TrackState<TP> xm = x;
+        TP Pm[21];
+#pragma unroll
+        for (int c = 0; c < 21; ++c) Pm[c] = P[c];
+        if (l > 0 && a.g.mat.x0[l - 1] > 0.0)
+          apply_material(a.g.mat.x0[l - 1], a.g.mat.eloss, a.g.mat.mass, xm, Pm);
+        if (!propagate<TP, BuildNewton<TP>::n>(xm, k, a.g.radii[l], l == 0, xp, F)) {
+          status |= kNoReach;
+          break;
+        }
+        cov_propagate(Pm, F, Pp);
+      } else {
+        if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], l == 0, xp, F)) {
+          status |= kNoReach;
+          break;
+        }
+        cov_propagate(P, F, Pp);
       }
       reached = l + 1;
-      TP Pp[21];
-      cov_propagate(P, F, Pp);
       const int g = e * L + l;
       const int32_t h0 = a.seed_hit[l * a.sp + s];
       // an index outside the layer's hit list counts as no hit
@@ -623,8 +639,9 @@ __device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32
   return c1 < c2 || (c1 == c2 && (uint32_t)h1 < (uint32_t)h2);
 }
 
-// One lane per live candidate (dense row c of the current buffer).
-template <typename TS, typename TP>
+// One lane per live candidate (dense row c of the current buffer).  MAT:
+// the layers carry material.
+template <typename TS, typename TP, bool MAT>
 __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, int cur) {
   int64_t c;
   if (!block_row(a, l - 1, c)) return;
@@ -640,6 +657,11 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
   const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
   TrackState<TP> xp;
   Jac<TP> F;
+  // the material of the layer being left (the stored candidate keeps its
+  // filtered state)
+  if constexpr (MAT) {
+    if (a.g.mat.x0[l - 1] > 0.0) apply_material(a.g.mat.x0[l - 1], a.g.mat.eloss, a.g.mat.mass, x, P);
+  }
   if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], false, xp, F)) {
     a.rcount[c] = -1;
     return;
@@ -1110,10 +1132,16 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nctr, bs)), dim3(bs), 0, st, reinterpret_cast<int32_t*>(a.ccount),
                      nctr, 0);
   hipLaunchKernelGGL(seed_event_kernel, dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
-  hipLaunchKernelGGL((build_seed_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
+  if (a.g.mat.on)
+    hipLaunchKernelGGL((build_seed_kernel<TS, TP, true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
+  else
+    hipLaunchKernelGGL((build_seed_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   int cur = 0;
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
-    hipLaunchKernelGGL((build_score_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
+    if (a.g.mat.on)
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, true>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
+    else
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, false>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
     launch_merge<TS>(a, l, cur, st);
     hipLaunchKernelGGL((build_clone_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
     cur ^= 1;
@@ -1169,6 +1197,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.g.hr.srphi2 = cfg.sigma_rphi * cfg.sigma_rphi;
   a.g.hr.sz2 = cfg.sigma_z * cfg.sigma_z;
   for (int l = 0; l < L; ++l) a.g.radii[l] = c->radii[l];
+  a.g.mat = material_of(c);
   a.n_events = ev->n_events;
   a.n_groups = ev->n_events * L;
   a.n_bins = cfg.n_zbins * cfg.n_phibins;

@@ -66,6 +66,7 @@ struct ServeState;
 struct ktf_ctx {
   ktf_config cfg{};
   std::vector<double> radii;
+  std::vector<double> x0;  // per-layer material thickness (radiation lengths), empty = none
   int device = 0;
   int n_cu = 0;
   std::string gcn_arch;
@@ -101,4 +102,14 @@ int build_impl(ktf_ctx* c, const ktf_event_batch* ev, ktf_build_out* out, hipStr
 int bin_impl(ktf_ctx* c, const ktf_event_batch* ev, int32_t* offsets, int32_t* perm,
              hipStream_t st);
 void serve_shutdown(ktf_ctx* c);
+
+// the context's layer material as kernels take it
+inline MaterialD material_of(const ktf_ctx* c) {
+  MaterialD m{};
+  m.on = c->x0.empty() ? 0 : 1;
+  for (size_t l = 0; l < c->x0.size(); ++l) m.x0[l] = c->x0[l];
+  m.eloss = c->cfg.eloss_per_x0;
+  m.mass = c->cfg.mass;
+  return m;
+}
 }  // namespace ktf

@@ -16,7 +16,7 @@
 //              round-trip HBM between launches (the memory-bound design used
 //              for per-layer graph sweeps)
 #include "kf_math.hpp"
-#include "ktf_internal.hpp"
+#include "ctx.hpp"
 
 namespace ktf {
 
@@ -25,8 +25,10 @@ template <> struct NewtonIters<double> { static constexpr int n = 3; };
 template <> struct NewtonIters<float> { static constexpr int n = 2; };
 
 // Storage type TS, propagation type TP (state, path solve, transport,
-// Jacobian), covariance type TC (registers, F P F^T and update).
-template <typename TS, typename TP, typename TC>
+// Jacobian), covariance type TC (registers, F P F^T and update).  MAT: the
+// layers carry material, applied to a copy of the state when it leaves a
+// layer (the filtered state stays the result if the next layer is missed).
+template <typename TS, typename TP, typename TC, bool MAT>
 __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
   const int64_t p = a.pitch;
   const TS* st = static_cast<const TS*>(a.state);
@@ -69,12 +71,25 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
     }
     TrackState<TP> xp;
     Jac<TP> F;
-    if (!propagate<TP, NewtonIters<TP>::n>(x, k, a.radii[l], l == 0, xp, F)) {
-      status |= kNoReach;
-      break;
-    }
     TC Pp[21];
-    cov_propagate(P, F, Pp);
+    if constexpr (MAT) {
+      TrackState<TP> xm = x;
+      TC Pm[21];
+#pragma unroll
+      for (int c = 0; c < 21; ++c) Pm[c] = P[c];
+      if (l > 0 && a.mat.x0[l - 1] > 0.0) apply_material(a.mat.x0[l - 1], a.mat.eloss, a.mat.mass, xm, Pm);
+      if (!propagate<TP, NewtonIters<TP>::n>(xm, k, a.radii[l], l == 0, xp, F)) {
+        status |= kNoReach;
+        break;
+      }
+      cov_propagate(Pm, F, Pp);
+    } else {
+      if (!propagate<TP, NewtonIters<TP>::n>(x, k, a.radii[l], l == 0, xp, F)) {
+        status |= kNoReach;
+        break;
+      }
+      cov_propagate(P, F, Pp);
+    }
     bool used = false;
     if ((vmask >> l) & 1u) {
       Residual R;
@@ -112,15 +127,15 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
 
 // W: the waves per SIMD the register allocation must allow (1 leaves it to
 // the compiler; more trades registers, and maybe spills, for latency hiding)
-template <typename TS, typename TP, typename TC, int BS, int W>
+template <typename TS, typename TP, typename TC, int BS, int W, bool MAT>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_fused_kernel(FitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < a.n) fit_one_track<TS, TP, TC>(a, i);
+  if (i < a.n) fit_one_track<TS, TP, TC, MAT>(a, i);
 }
 
 // Persistent blocks: every block loops taking the next tile of BS tracks
 // from counters[0]; all waves leave once the tile index passes tile_count.
-template <typename TS, typename TP, typename TC, int BS, int W>
+template <typename TS, typename TP, typename TC, int BS, int W, bool MAT>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_persistent_kernel(FitArgs a) {
   __shared__ long long tile;
   for (;;) {
@@ -130,7 +145,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fi
     __syncthreads();
     if (t >= a.tile_count) break;
     const int64_t i = t * BS + threadIdx.x;
-    if (i < a.n) fit_one_track<TS, TP, TC>(a, i);
+    if (i < a.n) fit_one_track<TS, TP, TC, MAT>(a, i);
   }
 }
 
@@ -138,8 +153,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fi
 // outputs and the per-track end layer; later layers work in place on the
 // outputs.  A track that has stopped (NO_REACH / NONFINITE) or is past its
 // last hit is left untouched.
-template <typename TS, typename TP, int BS>
-__global__ __launch_bounds__(BS) void fit_layer_kernel(FitArgs a, int l) {
+// Three waves per SIMD fit without spills in both precisions (this kernel
+// is bound by HBM latency, so occupancy matters).
+template <typename TS, typename TP, int BS, bool MAT>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void fit_layer_kernel(FitArgs a, int l) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= a.n) return;
   const int64_t p = a.pitch;
@@ -184,10 +201,19 @@ __global__ __launch_bounds__(BS) void fit_layer_kernel(FitArgs a, int l) {
   for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * p + i];
   const TP k = (TP)(kCLight * (double)a.q[i] * a.bz);
   const HitRes hr{a.hr.sr2, a.hr.srphi2, a.hr.sz2};
+  // the material of the layer being left; the stored (filtered) state stays
+  // the result if the next layer is missed
+  if constexpr (MAT) {
+    if (l > 0 && a.mat.x0[l - 1] > 0.0) apply_material(a.mat.x0[l - 1], a.mat.eloss, a.mat.mass, x, P);
+  }
   TrackState<TP> xp;
   Jac<TP> F;
   if (!propagate<TP, NewtonIters<TP>::n>(x, k, a.radii[l], l == 0, xp, F)) {
     status |= kNoReach;
+    if (l > 0) {
+      a.status[i] = status;
+      return;
+    }
   } else {
     TP Pp[21];
     cov_propagate(P, F, Pp);
@@ -241,15 +267,21 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
   return hipGetLastError();
 }
 
-template <typename TS, typename TP, typename TC, int BS, int W>
-static hipError_t launch_fused_bs(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
+template <typename TS, typename TP, typename TC, int BS, int W, bool MAT>
+static hipError_t launch_fused_m(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
   if (persistent) {
-    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, TC, BS, W>), dim3(pblocks), dim3(BS), 0, st, a);
+    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, TC, BS, W, MAT>), dim3(pblocks), dim3(BS), 0, st, a);
   } else {
     const int64_t nb = (a.n + BS - 1) / BS;
-    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS, W>), dim3((unsigned)nb), dim3(BS), 0, st, a);
+    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS, W, MAT>), dim3((unsigned)nb), dim3(BS), 0, st, a);
   }
   return hipGetLastError();
+}
+
+template <typename TS, typename TP, typename TC, int BS, int W>
+static hipError_t launch_fused_bs(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
+  return a.mat.on ? launch_fused_m<TS, TP, TC, BS, W, true>(a, persistent, pblocks, st)
+                  : launch_fused_m<TS, TP, TC, BS, W, false>(a, persistent, pblocks, st);
 }
 
 template <typename TS, typename TP, typename TC, int W>
@@ -288,10 +320,14 @@ hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hip
   if (a.n <= 0) return hipSuccess;
   constexpr int BS = 256;
   const unsigned nb = (unsigned)((a.n + BS - 1) / BS);
-  if (prec == KTF_FP64)
-    hipLaunchKernelGGL((fit_layer_kernel<double, double, BS>), dim3(nb), dim3(BS), 0, st, a, layer);
+  if (prec == KTF_FP64 && a.mat.on)
+    hipLaunchKernelGGL((fit_layer_kernel<double, double, BS, true>), dim3(nb), dim3(BS), 0, st, a, layer);
+  else if (prec == KTF_FP64)
+    hipLaunchKernelGGL((fit_layer_kernel<double, double, BS, false>), dim3(nb), dim3(BS), 0, st, a, layer);
+  else if (a.mat.on)
+    hipLaunchKernelGGL((fit_layer_kernel<float, float, BS, true>), dim3(nb), dim3(BS), 0, st, a, layer);
   else
-    hipLaunchKernelGGL((fit_layer_kernel<float, float, BS>), dim3(nb), dim3(BS), 0, st, a, layer);
+    hipLaunchKernelGGL((fit_layer_kernel<float, float, BS, false>), dim3(nb), dim3(BS), 0, st, a, layer);
   return hipGetLastError();
 }
 
@@ -299,34 +335,39 @@ hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hip
 
 namespace ktf {
 
-template <typename TS, typename TP, typename TC, int W>
+template <typename TS, typename TP, typename TC, int W, bool MAT>
 static int occ_blocks_w(int bs) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (bs) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 64, W>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 128, W>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 256, W>, 256, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 512, W>, 512, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 64, W, MAT>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 128, W, MAT>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 256, W, MAT>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 512, W, MAT>, 512, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;
 }
 
-template <typename TS, typename TP, typename TC>
+template <typename TS, typename TP, typename TC, bool MAT>
 static int occ_blocks(int bs, int waves) {
   switch (waves) {
-    case 1: return occ_blocks_w<TS, TP, TC, 1>(bs);
-    case 2: return occ_blocks_w<TS, TP, TC, 2>(bs);
-    case 3: return occ_blocks_w<TS, TP, TC, 3>(bs);
+    case 1: return occ_blocks_w<TS, TP, TC, 1, MAT>(bs);
+    case 2: return occ_blocks_w<TS, TP, TC, 2, MAT>(bs);
+    case 3: return occ_blocks_w<TS, TP, TC, 3, MAT>(bs);
     default: return 0;
   }
 }
 
-int persistent_blocks(ktf_ctx*, ktf_precision prec, int bs, int waves) {
-  if (prec == KTF_FP64) return occ_blocks<double, double, double>(bs, waves);
-  if (prec == KTF_FP32_PROP) return occ_blocks<float, float, double>(bs, waves);
-  return occ_blocks<float, float, float>(bs, waves);
+template <bool MAT>
+static int persistent_blocks_m(ktf_precision prec, int bs, int waves) {
+  if (prec == KTF_FP64) return occ_blocks<double, double, double, MAT>(bs, waves);
+  if (prec == KTF_FP32_PROP) return occ_blocks<float, float, double, MAT>(bs, waves);
+  return occ_blocks<float, float, float, MAT>(bs, waves);
+}
+
+int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves) {
+  return c->x0.empty() ? persistent_blocks_m<false>(prec, bs, waves) : persistent_blocks_m<true>(prec, bs, waves);
 }
 
 }  // namespace ktf

@@ -7,11 +7,13 @@
 // helix model is a charged particle in a uniform field along z between
 // cylindrical barrel layers; the measurement is the hit's global (x, y, z).
 //
-// Precision is a template parameter: TP is the type of the propagation
-// (path solve, transport, Jacobian, F P F^T); the update (hit covariance,
-// S, its inverse, chi2, gain, state and Joseph covariance update) always
-// runs in double.  TP = double is the plain FP64 path, TP = float the
-// FP32-bulk path.
+// Precision is a template parameter: TP is the type of the state
+// propagation (path solve, transport, Jacobian), C the type the covariance
+// is kept and propagated in (F P F^T); the update (hit covariance, S, its
+// inverse, chi2, gain, state and Joseph covariance update) and the layer
+// material always run in double.  TP = C = double is the plain FP64 path,
+// TP = C = float the FP32-bulk path, TP = float with C = double the FP32
+// state propagation with a double covariance.
 //
 // Packed symmetric 6x6: 21-value upper triangle, row order
 // (00,01,02,03,04,05,11,12,13,14,15,22,23,24,25,33,34,35,44,45,55).
@@ -82,7 +84,7 @@ template <> KTF_HD void ksincos<float>(float x, float* s, float* c) { sincosf(x,
 // ---------------------------------------------------------------------------
 template <typename T> struct NewtonTol;
 template <> struct NewtonTol<float> { static constexpr float v = 1e-6f; };
-template <> struct NewtonTol<double> { static constexpr double v = 1e-13; };
+template <> struct NewtonTol<double> { static constexpr double v = 1e-12; };
 
 template <typename T> struct SeriesLen;
 template <> struct SeriesLen<float> { static constexpr int n = 5; };
@@ -248,13 +250,21 @@ KTF_HD bool propagate(const TrackState<T>& x, T k, double r, bool nearest, Track
 #pragma unroll
   for (int it = 0; it < NITER; ++it) newton_step();
   // Newton converges quadratically from the straight-line root; a long or
-  // strongly curved step may need more: continue while the last step was
-  // still above the storage precision (rarely taken)
+  // strongly curved step may need more: continue while the last step is
+  // above the tolerance (1e-12 (1 + |s|) cm in double, 1e-6 (1 + |s|) in
+  // float), up to 50 steps in all in double.  A helix that only grazes the
+  // layer converges slowly (a double root); one that has not converged
+  // within the limit counts as not reaching the layer.
   const T tol = NewtonTol<T>::v * (T(1) + (s < T(0) ? -s : s));
+  constexpr int kTail = sizeof(T) == 8 ? 50 - NITER : 8;
+  bool conv = (ds < T(0) ? -ds : ds) <= tol;
 #pragma unroll 1
-  for (int it = 0; it < 3 && (ds < T(0) ? -ds : ds) > tol; ++it) newton_step();
+  for (int it = 0; it < kTail && !conv; ++it) {
+    newton_step();
+    conv = (ds < T(0) ? -ds : ds) <= tol;
+  }
   transport(x, k, ipt, s, t);
-  ok = ok && (nearest || s > T(0));
+  ok = ok && conv && (nearest || s > T(0));
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     xo.pos[i] = x.pos[i] + (double)t.d[i];
@@ -462,6 +472,74 @@ KTF_HD void apply_update(const TrackState<T>& xp, const C Pp[21], const Residual
         acc = fma(-D[i][c], K[j][c], acc);
       }
       P[pidx(i, j)] = (C)acc;
+    }
+  }
+}
+
+// Material of the layer a track leaves (radial position x.pos on it):
+// path t = x0 |p| / |p.n| radiation lengths (n the radial normal), multiple
+// scattering as process noise theta0^2 (|p|^2 I - p p^T) on the momentum
+// with the Highland width theta0 = 0.0136 / (beta p) sqrt(t) (1 + 0.038
+// ln(t / beta^2)), then the mean energy loss eloss t: |p| -> g = sqrt((E -
+// eloss t)^2 - m^2) along the same direction, the covariance carried by the
+// Jacobian J = f (I - u u^T) + g' u u^T on the momentum (u = p / |p|, f = g /
+// |p|, g' = (E - eloss t) |p| / (g E), t held fixed).  In double.
+template <typename T, typename C>
+KTF_HD void apply_material(double x0, double eloss, double mass, TrackState<T>& x, C P[21]) {
+  const double p[3] = {(double)x.mom[0], (double)x.mom[1], (double)x.mom[2]};
+  const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  const double pm = sqrt(p2);
+  const double r = sqrt(x.pos[0] * x.pos[0] + x.pos[1] * x.pos[1]);
+  const double pn = (x.pos[0] * p[0] + x.pos[1] * p[1]) / r;
+  const double t = x0 * pm / fabs(pn);
+  const double E = sqrt(p2 + mass * mass);
+  const double beta = pm / E;
+  const double th = 0.0136 / (beta * pm) * sqrt(t) * (1.0 + 0.038 * log(t / (beta * beta)));
+  const double th2 = th * th;
+  // momentum block plus the process noise; the position-momentum block
+  double A[3][3], B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      A[i][j] = (double)P[sidx(3 + i, 3 + j)] + th2 * ((i == j ? p2 : 0.0) - p[i] * p[j]);
+      B[i][j] = (double)P[sidx(i, 3 + j)];
+    }
+  }
+  if (eloss > 0.0) {
+    const double E2 = E - eloss * t;
+    const double g = E2 > mass ? sqrt(E2 * E2 - mass * mass) : 0.0;
+    const double f = g / pm;
+    const double gp = g > 0.0 ? E2 * pm / (g * E) : 0.0;
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) J[i][j] = (i == j ? f : 0.0) + (gp - f) * p[i] * p[j] / p2;
+    double JA[3][3], BJ[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        JA[i][j] = J[i][0] * A[0][j] + J[i][1] * A[1][j] + J[i][2] * A[2][j];
+        BJ[i][j] = B[i][0] * J[j][0] + B[i][1] * J[j][1] + B[i][2] * J[j][2];
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        A[i][j] = JA[i][0] * J[j][0] + JA[i][1] * J[j][1] + JA[i][2] * J[j][2];
+        B[i][j] = BJ[i][j];
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x.mom[i] = (T)(f * p[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (j >= i) P[pidx(3 + i, 3 + j)] = (C)A[i][j];
+      P[pidx(i, 3 + j)] = (C)B[i][j];
     }
   }
 }

@@ -14,6 +14,13 @@ struct HitResD {
 };
 
 // Arguments of the fit kernels (passed by value in the kernarg segment).
+// layer material (see ktf_config): thickness per layer, energy loss, mass
+struct MaterialD {
+  double x0[KTF_MAX_LAYERS];
+  double eloss, mass;
+  int32_t on;
+};
+
 struct FitArgs {
   int64_t n, pitch;
   const void* state;
@@ -34,6 +41,7 @@ struct FitArgs {
   double bz;
   HitResD hr;
   double radii[KTF_MAX_LAYERS];
+  MaterialD mat;
 };
 
 // launch shapes of the fused fit
@@ -52,6 +60,7 @@ struct BuildGeom {
   double bz, z_half, chi2_cut;
   HitResD hr;
   double radii[KTF_MAX_LAYERS];
+  MaterialD mat;
 };
 
 }  // namespace ktf

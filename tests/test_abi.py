@@ -38,13 +38,14 @@ def make_cfg(k, radii, **kw):
     arr = (C.c_double * len(radii))(*radii)
     base = dict(z_half=100.0, bz=3.8, sigma_r=0.01, sigma_rphi=0.01, sigma_z=0.1, n_zbins=64,
                 n_phibins=512, max_cands=10, max_missed=1, n_seed_layers=3, chi2_cut=30.0,
-                hbm_budget_bytes=1 << 30, max_inflight=8)
+                hbm_budget_bytes=1 << 30, max_inflight=8, x0=None, eloss=0.0, mass=0.13957)
     base.update(kw)
+    x0 = None if base["x0"] is None else (C.c_double * len(radii))(*base["x0"])
     cfg = k._Config(len(radii), arr, base["z_half"], base["bz"], base["sigma_r"], base["sigma_rphi"],
                     base["sigma_z"], base["n_zbins"], base["n_phibins"], base["max_cands"],
                     base["max_missed"], base["n_seed_layers"], base["chi2_cut"],
-                    base["hbm_budget_bytes"], base["max_inflight"])
-    return cfg, arr
+                    base["hbm_budget_bytes"], base["max_inflight"], x0, base["eloss"], base["mass"])
+    return cfg, (arr, x0)
 
 
 @pytest.mark.parametrize("bad", [
@@ -56,6 +57,10 @@ def make_cfg(k, radii, **kw):
     dict(max_cands=99),
     dict(n_seed_layers=20),
     dict(n_zbins=0),
+    dict(x0=[0.01] * 9 + [-0.01]),          # negative material
+    dict(x0=[0.01] * 9 + [float("nan")]),   # not a number
+    dict(x0=[0.01] * 10, mass=0.0),         # material needs a mass
+    dict(x0=[0.01] * 10, eloss=-1.0),
 ])
 def test_create_rejects_bad_config(lib, bad):
     import paper_1605_05508_amd as k

@@ -265,7 +265,8 @@ def truth_crossings_material(truth: dict, det: Detector, rng: np.random.Generato
     alive = np.ones(n, dtype=bool)
     for li, r in enumerate(det.radii):
         if li > 0:
-            npx, npy, npz = scatter_layer(rng, x, y, px, py, pz, det)
+            with np.errstate(invalid="ignore", divide="ignore"):  # stopped particles are masked
+                npx, npy, npz = scatter_layer(rng, x, y, px, py, pz, det)
             px, py, pz = np.where(alive, npx, px), np.where(alive, npy, py), np.where(alive, npz, pz)
             alive &= np.hypot(px, py) > 0.0
         with np.errstate(invalid="ignore", divide="ignore"):
@@ -466,6 +467,13 @@ def config2(n=1_000_000, seed=2) -> FitSet:
     """FP32-bulk vs FP64 fit at scale: 1e6 tracks, pT log-uniform 0.5-100 GeV."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return make_fit_set(rng, n, barrel(10), pt_range=(0.5, 100.0), pt_log=True)
+
+
+def config2_material(n=1_000_000, seed=6, x0=0.02, eloss=0.036) -> FitSet:
+    """The fit at scale through material: layers of 2% X0 with a silicon-like
+    mean energy loss (0.036 GeV per X0), pT log-uniform 0.5-100 GeV."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return make_fit_set(rng, n, barrel(10, x0=x0, eloss=eloss), pt_range=(0.5, 100.0), pt_log=True)
 
 
 def config4(n_events=2000, seed=4, median=3000.0, sigma=0.8, clip=(50, 50000),
