@@ -43,6 +43,7 @@ extern "C" {
 
 #define KTF_MAX_LAYERS 32
 #define KTF_MAX_CANDS 16
+#define KTF_MAX_PASSES 16
 
 /* return codes */
 #define KTF_OK 0
@@ -141,6 +142,19 @@ typedef struct {
   const int8_t *charge;     /* device [pitch], +1 or -1                          */
   const void *hits;         /* device [n_layers][3][pitch]: x, y, z              */
   const uint8_t *hit_valid; /* device [n_layers][pitch], 0 = no hit; NULL = all   */
+  int32_t n_passes;         /* 0 or 1: one pass of the filter.  2..KTF_MAX_PASSES:
+                               iterated refit, a re-linearisation for seeds too
+                               poor for one pass: each further pass refits from
+                               the previous pass's result carried back to the
+                               first layer (the helix travelled backwards, the
+                               mean energy loss given back), with seed_cov.  A
+                               pass that sets a status bit the pass before did
+                               not is dropped and ends the refit; so do a result
+                               that is non-finite or cannot be carried back.
+                               Fused and persistent modes, and a double
+                               covariance (KTF_FP64, KTF_FP32_PROP) only, else
+                               EINVAL: with a float covariance the passes
+                               amplify its rounding on poor seeds.          */
 } ktf_fit_in;
 
 typedef struct {

@@ -171,8 +171,9 @@ def pack(P):
 
 # ------------------------------------------------------------------- fit
 
-def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=True):
-    """Batched FP64 fit.  state[6,n], cov[21,n], q[n], hits[L,3,n], valid[L,n].
+def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=True, passes=1):
+    """Batched FP64 fit.  state[6,n], cov[21,n], q[n], hits[L,3,n], valid[L,n];
+    passes > 1: iterated refit (orc_refit_track).
 
     Returns dict(state[6,n], cov[21,n], chi2[n], nupd[n], status[n]).
     """
@@ -192,14 +193,24 @@ def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=Tru
     lib().orc_fit_batch(C.byref(g), C.c_int64(n), _p(st, C.c_double), _p(cv, C.c_double),
                         _p(qq, C.c_int8), _p(hh, C.c_double), _p(vv, C.c_uint8),
                         _p(so, C.c_double), _p(co, C.c_double), _p(c2, C.c_double),
-                        _p(nu, C.c_int32), _p(stt, C.c_uint32),
+                        _p(nu, C.c_int32), _p(stt, C.c_uint32), C.c_int(int(passes)),
                         C.c_int(nthreads or default_threads()))
     return dict(state=so.T.copy(), cov=co.T.copy(), chi2=c2, nupd=nu, status=stt)
 
 
-def fit(fs, nthreads=None, material=True):
-    """Fit a trackgen.FitSet."""
-    return fit_arrays(fs.det, fs.state, fs.cov, fs.q, fs.hits, fs.valid, nthreads, material)
+def fit(fs, nthreads=None, material=True, passes=1):
+    """Fit a trackgen.FitSet (passes > 1: iterated refit)."""
+    return fit_arrays(fs.det, fs.state, fs.cov, fs.q, fs.hits, fs.valid, nthreads, material, passes)
+
+
+def carry_back(det, q, from_layer, x):
+    """A state on layer from_layer carried back to layer 0 (orc_carry_back);
+    returns (state, rc)."""
+    g, keep = _geom(det)
+    xo = np.zeros(6)
+    rc = lib().orc_carry_back(C.byref(g), C.c_int(int(q)), C.c_int(int(from_layer)),
+                              _p(_d(x), C.c_double), _p(xo, C.c_double))
+    return xo, rc
 
 
 # ---------------------------------------------------------------- binning

@@ -353,11 +353,12 @@ void orc_material(const orc_geom *g, int l, const double x[6], const double P[36
   for (int i = 0; i < 3; ++i) xo[3 + i] = f * x[3 + i];
 }
 
-int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], int q,
-                  const double *hits, const uint8_t *valid,
-                  double xo[6], double Po[21], double *chi2, int32_t *nupd,
-                  uint32_t *status) {
+/* the fit of one pass; *last = layer of the final state (-1: none) */
+static int fit_pass(const orc_geom *g, const double x0[6], const double P0[21], int q,
+                    const double *hits, const uint8_t *valid, double xo[6], double Po[21],
+                    double *chi2, int32_t *nupd, uint32_t *status, int *last_layer) {
   const int L = g->n_layers;
+  int at = -1;
   int last = -1;
   for (int l = 0; l < L; ++l)
     if (!valid || valid[l]) last = l;
@@ -381,6 +382,7 @@ int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], in
       st |= ORC_NO_REACH;
       break;
     }
+    at = l;
     orc_cov_propagate(Pm, F, Pp);
     if (!valid || valid[l]) {
       const double *m = hits + 3 * l;
@@ -410,7 +412,67 @@ int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], in
   *chi2 = c2sum;
   *nupd = n;
   *status = st;
+  *last_layer = at;
   return (int)st;
+}
+
+int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], int q,
+                  const double *hits, const uint8_t *valid,
+                  double xo[6], double Po[21], double *chi2, int32_t *nupd,
+                  uint32_t *status) {
+  int last;
+  return fit_pass(g, x0, P0, q, hits, valid, xo, Po, chi2, nupd, status, &last);
+}
+
+int orc_carry_back(const orc_geom *g, int q, int from, const double x[6], double xo[6]) {
+  double cur[6];
+  memcpy(cur, x, sizeof cur);
+  for (int l = from - 1; l >= 0; --l) {
+    /* the same helix travelled backwards: reversed momentum, opposite charge */
+    double xr[6] = {cur[0], cur[1], cur[2], -cur[3], -cur[4], -cur[5]}, xp[6], F[36], s;
+    if (orc_propagate(xr, -q, g->bz, g->radii[l], 1, xp, F, &s)) return (int)ORC_NO_REACH;
+    for (int i = 0; i < 3; ++i) {
+      cur[i] = xp[i];
+      cur[3 + i] = -xp[3 + i];
+    }
+    /* give back the mean energy lost when leaving layer l */
+    if (g->x0 && g->x0[l] > 0.0 && g->eloss > 0.0) {
+      const double *p = cur + 3;
+      const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2], pm = sqrt(p2);
+      const double r = sqrt(cur[0] * cur[0] + cur[1] * cur[1]);
+      const double t = g->x0[l] * pm / fabs((cur[0] * p[0] + cur[1] * p[1]) / r);
+      const double E = sqrt(p2 + g->mass * g->mass) + g->eloss * t;
+      const double f = sqrt(E * E - g->mass * g->mass) / pm;
+      for (int i = 0; i < 3; ++i) cur[3 + i] *= f;
+    }
+  }
+  memcpy(xo, cur, sizeof cur);
+  return 0;
+}
+
+int orc_refit_track(const orc_geom *g, const double x0[6], const double P0[21], int q,
+                    const double *hits, const uint8_t *valid, int n_passes,
+                    double xo[6], double Po[21], double *chi2, int32_t *nupd, uint32_t *status) {
+  double seed[6];
+  memcpy(seed, x0, sizeof seed);
+  int last;
+  fit_pass(g, seed, P0, q, hits, valid, xo, Po, chi2, nupd, status, &last);
+  for (int pass = 1; pass < n_passes; ++pass) {
+    if ((*status & ORC_NONFINITE) || last < 0 || orc_carry_back(g, q, last, xo, seed)) break;
+    double x2[6], P2[21], c2;
+    int32_t n2;
+    uint32_t st2;
+    int last2;
+    fit_pass(g, seed, P0, q, hits, valid, x2, P2, &c2, &n2, &st2, &last2);
+    if (st2 != 0 && *status == 0) break; /* a clean pass is not replaced by a failed one */
+    memcpy(xo, x2, sizeof x2);
+    memcpy(Po, P2, sizeof P2);
+    *chi2 = c2;
+    *nupd = n2;
+    *status = st2;
+    last = last2;
+  }
+  return (int)*status;
 }
 
 typedef struct {
@@ -422,29 +484,30 @@ typedef struct {
   double *state_o, *cov_o, *chi2_o;
   int32_t *nupd_o;
   uint32_t *status_o;
+  int n_passes;
 } fit_job;
 
 static void *fit_worker(void *arg) {
   fit_job *j = (fit_job *)arg;
   const int L = j->g->n_layers;
   for (int64_t i = j->lo; i < j->hi; ++i)
-    orc_fit_track(j->g, j->state + 6 * i, j->cov + 21 * i, j->q[i], j->hits + (int64_t)3 * L * i,
-                  j->valid ? j->valid + (int64_t)L * i : NULL, j->state_o + 6 * i,
-                  j->cov_o + 21 * i, j->chi2_o + i, j->nupd_o + i, j->status_o + i);
+    orc_refit_track(j->g, j->state + 6 * i, j->cov + 21 * i, j->q[i], j->hits + (int64_t)3 * L * i,
+                    j->valid ? j->valid + (int64_t)L * i : NULL, j->n_passes, j->state_o + 6 * i,
+                    j->cov_o + 21 * i, j->chi2_o + i, j->nupd_o + i, j->status_o + i);
   return NULL;
 }
 
 void orc_fit_batch(const orc_geom *g, int64_t n, const double *state, const double *cov,
                    const int8_t *q, const double *hits, const uint8_t *valid,
                    double *state_o, double *cov_o, double *chi2_o, int32_t *nupd_o,
-                   uint32_t *status_o, int nthreads) {
+                   uint32_t *status_o, int n_passes, int nthreads) {
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   pthread_t th[256];
   fit_job jobs[256];
   for (int t = 0; t < nthreads; ++t) {
     fit_job j = {g, n * t / nthreads, n * (t + 1) / nthreads, state, cov, hits, q, valid,
-                 state_o, cov_o, chi2_o, nupd_o, status_o};
+                 state_o, cov_o, chi2_o, nupd_o, status_o, n_passes};
     jobs[t] = j;
   }
   if (nthreads == 1) {

@@ -100,12 +100,28 @@ int orc_fit_track(const orc_geom *g, const double x0[6], const double P0[21], in
                   double xo[6], double Po[21], double *chi2, int32_t *nupd,
                   uint32_t *status);
 
-/* batched fit: AoS inputs state[n][6], cov[n][21], q[n], hits[n][L][3],
+/* a state on layer `from` carried back to layer 0 along its helix
+ * (reversed momentum and charge, one layer at a time), giving back the mean
+ * energy lost when leaving each crossed layer.  Returns 0 or ORC_NO_REACH. */
+int orc_carry_back(const orc_geom *g, int q, int from, const double x[6], double xo[6]);
+
+/* iterated refit (re-linearisation, a remedy for seeds too poor for one
+ * pass of the linearised filter): pass 1 is orc_fit_track; each further
+ * pass refits from the previous pass's final state carried back to layer 0
+ * (orc_carry_back), with the seed covariance P0.  The result is that of the
+ * last pass; the refit stops early, keeping the pass before, when that pass
+ * ended non-finite, its state cannot be carried back, or the new pass sets a
+ * status bit that the one before did not.  n_passes <= 1: one pass. */
+int orc_refit_track(const orc_geom *g, const double x0[6], const double P0[21], int q,
+                    const double *hits, const uint8_t *valid, int n_passes,
+                    double xo[6], double Po[21], double *chi2, int32_t *nupd, uint32_t *status);
+
+/* batched (re)fit: AoS inputs state[n][6], cov[n][21], q[n], hits[n][L][3],
  * valid[n][L] (may be NULL); outputs AoS.  Tracks split over nthreads. */
 void orc_fit_batch(const orc_geom *g, int64_t n, const double *state, const double *cov,
                    const int8_t *q, const double *hits, const uint8_t *valid,
                    double *state_o, double *cov_o, double *chi2_o, int32_t *nupd_o,
-                   uint32_t *status_o, int nthreads);
+                   uint32_t *status_o, int n_passes, int nthreads);
 
 /* hit binning of one layer: zbin = floor((z + zh) * nz / (2 zh)) clamped,
  * phibin = floor((atan2(y,x) + pi) * nphi / (2 pi)) mod nphi, bin = zbin *

@@ -48,7 +48,7 @@ class _Config(C.Structure):
 class _FitIn(C.Structure):
     _fields_ = [("n", C.c_int64), ("pitch", C.c_int64), ("prec", C.c_int), ("seed_state", C.c_void_p),
                 ("seed_cov", C.c_void_p), ("charge", C.c_void_p), ("hits", C.c_void_p),
-                ("hit_valid", C.c_void_p)]
+                ("hit_valid", C.c_void_p), ("n_passes", C.c_int32)]
 
 
 class _FitOut(C.Structure):
@@ -191,7 +191,7 @@ class Context:
             raise KtfError(rc, f"{what}: {msg.decode() if msg else ''}")
 
     # ---------------------------------------------------------------- fit
-    def _fit_structs(self, state, cov, q, hits, valid, out, prec=None):
+    def _fit_structs(self, state, cov, q, hits, valid, out, prec=None, passes=1):
         torch = _torch()
         if prec is None:
             prec = FP64 if state.dtype == torch.float64 else FP32_BULK
@@ -201,7 +201,7 @@ class Context:
                 raise ValueError("precision and storage dtype disagree")
         n = q.shape[0]
         pitch = state.shape[1]
-        fin = _FitIn(n, pitch, prec, _ptr(state), _ptr(cov), _ptr(q), _ptr(hits), _ptr(valid))
+        fin = _FitIn(n, pitch, prec, _ptr(state), _ptr(cov), _ptr(q), _ptr(hits), _ptr(valid), int(passes))
         fout = _FitOut(_ptr(out["state"]), _ptr(out["cov"]), _ptr(out["chi2"]), _ptr(out["nupd"]),
                        _ptr(out["status"]))
         return fin, fout
@@ -215,16 +215,18 @@ class Context:
                     nupd=torch.empty(pitch, dtype=torch.int32, device=dev),
                     status=torch.empty(pitch, dtype=torch.int32, device=dev))
 
-    def fit(self, state, cov, q, hits, valid=None, *, mode="auto", out=None, stream=None, prec=None):
+    def fit(self, state, cov, q, hits, valid=None, *, mode="auto", out=None, stream=None, prec=None,
+            passes=1):
         """Enqueue a fit.  state [6, pitch], cov [21, pitch] (float64 for the FP64
         path, float32 for the float-storage paths), q int8 [pitch] (first n =
         len(q) are tracks), hits [L, 3, pitch] same dtype, valid uint8 [L, pitch]
         or None.  prec: None (from the dtype: 'fp64' or 'fp32b') or 'fp32p'
-        (float state propagation, double covariance; fused modes only)."""
+        (float state propagation, double covariance; fused modes only).
+        passes > 1: iterated refit (fused modes only)."""
         self._validate_fit(state, cov, q, hits, valid)
         if out is None:
             out = self.alloc_fit_out(q.shape[0], state.shape[1], state.dtype)
-        fin, fout = self._fit_structs(state, cov, q, hits, valid, out, prec)
+        fin, fout = self._fit_structs(state, cov, q, hits, valid, out, prec, passes)
         self._check(self._lib.ktf_fit(self._h, C.byref(fin), C.byref(fout), MODES[mode],
                                       _stream_handle(stream)), "ktf_fit")
         return out

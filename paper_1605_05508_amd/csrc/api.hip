@@ -38,6 +38,7 @@ FitArgs make_fit_args(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out) {
   a.nupd = out->n_upd;
   a.status = out->status;
   a.n_layers = c->cfg.n_layers;
+  a.n_passes = in->n_passes > 1 ? in->n_passes : 1;
   a.bz = c->cfg.bz;
   a.hr.sr2 = c->cfg.sigma_r * c->cfg.sigma_r;
   a.hr.srphi2 = c->cfg.sigma_rphi * c->cfg.sigma_rphi;
@@ -59,6 +60,10 @@ static int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* o
     return fail(c, KTF_EINVAL, "ktf_fit: n=%lld pitch=%lld", (long long)in->n, (long long)in->pitch);
   if (in->prec != KTF_FP64 && in->prec != KTF_FP32_BULK && in->prec != KTF_FP32_PROP)
     return fail(c, KTF_EINVAL, "ktf_fit: unknown precision %d", (int)in->prec);
+  if (in->n_passes < 0 || in->n_passes > KTF_MAX_PASSES)
+    return fail(c, KTF_EINVAL, "ktf_fit: n_passes %d outside 0..%d", (int)in->n_passes, KTF_MAX_PASSES);
+  if (in->n_passes > 1 && in->prec == KTF_FP32_BULK)
+    return fail(c, KTF_EINVAL, "ktf_fit: the iterated refit needs a double covariance (KTF_FP64 or KTF_FP32_PROP)");
   if (in->n > 0 && (!in->seed_state || !in->seed_cov || !in->charge || !in->hits || !out->state ||
                     !out->cov || !out->chi2 || !out->n_upd || !out->status))
     return fail(c, KTF_EINVAL, "ktf_fit: null buffer");
@@ -227,6 +232,8 @@ int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mod
     case KTF_FIT_SWEEP_GRAPH:
       if (in->prec == KTF_FP32_PROP)
         return fail(c, KTF_EINVAL, "ktf_fit: KTF_FP32_PROP keeps the covariance in registers; use a fused mode");
+      if (in->n_passes > 1)
+        return fail(c, KTF_EINVAL, "ktf_fit: the iterated refit runs in the fused modes");
       break;
     default: return fail(c, KTF_EINVAL, "ktf_fit: unknown mode %d", (int)mode);
   }

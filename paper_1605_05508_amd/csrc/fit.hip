@@ -24,34 +24,24 @@ template <typename T> struct NewtonIters;
 template <> struct NewtonIters<double> { static constexpr int n = 3; };
 template <> struct NewtonIters<float> { static constexpr int n = 2; };
 
-// Storage type TS, propagation type TP (state, path solve, transport,
-// Jacobian), covariance type TC (registers, F P F^T and update).  MAT: the
-// layers carry material, applied to a copy of the state when it leaves a
-// layer (the filtered state stays the result if the next layer is missed).
+// One pass of the filter over a track's layers from the start state (x, P):
+// x and P end as the filtered state at the last layer reached (layer `at`,
+// -1 if none).  Storage type TS,
+// propagation type TP (state, path solve, transport, Jacobian), covariance
+// type TC (registers, F P F^T and update).  MAT: the layers carry material,
+// applied to a copy of the state when it leaves a layer (the filtered state
+// stays the result if the next layer is missed).
 template <typename TS, typename TP, typename TC, bool MAT>
-__device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
+__device__ __forceinline__ void fit_pass(const FitArgs& a, int64_t i, uint32_t vmask, TP k,
+                                         TrackState<TP>& x, TC P[21], double& chi2, int32_t& nupd,
+                                         uint32_t& status, int& at) {
   const int64_t p = a.pitch;
-  const TS* st = static_cast<const TS*>(a.state);
-  const TS* cv = static_cast<const TS*>(a.cov);
-  TrackState<TP> x;
-  TC P[21];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * p + i];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * p + i];
-#pragma unroll
-  for (int c = 0; c < 21; ++c) P[c] = (TC)cv[c * p + i];
-  const TP k = (TP)(kCLight * (double)a.q[i] * a.bz);
-  const int L = a.n_layers;
-  uint32_t vmask = 0;
-  for (int l = 0; l < L; ++l)
-    if (a.valid == nullptr || a.valid[l * p + i]) vmask |= 1u << l;
   const int lend = vmask ? 32 - __builtin_clz(vmask) : 1;
-
   const HitRes hr{a.hr.sr2, a.hr.srphi2, a.hr.sz2};
-  double chi2 = 0.0;
-  int32_t nupd = 0;
-  uint32_t status = 0;
+  chi2 = 0.0;
+  nupd = 0;
+  status = 0;
+  at = -1;
   const TS* hits = static_cast<const TS*>(a.hits);
   // the next layer's hit is loaded one layer ahead so that its latency
   // hides behind the current layer's arithmetic
@@ -90,6 +80,7 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
       }
       cov_propagate(P, F, Pp);
     }
+    at = l;
     bool used = false;
     if ((vmask >> l) & 1u) {
       Residual R;
@@ -112,25 +103,91 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
       break;
     }
   }
+}
+
+// The state on layer `from` carried back to layer 0 along its helix: the
+// same helix travelled with reversed momentum and charge, one layer at a
+// time, giving back the mean energy lost when leaving each crossed layer.
+template <typename TP, bool MAT>
+__device__ __forceinline__ bool carry_back(const FitArgs& a, TP k, int from, TrackState<TP>& x) {
+  for (int l = from - 1; l >= 0; --l) {
+    TrackState<TP> xr = x, xo;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xr.mom[c] = -x.mom[c];
+    Jac<TP> F;
+    if (!propagate<TP, NewtonIters<TP>::n>(xr, -k, a.radii[l], true, xo, F)) return false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x.pos[c] = xo.pos[c];
+      x.mom[c] = -xo.mom[c];
+    }
+    if constexpr (MAT) {
+      if (a.mat.x0[l] > 0.0 && a.mat.eloss > 0.0) undo_energy_loss(a.mat.x0[l], a.mat.eloss, a.mat.mass, x);
+    }
+  }
+  return true;
+}
+
+// The fit of one track: one pass, or (REFIT) an iterated refit over
+// a.n_passes passes: each further pass refits from the previous pass's
+// result carried back to layer 0, with the seed covariance.  A pass that
+// sets a status bit the pass before did not is dropped and ends the refit,
+// as does a result that is non-finite or cannot be carried back; the kept
+// pass's result stays in the outputs.  The single pass is its own
+// instantiation so that it keeps its register allocation.
+template <typename TS, typename TP, typename TC, bool MAT, bool REFIT>
+__device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
+  const int64_t p = a.pitch;
+  const TS* st = static_cast<const TS*>(a.state);
+  const TS* cv = static_cast<const TS*>(a.cov);
+  TrackState<TP> x;
+  TC P[21];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * p + i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * p + i];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) P[c] = (TC)cv[c * p + i];
+  const TP k = (TP)(kCLight * (double)a.q[i] * a.bz);
+  uint32_t vmask = 0;
+  for (int l = 0; l < a.n_layers; ++l)
+    if (a.valid == nullptr || a.valid[l * p + i]) vmask |= 1u << l;
   TS* so = static_cast<TS*>(a.state_o);
   TS* co = static_cast<TS*>(a.cov_o);
+  uint32_t kept = 0;
+  const int npass = REFIT ? a.n_passes : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+    if (pass > 0) {  // the seed covariance again
 #pragma unroll
-  for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
+      for (int c = 0; c < 21; ++c) P[c] = (TC)cv[c * p + i];
+    }
+    double chi2;
+    int32_t nupd;
+    uint32_t status;
+    int at;
+    fit_pass<TS, TP, TC, MAT>(a, i, vmask, k, x, P, chi2, nupd, status, at);
+    if (pass > 0 && status != 0 && kept == 0) break;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x.mom[c];
+    for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
 #pragma unroll
-  for (int c = 0; c < 21; ++c) co[c * p + i] = (TS)P[c];
-  a.chi2[i] = chi2;
-  a.nupd[i] = nupd;
-  a.status[i] = status;
+    for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x.mom[c];
+#pragma unroll
+    for (int c = 0; c < 21; ++c) co[c * p + i] = (TS)P[c];
+    a.chi2[i] = chi2;
+    a.nupd[i] = nupd;
+    a.status[i] = status;
+    kept = status;
+    if constexpr (!REFIT) break;
+    if (pass + 1 >= npass || (status & kNonFinite) || at < 0 || !carry_back<TP, MAT>(a, k, at, x)) break;
+  }
 }
 
 // W: the waves per SIMD the register allocation must allow (1 leaves it to
 // the compiler; more trades registers, and maybe spills, for latency hiding)
-template <typename TS, typename TP, typename TC, int BS, int W, bool MAT>
+template <typename TS, typename TP, typename TC, int BS, int W, bool MAT, bool REFIT = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_fused_kernel(FitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < a.n) fit_one_track<TS, TP, TC, MAT>(a, i);
+  if (i < a.n) fit_one_track<TS, TP, TC, MAT, REFIT>(a, i);
 }
 
 // Persistent blocks: every block loops taking the next tile of BS tracks
@@ -145,7 +202,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fi
     __syncthreads();
     if (t >= a.tile_count) break;
     const int64_t i = t * BS + threadIdx.x;
-    if (i < a.n) fit_one_track<TS, TP, TC, MAT>(a, i);
+    if (i < a.n) fit_one_track<TS, TP, TC, MAT, false>(a, i);
   }
 }
 
@@ -284,6 +341,19 @@ static hipError_t launch_fused_bs(const FitArgs& a, bool persistent, int pblocks
                   : launch_fused_m<TS, TP, TC, BS, W, false>(a, persistent, pblocks, st);
 }
 
+// the iterated refit: one launch shape (256 threads, the compiler's
+// register allocation, plain grid)
+template <typename TS, typename TP, typename TC>
+static hipError_t launch_refit(const FitArgs& a, hipStream_t st) {
+  constexpr int BS = 256;
+  const unsigned nb = (unsigned)((a.n + BS - 1) / BS);
+  if (a.mat.on)
+    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS, 1, true, true>), dim3(nb), dim3(BS), 0, st, a);
+  else
+    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS, 1, false, true>), dim3(nb), dim3(BS), 0, st, a);
+  return hipGetLastError();
+}
+
 template <typename TS, typename TP, typename TC, int W>
 static hipError_t launch_fused_w(const FitArgs& a, int bs, bool persistent, int pblocks, hipStream_t st) {
   switch (bs) {
@@ -309,6 +379,10 @@ static hipError_t launch_fused_t(const FitArgs& a, int bs, int waves, bool persi
 hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, int waves, bool persistent,
                             int persistent_blocks, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
+  if (a.n_passes > 1) {  // a double covariance (checked at the boundary)
+    if (prec == KTF_FP64) return launch_refit<double, double, double>(a, st);
+    return launch_refit<float, float, double>(a, st);
+  }
   if (prec == KTF_FP64)
     return launch_fused_t<double, double, double>(a, bs, waves, persistent, persistent_blocks, st);
   if (prec == KTF_FP32_PROP)

@@ -544,6 +544,21 @@ KTF_HD void apply_material(double x0, double eloss, double mass, TrackState<T>& 
   }
 }
 
+// Inverse of the mean energy loss of apply_material for a state that has
+// just crossed the layer inwards: |p| back to sqrt((E + eloss t)^2 - m^2).
+template <typename T>
+KTF_HD void undo_energy_loss(double x0, double eloss, double mass, TrackState<T>& x) {
+  const double p[3] = {(double)x.mom[0], (double)x.mom[1], (double)x.mom[2]};
+  const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  const double pm = sqrt(p2);
+  const double r = sqrt(x.pos[0] * x.pos[0] + x.pos[1] * x.pos[1]);
+  const double t = x0 * pm / fabs((x.pos[0] * p[0] + x.pos[1] * p[1]) / r);
+  const double E = sqrt(p2 + mass * mass) + eloss * t;
+  const double f = sqrt(E * E - mass * mass) / pm;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) x.mom[i] = (T)(f * p[i]);
+}
+
 template <typename T, typename C>
 KTF_HD bool finite_state(const TrackState<T>& x, const C P[21]) {
   C acc = (C)(x.pos[0] + x.pos[1] + x.pos[2]);

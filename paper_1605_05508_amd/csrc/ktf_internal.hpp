@@ -38,6 +38,7 @@ struct FitArgs {
   unsigned long long* counters;  // persistent: tile counters
   int64_t tile_count;   // persistent: number of tiles
   int32_t n_layers;
+  int32_t n_passes;     // fused fits: passes of the iterated refit, >= 1
   double bz;
   HitResD hr;
   double radii[KTF_MAX_LAYERS];
