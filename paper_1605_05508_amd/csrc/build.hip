@@ -12,8 +12,10 @@
 //   merge   a lane group per seed: merge the candidates' sorted record
 //           lists to the best max_cands by the ranking (more hits, lower chi2, lower
 //           parent rank, lower hit index, a missed layer last);
-//   clone   one lane per selected record: clone its parent's propagated
-//           state and apply the Kalman update with the record's hit;
+//   clone   applying each kept record's update to its parent's propagated
+//           state (the child) is folded into the next layer's score, which
+//           needs the child anyway; only the children of the last layer
+//           are cloned by a kernel of their own;
 //   final   one lane per seed: the best survivor or ended candidate, hit
 //           indices recovered by walking the per-layer (parent, hit) records.
 //
@@ -72,7 +74,8 @@ struct BuildArgs {
   int32_t* cseed[2];       // [S]: seed of each dense candidate row
   int32_t* cstart[2];      // [sp]: first dense row of each seed's candidates
   int32_t* sel_parent;     // [S]: per child row, its parent's row
-  int32_t* sel_rec;        // [S]: per child row, the parent's record it takes
+  int32_t* sel_hit;        // [S]: per child row, the hit it takes (-1: missed layer)
+  double* sel_chi2;        // [S]: per child row, its chi2 total
   unsigned* ccount;        // [n_layers][kRegions][kCtrStride]: rows used per region after each layer
   void* hb;                // [3][n_hits]: binned coordinates
   // candidates (double buffered), propagated parents, records
@@ -81,12 +84,11 @@ struct BuildArgs {
   void* ccov[2];
   double* cchi2[2];
   uint32_t* cmeta[2];      // nh | nm << 8 | status << 16
-  double* ppos;
-  void* pmom;
-  void* pcov;
+  double* ppos[2];         // propagated candidates, by layer parity
+  void* pmom[2];
+  void* pcov[2];
   double* rchi;            // [max_cands][S]
   int32_t* rhit;           // [max_cands][S]: original hit index
-  int32_t* rpos;           // [max_cands][S]: binned position of the hit
   int32_t* rcount;         // [S]: records, -1 ended (no reach), -2 ended (missed too often)
   int32_t* hist;           // [L][max_cands][2][sp]
   int32_t* count;          // [L][sp]
@@ -639,10 +641,46 @@ __device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32
   return c1 < c2 || (c1 == c2 && (uint32_t)h1 < (uint32_t)h2);
 }
 
+// A child of layer l (row c of the buffer `to`): its parent's propagated
+// state on layer l with the Kalman update of the hit it took (a missed layer
+// keeps the propagated state); returns its meta word.
+template <typename TS, typename TP>
+__device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int from, int64_t c, int64_t s,
+                                               TrackState<TP>& x, TP P[21]) {
+  const int64_t p = a.sel_parent[c];
+  const int32_t h = a.sel_hit[c];
+  const uint32_t pm = a.cmeta[from][p];
+  TrackState<TP> xq;
+  TP Pq[21];
+  load_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], a.S, p, xq, Pq);
+  int cnh = meta_nh(pm), cnm = meta_nm(pm);
+  if (h >= 0) {
+    const int64_t hi = a.hit_off[(int64_t)a.sev[s] * a.g.n_layers + l] + h;
+    const TS* hits = static_cast<const TS*>(a.hits);
+    const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
+    Residual R;
+    residual(xq, Pq, m, hit_res(a), R);  // scored positive definite already
+    apply_update(xq, Pq, R, x, P);
+    ++cnh;
+  } else {
+    x = xq;
+#pragma unroll
+    for (int i = 0; i < 21; ++i) P[i] = Pq[i];
+    ++cnm;
+  }
+  return pack_meta(cnh, cnm, meta_st(pm));
+}
+
 // One lane per live candidate (dense row c of the current buffer).  MAT:
-// the layers carry material.
-template <typename TS, typename TP, bool MAT>
-__global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, int cur) {
+// the layers carry material.  CHILD: the candidates are the children kept
+// on layer l - 1, made here from their parents' propagated states (their
+// state is stored only if they end here, for the best-ended choice);
+// otherwise they are stored (the seeds' fits).
+// (The float child variant is held to three waves per SIMD: left alone it
+// takes one register over the budget and runs at two.)
+template <typename TS, typename TP, bool MAT, bool CHILD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(TP) == 4 && CHILD ? 3 : 1)))
+void build_score_kernel(BuildArgs a, int l, int cur) {
   int64_t c;
   if (!block_row(a, l - 1, c)) return;
   const int64_t s = a.cseed[cur][c];
@@ -651,24 +689,42 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
   const int e = a.sev[s];
   TrackState<TP> x;
   TP P[21];
-  load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], S, c, x, P);
-  const uint32_t meta = a.cmeta[cur][c];
-  const double pchi2 = a.cchi2[cur][c];
+  uint32_t meta;
+  double pchi2;
+  if constexpr (CHILD) {
+    meta = make_child<TS, TP>(a, l - 1, cur ^ 1, c, s, x, P);
+    pchi2 = a.sel_chi2[c];
+    a.cmeta[cur][c] = meta;
+    a.cchi2[cur][c] = pchi2;
+  } else {
+    load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], S, c, x, P);
+    meta = a.cmeta[cur][c];
+    pchi2 = a.cchi2[cur][c];
+  }
+  // an ended child keeps its filtered state for the best-ended choice
+  auto store_ended = [&]() {
+    if constexpr (CHILD) {
+      TrackState<TP> xc;
+      TP Pc[21];
+      make_child<TS, TP>(a, l - 1, cur ^ 1, c, s, xc, Pc);
+      store_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], S, c, xc, Pc);
+    }
+  };
   const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
   TrackState<TP> xp;
   Jac<TP> F;
-  // the material of the layer being left (the stored candidate keeps its
-  // filtered state)
+  // the material of the layer being left
   if constexpr (MAT) {
     if (a.g.mat.x0[l - 1] > 0.0) apply_material(a.g.mat.x0[l - 1], a.g.mat.eloss, a.g.mat.mass, x, P);
   }
   if (!propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[l], false, xp, F)) {
     a.rcount[c] = -1;
+    store_ended();
     return;
   }
   TP Pp[21];
   cov_propagate(P, F, Pp);
-  store_cand<TS, TP>(a.ppos, a.pmom, a.pcov, S, c, xp, Pp);
+  store_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], S, c, xp, Pp);
 
   // search window: for any unit vector u, chi2 < cut implies
   // |u.d| < sqrt(cut u^T S u) (Cauchy-Schwarz in the S^-1 metric); with u
@@ -708,7 +764,6 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
   int nrec = 0;
   double* rchi = a.rchi;
   int32_t* rhit = a.rhit;
-  int32_t* rpos = a.rpos;
   for (int zb = zlo; zb <= zhi; ++zb) {
     // up to two contiguous runs of phi bins (wrap-around)
     int runs[2][2];
@@ -743,12 +798,10 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
         while (pos > 0 && rec_less(c2, hid, rchi[(int64_t)(pos - 1) * S + c], rhit[(int64_t)(pos - 1) * S + c])) {
           rchi[(int64_t)pos * S + c] = rchi[(int64_t)(pos - 1) * S + c];
           rhit[(int64_t)pos * S + c] = rhit[(int64_t)(pos - 1) * S + c];
-          rpos[(int64_t)pos * S + c] = rpos[(int64_t)(pos - 1) * S + c];
           --pos;
         }
         rchi[(int64_t)pos * S + c] = c2;
         rhit[(int64_t)pos * S + c] = hid;
-        rpos[(int64_t)pos * S + c] = (int32_t)hj;
         if (nrec < NC) ++nrec;
       }
     }
@@ -757,10 +810,10 @@ __global__ __launch_bounds__(256) void build_score_kernel(BuildArgs a, int l, in
     if (meta_nm(meta) < a.g.max_missed) {
       rchi[c] = pchi2;
       rhit[c] = -1;
-      rpos[c] = -1;
       nrec = 1;
     } else {
       a.rcount[c] = -2;
+      store_ended();
       return;
     }
   }
@@ -833,6 +886,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   __shared__ int wtot[kMergeThreads / 64 + 1];
   __shared__ int pick_s[kMergeSeeds][4 * PPL];  // parent | record << 8
   __shared__ int phit_s[kMergeSeeds][4 * PPL];
+  __shared__ double pchi_s[kMergeSeeds][4 * PPL];
   const int NC = a.g.max_cands;
   const int tid = threadIdx.x;
   const int q = tid & 3, ls = tid >> 2;
@@ -934,6 +988,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     if (q == 0) {
       pick_s[ls][k] = w.pj;
       phit_s[ls][k] = w.hit;
+      pchi_s[ls][k] = w.c;
     }
     const int wj = w.pj >> 8;
     if ((wj & 3) == q) {  // the owner lane advances that parent's head
@@ -967,46 +1022,25 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = pk >> 8;
     a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = phit_s[ls][k];
     a.sel_parent[first + k] = (int32_t)(pbase + (pk >> 8));
-    a.sel_rec[first + k] = pk & 0xff;
+    a.sel_hit[first + k] = phit_s[ls][k];
+    a.sel_chi2[first + k] = pchi_s[ls][k];
     a.cseed[cur ^ 1][first + k] = (int32_t)s;
   }
 }
 
-// One lane per child (dense row of the next buffer): clone the selected
-// record's parent from its propagated state and apply the Kalman update with
-// the record's hit (a missed layer keeps the propagated state).
+// The children kept on the last layer (dense rows of buffer `to`), made
+// from their parents' propagated states and stored for the final choice.
 template <typename TS, typename TP>
-__global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int cur) {
+__global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int to) {
   int64_t c;
   if (!block_row(a, l, c)) return;
-  const int nxt = cur ^ 1;
-  const int64_t S = a.S;
-  const int64_t p = a.sel_parent[c];
-  const int rec = a.sel_rec[c];
-  const int32_t h = a.rhit[(int64_t)rec * S + p];
-  const double c2 = a.rchi[(int64_t)rec * S + p];
-  const uint32_t pm = a.cmeta[cur][p];
-  TrackState<TP> xp;
-  TP Pp[21];
-  load_cand<TS, TP>(a.ppos, a.pmom, a.pcov, S, p, xp, Pp);
-  int cnh = meta_nh(pm), cnm = meta_nm(pm);
-  if (h >= 0) {
-    const int64_t hp = a.rpos[(int64_t)rec * S + p];
-    const TS* hb = static_cast<const TS*>(a.hb);
-    const double m[3] = {(double)hb[hp], (double)hb[a.n_hits + hp], (double)hb[2 * a.n_hits + hp]};
-    Residual R;
-    residual(xp, Pp, m, hit_res(a), R);  // scored positive definite already
-    TrackState<TP> x;
-    TP P[21];
-    apply_update(xp, Pp, R, x, P);
-    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, c, x, P);
-    ++cnh;
-  } else {
-    store_cand<TS, TP>(a.cpos[nxt], a.cmom[nxt], a.ccov[nxt], S, c, xp, Pp);
-    ++cnm;
-  }
-  a.cchi2[nxt][c] = c2;
-  a.cmeta[nxt][c] = pack_meta(cnh, cnm, meta_st(pm));
+  const int64_t s = a.cseed[to][c];
+  TrackState<TP> x;
+  TP P[21];
+  const uint32_t meta = make_child<TS, TP>(a, l, to ^ 1, c, s, x, P);
+  store_cand<TS, TP>(a.cpos[to], a.cmom[to], a.ccov[to], a.S, c, x, P);
+  a.cchi2[to][c] = a.sel_chi2[c];
+  a.cmeta[to][c] = meta;
 }
 
 // ------------------------------------------------------------------ final
@@ -1137,15 +1171,22 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   else
     hipLaunchKernelGGL((build_seed_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   int cur = 0;
+  const dim3 rows(nblk(a.S, bs));
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
-    if (a.g.mat.on)
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, true>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
+    const bool child = l > a.g.n_seed_layers;  // candidates kept on layer l - 1, not yet made
+    if (a.g.mat.on && child)
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, true>), rows, dim3(bs), 0, st, a, l, cur);
+    else if (a.g.mat.on)
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, false>), rows, dim3(bs), 0, st, a, l, cur);
+    else if (child)
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, true>), rows, dim3(bs), 0, st, a, l, cur);
     else
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, false>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, false>), rows, dim3(bs), 0, st, a, l, cur);
     launch_merge<TS>(a, l, cur, st);
-    hipLaunchKernelGGL((build_clone_kernel<TS, TP>), dim3(nblk(a.S, bs)), dim3(bs), 0, st, a, l, cur);
     cur ^= 1;
   }
+  if (a.g.n_layers > a.g.n_seed_layers)  // the last layer's children, for the final choice
+    hipLaunchKernelGGL((build_clone_kernel<TS, TP>), rows, dim3(bs), 0, st, a, a.g.n_layers - 1, cur);
   hipLaunchKernelGGL((build_final_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
   return hipGetLastError();
 }
@@ -1270,24 +1311,28 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     p += (size_t)S * 21 * ts;
     a.cmeta[b] = reinterpret_cast<uint32_t*>(p);
   }
-  if ((e = c->b_prop.ensure((size_t)S * (3 * 8 + 24 * ts))) != hipSuccess) return hip_fail(c, e, "workspace");
+  if ((e = c->b_prop.ensure(2 * (size_t)S * (3 * 8 + 24 * ts + 8) + 8)) != hipSuccess)
+    return hip_fail(c, e, "workspace");
   {
     char* p = static_cast<char*>(c->b_prop.p);
-    a.ppos = reinterpret_cast<double*>(p);
-    p += (size_t)S * 3 * 8;
-    a.pmom = p;
-    p += (size_t)S * 3 * ts;
-    a.pcov = p;
+    for (int b = 0; b < 2; ++b) {
+      a.ppos[b] = reinterpret_cast<double*>(p);
+      p += (size_t)S * 3 * 8;
+      a.pmom[b] = p;
+      p += (size_t)S * 3 * ts;
+      a.pcov[b] = p;
+      p += (size_t)S * 21 * ts;
+    }
+    p = reinterpret_cast<char*>(((uintptr_t)p + 7) & ~(uintptr_t)7);
+    a.sel_chi2 = reinterpret_cast<double*>(p);
   }
   const int NC = cfg.max_cands;
-  if ((e = c->b_rec.ensure((size_t)S * (NC * 16 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
+  if ((e = c->b_rec.ensure((size_t)S * (NC * 12 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
   {
     char* p = static_cast<char*>(c->b_rec.p);
     a.rchi = reinterpret_cast<double*>(p);
     p += (size_t)S * NC * 8;
     a.rhit = reinterpret_cast<int32_t*>(p);
-    p += (size_t)S * NC * 4;
-    a.rpos = reinterpret_cast<int32_t*>(p);
     p += (size_t)S * NC * 4;
     a.rcount = reinterpret_cast<int32_t*>(p);
   }
@@ -1320,7 +1365,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.cseed[0] = p;
     a.cseed[1] = p + S;
     a.sel_parent = p + 2 * S;
-    a.sel_rec = p + 3 * S;
+    a.sel_hit = p + 3 * S;
     a.cstart[0] = p + 4 * S;
     a.cstart[1] = p + 4 * S + sp;
     a.ccount = reinterpret_cast<unsigned*>(p + ctr_at);
