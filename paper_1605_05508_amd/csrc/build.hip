@@ -415,37 +415,70 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
     }
   }
   __syncthreads();
-  // order every bin by original index and copy the coordinates
-  TS* o = static_cast<TS*>(a.hb);
-  for (int32_t j0 = 0; j0 < n; j0 += kBinBatch * kBinThreads) {
+  // order every bin by original index: a hit's place is the number of its
+  // bin's hits with a smaller index; the places stay in registers until all
+  // are taken, then the permutation goes to LDS and out in coalesced rows
+  // (scattered 4-byte stores would each cost HBM a line)
+  constexpr int kMaxBatches = kPackMaxHits / (kBinBatch * kBinThreads);
+  int dst[kMaxBatches][kBinBatch];
+#pragma unroll
+  for (int bi = 0; bi < kMaxBatches; ++bi) {
+    const int32_t j0 = bi * kBinBatch * kBinThreads;
     int bb[kBinBatch];
-    TS x[kBinBatch], y[kBinBatch], z[kBinBatch];
 #pragma unroll
     for (int u = 0; u < kBinBatch; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
-      bb[u] = 0;
-      x[u] = y[u] = z[u] = TS(0);
-      if (j < n) {
-        bb[u] = a.hit_bin[base + j];
-        x[u] = h[base + j];
-        y[u] = h[a.hp + base + j];
-        z[u] = h[2 * a.hp + base + j];
-      }
+      bb[u] = j < n ? a.hit_bin[base + j] : 0;
     }
 #pragma unroll
     for (int u = 0; u < kBinBatch; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
+      dst[bi][u] = -1;
       if (j < n) {
         const int b = bb[u];
         const int32_t hi = (int32_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
         const int32_t lo = b > 0 ? (int32_t)((cnt[(b - 1) >> 1] >> (((b - 1) & 1) * 16)) & 0xffffu) : 0;
         int32_t rank = 0;
         for (int32_t k = lo; k < hi; ++k) rank += permr[k] < j ? 1 : 0;
-        const int64_t dst = base + lo + rank;
-        a.perm[dst] = j;
-        o[dst] = x[u];
-        o[a.n_hits + dst] = y[u];
-        o[2 * a.n_hits + dst] = z[u];
+        dst[bi][u] = lo + rank;
+      }
+    }
+  }
+  __syncthreads();  // every place is taken; the unordered scatter is done with
+#pragma unroll
+  for (int bi = 0; bi < kMaxBatches; ++bi)
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u)
+      if (dst[bi][u] >= 0) permr[dst[bi][u]] = (uint16_t)(bi * kBinBatch * kBinThreads + u * kBinThreads + tid);
+  __syncthreads();
+  TS* o = static_cast<TS*>(a.hb);
+  for (int32_t i0 = 0; i0 < n; i0 += kBinBatch * kBinThreads) {
+    int32_t jj[kBinBatch];
+    TS x[kBinBatch], y[kBinBatch], z[kBinBatch];
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t i = i0 + u * kBinThreads + tid;
+      jj[u] = i < n ? (int32_t)permr[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t i = i0 + u * kBinThreads + tid;
+      x[u] = y[u] = z[u] = TS(0);
+      if (i < n) {
+        x[u] = h[base + jj[u]];
+        y[u] = h[a.hp + base + jj[u]];
+        z[u] = h[2 * a.hp + base + jj[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBinBatch; ++u) {
+      const int32_t i = i0 + u * kBinThreads + tid;
+      if (i < n) {
+        const int64_t d = base + i;
+        a.perm[d] = jj[u];
+        o[d] = x[u];
+        o[a.n_hits + d] = y[u];
+        o[2 * a.n_hits + d] = z[u];
       }
     }
   }
