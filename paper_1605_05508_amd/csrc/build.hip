@@ -783,8 +783,10 @@ void build_score_kernel(BuildArgs a, int l, int cur) {
   int plo = 0, phi_hi = nphi - 1;
   bool full_phi = true;
   if (sphi < 0.5) {
-    const double dphi = 1.1 * sphi;  // asin(x) <= 1.1 x for x <= 0.5
-    const double php = atan2(xp.pos[1], xp.pos[0]);
+    // asin(x) <= 1.1 x for x <= 0.5; the window centre in float (an error
+    // of a few 1e-7 rad, covered by the 1e-5 added)
+    const double dphi = 1.1 * sphi + 1e-5;
+    const double php = (double)atan2f((float)xp.pos[1], (float)xp.pos[0]);
     plo = (int)floor((php - dphi + kPi) * nphi / (2.0 * kPi));
     phi_hi = (int)floor((php + dphi + kPi) * nphi / (2.0 * kPi));
     full_phi = (phi_hi - plo + 1) >= nphi;
