@@ -553,6 +553,15 @@ __device__ __forceinline__ int64_t block_reserve(unsigned* counter, int n, int* 
   return (int64_t)(unsigned)wtot[nw] + before + (x - n);
 }
 
+// Region of this block in a launch that reserves rows (seed fit, merge):
+// contiguous ranges of at most ceil(gridDim / kRegions) blocks share a
+// region, so a region holds the candidates of neighbouring seeds (one or
+// two events), and blocks in flight together still spread their row
+// reservations over several counters.
+__device__ __forceinline__ int block_region() {
+  return (int)(((int64_t)blockIdx.x * kRegions) / gridDim.x);
+}
+
 __device__ __forceinline__ unsigned* region_ctr(const BuildArgs& a, int l, int r) {
   return a.ccount + ((int64_t)l * kRegions + r) * kCtrStride;
 }
@@ -657,7 +666,7 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
   }
   __shared__ int wtot[256 / 64 + 1];
   const int alive = valid && reached == NSL ? 1 : 0;
-  const int reg = blockIdx.x & (kRegions - 1);
+  const int reg = block_region();
   const int64_t row = reg * a.RS + block_reserve(region_ctr(a, NSL - 1, reg), alive, wtot);
   if (alive) {
     a.cstart[0][s] = (int32_t)row;
@@ -1045,7 +1054,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     }
     ++nsel;
   }
-  const int reg = blockIdx.x & (kRegions - 1);
+  const int reg = block_region();
   const int local = (int)block_reserve(region_ctr(a, l, reg), q == 0 ? nsel : 0, wtot);
   const int64_t first = reg * a.RS + dpp_i<0x00>(local);  // lane 0 of the quad
   if (real && q == 0) {
@@ -1151,8 +1160,8 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
 // -------------------------------------------------------------- host side
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Rows per region: enough for the blocks that reserve in one region (blocks
-// go to regions round robin), for the seed kernel (256 seeds of one row
+// Rows per region: enough for the blocks that reserve in one region (at
+// most ceil(blocks / kRegions), see block_region), for the seed kernel (256 seeds of one row
 // each per block) and for the merge (kMergeSeeds seeds of up to max_cands
 // rows each per block); a multiple of 256 rows (the row-kernel block).
 static int64_t region_rows(int64_t n_seeds, int nc) {
