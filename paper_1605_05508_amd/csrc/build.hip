@@ -566,17 +566,31 @@ __device__ __forceinline__ unsigned* region_ctr(const BuildArgs& a, int l, int r
   return a.ccount + ((int64_t)l * kRegions + r) * kCtrStride;
 }
 
-// Row of this thread for a launch of S / blockDim blocks over the rows
-// (RS a multiple of blockDim): consecutive blocks take the same chunk of
-// consecutive regions, so the rows in flight together belong to seeds close
-// in index (same events, same bins in cache).  Returns whether the row holds
-// a live candidate after layer l.
-__device__ __forceinline__ bool block_row(const BuildArgs& a, int l, int64_t& c) {
-  const int r = (int)(blockIdx.x % kRegions);
-  const int64_t local = (int64_t)(blockIdx.x / kRegions) * blockDim.x + threadIdx.x;
-  c = r * a.RS + local;
-  return local < (int64_t)*region_ctr(a, l, r);
-}
+// The row kernels (score, clone) run one lane per live candidate row after
+// layer l.  A launch has kRegions * k blocks: block b takes region
+// b % kRegions and, within it, the kRowChunks chunks b / kRegions + j k
+// (j = 0 .. kRowChunks - 1) of blockDim rows, each while it holds live
+// rows.  Consecutive blocks take the same chunk of consecutive regions, so
+// the rows in flight together belong to seeds close in index (same events,
+// same bins in cache), and a region's empty tail costs kRowChunks times
+// fewer blocks.  The chunks are written out rather than looped over: a loop
+// around the row body costs the row kernels registers.
+constexpr int kRowChunks = 4;
+#define ROW_CHUNK(J, CALL)                                                              \
+  if (l0_ + (J) * step_ < n_) {                                                         \
+    const int64_t c = r_ * rs_ + l0_ + (J) * step_;                                     \
+    CALL;                                                                               \
+  }
+#define ROW_CHUNKS(a, l, CALL)                                                          \
+  do {                                                                                  \
+    const int r_ = (int)(blockIdx.x % kRegions);                                        \
+    const int64_t n_ = *region_ctr(a, l, r_);                                           \
+    const int64_t rs_ = (a).RS;                                                         \
+    const int64_t step_ = (int64_t)(gridDim.x / kRegions) * blockDim.x;                 \
+    const int64_t l0_ = (int64_t)(blockIdx.x / kRegions) * blockDim.x + threadIdx.x;    \
+    static_assert(kRowChunks == 4, "ROW_CHUNKS writes out four chunks");                \
+    ROW_CHUNK(0, CALL) ROW_CHUNK(1, CALL) ROW_CHUNK(2, CALL) ROW_CHUNK(3, CALL)         \
+  } while (0)
 
 // seed phase: fit each seed over the seed layers with its own hits.  MAT:
 // the material of the layer being left goes onto a copy of the state, so
@@ -718,13 +732,11 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
 // on layer l - 1, made here from their parents' propagated states (their
 // state is stored only if they end here, for the best-ended choice);
 // otherwise they are stored (the seeds' fits).
-// (The float child variant is held to three waves per SIMD: left alone it
-// takes one register over the budget and runs at two.)
+// (The child variants are held to three waves per SIMD: left alone they
+// take a few registers over that budget and run at two, which costs more
+// than the few registers the cap spills in double.)
 template <typename TS, typename TP, bool MAT, bool CHILD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(TP) == 4 && CHILD ? 3 : 1)))
-void build_score_kernel(BuildArgs a, int l, int cur) {
-  int64_t c;
-  if (!block_row(a, l - 1, c)) return;
+__device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, int64_t c) {
   const int64_t s = a.cseed[cur][c];
   const int L = a.g.n_layers, NC = a.g.max_cands;
   const int64_t S = a.S;
@@ -862,6 +874,12 @@ void build_score_kernel(BuildArgs a, int l, int cur) {
     }
   }
   a.rcount[c] = nrec;
+}
+
+template <typename TS, typename TP, bool MAT, bool CHILD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHILD ? 3 : 1)))
+void build_score_kernel(BuildArgs a, int l, int cur) {
+  ROW_CHUNKS(a, l - 1, (score_row<TS, TP, MAT, CHILD>(a, l, cur, c)));
 }
 
 // ----------------------------------------------------------------- select
@@ -1075,9 +1093,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
 // The children kept on the last layer (dense rows of buffer `to`), made
 // from their parents' propagated states and stored for the final choice.
 template <typename TS, typename TP>
-__global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int to) {
-  int64_t c;
-  if (!block_row(a, l, c)) return;
+__device__ __forceinline__ void clone_row(const BuildArgs& a, int l, int to, int64_t c) {
   const int64_t s = a.cseed[to][c];
   TrackState<TP> x;
   TP P[21];
@@ -1085,6 +1101,11 @@ __global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, in
   store_cand<TS, TP>(a.cpos[to], a.cmom[to], a.ccov[to], a.S, c, x, P);
   a.cchi2[to][c] = a.sel_chi2[c];
   a.cmeta[to][c] = meta;
+}
+
+template <typename TS, typename TP>
+__global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int to) {
+  ROW_CHUNKS(a, l, (clone_row<TS, TP>(a, l, to, c)));
 }
 
 // ------------------------------------------------------------------ final
@@ -1215,7 +1236,7 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   else
     hipLaunchKernelGGL((build_seed_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   int cur = 0;
-  const dim3 rows(nblk(a.S, bs));
+  const dim3 rows((unsigned)(kRegions * ((a.RS / bs + kRowChunks - 1) / kRowChunks)));
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     const bool child = l > a.g.n_seed_layers;  // candidates kept on layer l - 1, not yet made
     if (a.g.mat.on && child)
