@@ -85,11 +85,12 @@ def parse():
     ap.add_argument("--profile", choices=["fit", "sweep", "build", "copy"], default=None,
                     help="only one timed loop, for rocprofv3 runs (copy: a plain copy of "
                          "known size to calibrate the HBM byte counters)")
-    ap.add_argument("--workload", choices=["fit", "uneven", "dense_events", "material"], default="fit",
+    ap.add_argument("--workload", choices=["fit", "uneven", "dense_events", "material", "shapes"], default="fit",
                     help="fit: the headline line; uneven: events of uneven size in one "
                          "launch versus per-event launches; dense_events: building on "
                          "20,000-track events, combinatorial and best-hit; material: the "
-                         "fit at scale through layer material")
+                         "fit at scale through layer material; shapes: the fit's time per "
+                         "launch shape and its throughput from 1e3 to 1e7 tracks")
     ap.add_argument("--no-build", action="store_true", help="skip the building measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-events", type=int, default=200)
@@ -221,6 +222,19 @@ def build_measurement(ctx_cls, tg, torch, reps=5, orc=None, bs=None, precs=("fp3
                                      **build_efficiency(hit1, bs.true_idx)}
             del o1
             ctx1.close()
+            # the paper's eta partition (Sec. 3) as a seed order: each event's
+            # seeds grouped by eta bin, so neighbouring lanes search
+            # neighbouring hit bins; every seed's result is unchanged
+            perm = tg.eta_order(bs, n_bins=21)
+            de = build_inputs(tg.permute_seeds(bs, perm), prec)
+            oe = ctx.build(de)
+            mse = time_build(ctx, de, oe, reps, torch)
+            inv = np.empty_like(perm)
+            inv[perm] = np.arange(bs.n_seeds)
+            hite = oe["hit_idx"].cpu().numpy()[:, :bs.n_seeds][:, inv]
+            out["fp32b_eta_order"] = {"ms": round(mse, 3), "seeds_per_s": round(bs.n_seeds / (mse * 1e-3)),
+                                      "eta_bins": 21, "same_hits_as_generation_order": bool(np.array_equal(hite, hit))}
+            del de, oe
         del d, o
     if orc is not None:
         m = 100
@@ -250,6 +264,55 @@ def dense_events_workload(args):
                       "config": {"workload": "25 events x 20,000 tracks, 17 barrel layers, +20% noise hits, "
                                              "64 x 512 bins, chi2 < 30, one missed layer"},
                       "building": res}), flush=True)
+
+
+def shapes_workload(args):
+    """Launch shape and problem size, the GPU's counterpart of the paper's
+    vector-width and thread-count scans (Sec. 3.2): the fused FP32-bulk fit's
+    time for every launch shape the tuner tries on 1e6 tracks (tracks per
+    block, register budget in waves per SIMD, plain or persistent grid), and
+    the tuned fit's throughput from 1e3 to 1e7 tracks (1e7 as ten copies of
+    the 1e6 tracks)."""
+    import torch
+    import paper_1605_05508_amd as ktf
+    import trackgen as tg
+    from tests.helpers import fit_inputs
+    print("[bench] generating 1e6 tracks", file=sys.stderr, flush=True)
+    fs = tg.config2()
+    n = fs.n
+    ctx = ktf.Context.for_detector(fs.det)
+    d = fit_inputs(fs, "fp32b", pitch=n)
+    out = ctx.alloc_fit_out(n, n, torch.float32)
+    ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out)
+    tuned = json.loads(ctx.tuned_shape("fp32b", n, trials=True))
+    trials = [{"block": b, "waves_per_simd": w, "persistent": bool(p), "ms": ms}
+              for b, w, p, ms in tuned.pop("trials")]
+    del out
+    scan = []
+    for m in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):
+        print(f"[bench] size {m}", file=sys.stderr, flush=True)
+        if m <= n:
+            x = dict(d, q=d["q"][:m])
+            pitch = n
+        else:
+            k = m // n
+            x = dict(state=d["state"].repeat(1, k), cov=d["cov"].repeat(1, k), q=d["q"].repeat(k),
+                     hits=d["hits"].repeat(1, 1, k), valid=d["valid"].repeat(1, k))
+            pitch = m
+        o = ctx.alloc_fit_out(m, pitch, torch.float32)
+        ctx.autotune_fit(x["state"], x["cov"], x["q"], x["hits"], x["valid"], out=o)
+        run = lambda: ctx.fit(x["state"], x["cov"], x["q"], x["hits"], x["valid"], out=o)
+        ms, _ = timed_loop(run, args.steps, args.warmup, torch)
+        scan.append({"tracks": m, "ms": round(ms, 4), "tracks_per_s": round(m / (ms * 1e-3)),
+                     "launch": json.loads(ctx.tuned_shape("fp32b", m))})
+        del x, o
+        torch.cuda.synchronize()
+    print(json.dumps({"metric": "fused FP32-bulk fit time per launch shape and tracks/s per problem size",
+                      "value": scan[-2]["tracks_per_s"], "unit": "tracks/s", "n_gpus": 1,
+                      "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+                      "config": {"workload": "1,000,000 tracks, 10 barrel layers r=4..40 cm, Bz=3.8 T, "
+                                             "pT log-uniform 0.5-100 GeV; sizes 1e3..1e7"},
+                      "tuned_1e6": tuned, "shapes_1e6": trials, "size_scan": scan}), flush=True)
 
 
 def material_workload(args):
@@ -442,6 +505,9 @@ def main():
         return
     if args.workload == "dense_events":
         dense_events_workload(args)
+        return
+    if args.workload == "shapes":
+        shapes_workload(args)
         return
     if args.workload == "material":
         material_workload(args)

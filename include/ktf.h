@@ -176,11 +176,14 @@ int ktf_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, ktf_fit_mode m
 
 /* Time each launch shape of the fused fit (block size 64..512 x plain or
  * persistent x a register budget of 1, 2 or 3 waves per SIMD) on the given
- * inputs and keep the fastest for this precision and size class;
- * KTF_FIT_AUTO then uses it.  Runs synchronously on hip_stream and
- * overwrites out. */
+ * inputs, in two rounds keeping each shape's faster one, and keep the
+ * fastest shape for this precision and size class; KTF_FIT_AUTO then uses
+ * it.  Runs synchronously on hip_stream and overwrites out. */
 int ktf_autotune_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, void *hip_stream);
-/* Describe the chosen launch shape for (prec, n) as text into buf. */
+/* Describe the chosen launch shape for (prec, n) as JSON into buf (block,
+ * waves_per_simd, persistent, blocks_per_cu, ms, tuned, and "trials": one
+ * [block, waves_per_simd, persistent, ms] per shape tried).  The text is cut
+ * at len - 1 characters; 4096 bytes hold every shape. */
 int ktf_tuned_shape(ktf_ctx *ctx, ktf_precision prec, int64_t n, char *buf, size_t len);
 
 /* --------------------------------------------------------------- building

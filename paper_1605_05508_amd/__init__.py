@@ -9,6 +9,7 @@ library is missing, or no GPU is present, calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 from typing import Optional, Sequence
 
@@ -240,11 +241,17 @@ class Context:
                                                _stream_handle(stream)), "ktf_autotune_fit")
         return out
 
-    def tuned_shape(self, prec, n):
-        buf = C.create_string_buffer(256)
-        self._check(self._lib.ktf_tuned_shape(self._h, PRECS.get(prec, prec), n, buf, 256),
+    def tuned_shape(self, prec, n, trials=False):
+        """The tuned launch shape for (prec, n) as a JSON string; with
+        trials=True it keeps the time of every shape the tuner tried."""
+        size = 8192
+        buf = C.create_string_buffer(size)
+        self._check(self._lib.ktf_tuned_shape(self._h, PRECS.get(prec, prec), n, buf, size),
                     "ktf_tuned_shape")
-        return buf.value.decode()
+        d = json.loads(buf.value.decode())
+        if not trials:
+            d.pop("trials", None)
+        return json.dumps(d)
 
     def _validate_fit(self, state, cov, q, hits, valid):
         torch = _torch()

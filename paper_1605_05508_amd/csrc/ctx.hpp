@@ -42,12 +42,20 @@ struct DevBuf {
   }
 };
 
+struct LaunchTrial {
+  int block;
+  int waves;
+  bool persistent;
+  float ms;
+};
+
 struct TunedShape {
   int block = 256;
   int waves = 1;  // waves per SIMD the registers must allow (1: compiler's choice)
   bool persistent = false;
   int persistent_blocks = 0;
   float ms = 0.f;
+  std::vector<LaunchTrial> trials;  // every shape timed, in trial order
 };
 
 struct SweepGraph {

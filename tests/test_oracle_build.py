@@ -179,3 +179,40 @@ def test_debug_records_are_consistent(orc):
         for l in range(3, L):
             for r in range(o["dbg_n"][l, s]):
                 assert 0 <= ranks[l, r] < o["dbg_n"][l - 1, s]
+
+
+def test_seed_order_does_not_change_results(orc):
+    """Seeds are built independently given their event's hits (Sec. 3): the
+    oracle on a permuted seed order (the eta-bin order, and a random order
+    within each event) gives each seed exactly the same result."""
+    det = tg.barrel(9)
+    rng = np.random.default_rng(12)
+    bs = tg.concat_events([tg.make_build_event(rng, 120, det) for _ in range(2)])
+    eta_perm = tg.eta_order(bs)
+    rnd_perm = np.concatenate([a + rng.permutation(b - a) for a, b in zip(bs.seed_off[:-1], bs.seed_off[1:])])
+    base = [orc.build_event(bs, e) for e in range(bs.n_events)]
+    for perm in (eta_perm, rnd_perm):
+        assert not np.array_equal(perm, np.arange(bs.n_seeds))
+        pb = tg.permute_seeds(bs, perm)
+        for e in range(bs.n_events):
+            a, b = bs.seed_off[e], bs.seed_off[e + 1]
+            o = orc.build_event(pb, e)
+            inv = np.argsort(perm[a:b] - a)
+            for key in ("hit_idx", "nhits", "chi2", "state", "cov", "status"):
+                assert np.array_equal(o[key][..., inv], base[e][key]), key
+
+
+def test_eta_order_groups_seeds_by_eta_bin():
+    det = tg.barrel(6)
+    rng = np.random.default_rng(13)
+    bs = tg.concat_events([tg.make_build_event(rng, n, det) for n in (300, 0, 200)])
+    perm = tg.eta_order(bs, n_bins=21)
+    eta = np.arcsinh(bs.state[5] / np.hypot(bs.state[3], bs.state[4]))
+    bins = np.clip(np.floor((eta + 1.0) * 21 / 2.0), 0, 20)
+    for a, b in zip(bs.seed_off[:-1], bs.seed_off[1:]):
+        p = perm[a:b]
+        assert np.array_equal(np.sort(p), np.arange(a, b))      # a permutation within the event
+        assert np.all(np.diff(bins[p]) >= 0)                      # bins in order
+        for v in np.unique(bins[p]):                              # stable within a bin
+            q = p[bins[p] == v]
+            assert np.all(np.diff(q) > 0)

@@ -575,6 +575,34 @@ def concat_events(events) -> BuildSet:
                     cat("truth_pos"), cat("truth_mom"))
 
 
+def permute_seeds(bs: BuildSet, perm) -> BuildSet:
+    """The same events with the seeds in the order perm (a permutation that
+    keeps every event's seeds within the event's range)."""
+    perm = np.asarray(perm)
+    for e in range(bs.n_events):
+        a, b = bs.seed_off[e], bs.seed_off[e + 1]
+        assert np.array_equal(np.sort(perm[a:b]), np.arange(a, b)), "perm must stay within events"
+    return BuildSet(bs.det, bs.n_events, bs.hit_off, bs.hits, bs.seed_off, bs.state[:, perm],
+                    bs.cov[:, perm], bs.q[perm], bs.seed_hit[:, perm], bs.true_idx[:, perm],
+                    bs.truth_pos[:, :, perm], bs.truth_mom[:, :, perm])
+
+
+def eta_order(bs: BuildSet, n_bins=21, eta_max=1.0) -> np.ndarray:
+    """A seed order that groups each event's seeds by pseudorapidity bin of
+    their momentum (n_bins equal bins over |eta| < eta_max, the outermost
+    bins open-ended; stable within a bin), events kept in place: the eta
+    partition that the paper's building threads over (Sec. 3), here an
+    order in which neighbouring seeds search neighbouring hit bins."""
+    px, py, pz = bs.state[3], bs.state[4], bs.state[5]
+    eta = np.arcsinh(pz / np.hypot(px, py))
+    b = np.clip(np.floor((eta + eta_max) * n_bins / (2.0 * eta_max)), 0, n_bins - 1).astype(np.int64)
+    parts = []
+    for e in range(bs.n_events):
+        a, c = bs.seed_off[e], bs.seed_off[e + 1]
+        parts.append(a + np.argsort(b[a:c], kind="stable"))
+    return np.concatenate(parts).astype(np.int64) if parts else np.zeros(0, np.int64)
+
+
 def make_build_event(rng, n_tracks, det: Detector, *, noise_frac=0.2, seed_mode="smeared",
                      pt_range=(0.5, 10.0), pt_log=False):
     """One building event: n_tracks truth tracks plus uniform noise per layer.
