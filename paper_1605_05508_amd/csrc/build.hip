@@ -235,94 +235,20 @@ __global__ void bin_rank_kernel(BuildArgs a) {
   o[2 * a.n_hits + dst] = h[2 * a.hp + j];
 }
 
-// One block per (event, layer) with the whole bin histogram in LDS: count
-// the hits per bin with LDS atomics, scan the counts into the CSR offsets,
-// scatter the hits through an LDS cursor, then order every bin by original
-// index (a hit's place is the number of its bin's hits with a smaller index)
-// and copy the coordinates into binned order.  Used when the bin table fits
-// in LDS; the multi-kernel path above covers larger tables.
 constexpr int kBinThreads = 1024;
 constexpr int kLdsBins = 32768;
-template <typename TS>
-__global__ __launch_bounds__(kBinThreads) void bin_group_kernel(BuildArgs a) {
-  __shared__ int32_t hist[kLdsBins];
-  __shared__ int32_t wsum[kBinThreads / 64];
-  const int g = blockIdx.x;
-  const int nb = a.n_bins;
-  const int tid = threadIdx.x;
-  const int64_t base = a.hit_off[g];
-  const int32_t n = (int32_t)(a.hit_off[g + 1] - base);
-  int32_t* off = a.bin_off + (int64_t)g * (nb + 1);
-  const TS* h = static_cast<const TS*>(a.hits);
-  for (int b = tid; b < nb; b += kBinThreads) hist[b] = 0;
-  __syncthreads();
-  for (int32_t j = tid; j < n; j += kBinThreads) {
-    const int64_t gj = base + j;
-    const int b = hit_bin_of((double)h[gj], (double)h[a.hp + gj], (double)h[2 * a.hp + gj], a.g.z_half,
-                             a.g.n_zbins, a.g.n_phibins);
-    a.hit_bin[gj] = b;
-    atomicAdd(&hist[b], 1);
-  }
-  __syncthreads();
-  // exclusive scan of the counts (coalesced chunks, wave shuffles)
-  const int lane = tid & 63, wave = tid >> 6;
-  constexpr int nw = kBinThreads / 64;
-  int32_t carry = 0;
-  for (int b0 = 0; b0 < nb; b0 += kBinThreads) {
-    const int b = b0 + tid;
-    const int32_t v = b < nb ? hist[b] : 0;
-    int32_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int32_t y = __shfl_up(x, d, 64);
-      if (lane >= d) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    if (wave == 0) {
-      int32_t t = lane < nw ? wsum[lane] : 0;
-#pragma unroll
-      for (int d = 1; d < nw; d <<= 1) {
-        const int32_t y = __shfl_up(t, d, 64);
-        if (lane >= d) t += y;
-      }
-      if (lane < nw) wsum[lane] = t;
-    }
-    __syncthreads();
-    const int32_t excl = carry + (wave > 0 ? wsum[wave - 1] : 0) + x - v;
-    if (b < nb) {
-      off[b] = excl;
-      hist[b] = excl;
-    }
-    carry += wsum[nw - 1];
-    __syncthreads();
-  }
-  if (tid == 0) off[nb] = carry;
-  for (int32_t j = tid; j < n; j += kBinThreads) {
-    const int b = a.hit_bin[base + j];
-    const int32_t pos = atomicAdd(&hist[b], 1);
-    a.perm_raw[base + pos] = j;
-  }
-  __syncthreads();
-  TS* o = static_cast<TS*>(a.hb);
-  for (int32_t j = tid; j < n; j += kBinThreads) {
-    const int64_t gj = base + j;
-    const int b = a.hit_bin[gj];
-    const int32_t lo = off[b], hi = off[b + 1];
-    int32_t rank = 0;
-    for (int32_t k = lo; k < hi; ++k) rank += a.perm_raw[base + k] < j ? 1 : 0;
-    const int64_t dst = base + lo + rank;
-    a.perm[dst] = j;
-    o[dst] = h[gj];
-    o[a.n_hits + dst] = h[a.hp + gj];
-    o[2 * a.n_hits + dst] = h[2 * a.hp + gj];
-  }
-}
 
-// Packed variant for groups of at most kPackMaxHits hits (the usual case):
-// counts, offsets and cursors are 16-bit halves of 32-bit LDS words (64 KB
-// for 32,768 bins) and the unordered scatter stays in LDS as 16-bit local
-// indices, so ordering each bin by original index reads LDS only.  Each
+// One block per (event, layer) group of at most kPackMaxHits hits (the
+// usual case) with the whole bin table in LDS: count the hits per bin,
+// scan the counts into the CSR offsets, scatter the hits through a cursor,
+// then order every bin by original index (a hit's place is the number of
+// its bin's hits with a smaller index) and copy the coordinates into binned
+// order.  Counts, offsets and cursors are 16-bit halves of 32-bit LDS words
+// (64 KB for 32,768 bins) and the unordered scatter stays in LDS as 16-bit
+// local indices, so ordering each bin by original index reads LDS only.
+// Larger groups or bin tables take the multi-kernel path above, whose
+// kernels spread every phase over all hits (one block per group would
+// leave a batch of few heavy events with few blocks).  Each
 // thread takes its hits kBinBatch at a time with their loads issued
 // together, so a phase costs one memory round trip per batch.
 constexpr int kPackMaxHits = 32768;
@@ -817,9 +743,31 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   const int64_t base = a.hit_off[g];
   const TS* hb = static_cast<const TS*>(a.hb);
   const HitRes hr = hit_res(a);
+  // the candidate's sorted record list lives in LDS while the window is
+  // scanned (rows [k][blockDim] of the dynamic shared memory: chi2 totals,
+  // then hit indices) and goes to its record rows once complete
+  extern __shared__ double rec_lds[];
+  const int t = threadIdx.x, B = blockDim.x;
+  double* lc = rec_lds;
+  int32_t* lh = reinterpret_cast<int32_t*>(rec_lds + NC * B);
   int nrec = 0;
-  double* rchi = a.rchi;
-  int32_t* rhit = a.rhit;
+  auto insert = [&](double c2, int32_t hid) {
+    if (nrec == NC && !rec_less(c2, hid, lc[(NC - 1) * B + t], lh[(NC - 1) * B + t])) return;
+    int pos = nrec < NC ? nrec : NC - 1;
+    while (pos > 0 && rec_less(c2, hid, lc[(pos - 1) * B + t], lh[(pos - 1) * B + t])) {
+      lc[pos * B + t] = lc[(pos - 1) * B + t];
+      lh[pos * B + t] = lh[(pos - 1) * B + t];
+      --pos;
+    }
+    lc[pos * B + t] = c2;
+    lh[pos * B + t] = hid;
+    if (nrec < NC) ++nrec;
+  };
+  auto score_hit = [&](double m0, double m1, double m2, int32_t hid) {
+    const double m[3] = {m0, m1, m2};
+    Residual R;
+    if (residual(xp, Pp, m, hr, R) && R.chi2 < cut) insert(pchi2 + R.chi2, hid);
+  };
   for (int zb = zlo; zb <= zhi; ++zb) {
     // up to two contiguous runs of phi bins (wrap-around)
     int runs[2][2];
@@ -839,39 +787,39 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     for (int ri = 0; ri < nrun; ++ri) {
       const int32_t j0 = off[zb * nphi + runs[ri][0]];
       const int32_t j1 = off[zb * nphi + runs[ri][1] + 1];
-      for (int32_t j = j0; j < j1; ++j) {
-        const int64_t hj = base + j;
-        const double m[3] = {(double)hb[hj], (double)hb[a.n_hits + hj], (double)hb[2 * a.n_hits + hj]};
-        Residual R;
-        if (!residual(xp, Pp, m, hr, R)) continue;
-        if (!(R.chi2 < cut)) continue;
-        const double c2 = pchi2 + R.chi2;
-        const int32_t hid = a.perm[hj];
-        // insert into the sorted list of at most NC records
-        if (nrec == NC && !rec_less(c2, hid, rchi[(int64_t)(NC - 1) * S + c], rhit[(int64_t)(NC - 1) * S + c]))
-          continue;
-        int pos = nrec < NC ? nrec : NC - 1;
-        while (pos > 0 && rec_less(c2, hid, rchi[(int64_t)(pos - 1) * S + c], rhit[(int64_t)(pos - 1) * S + c])) {
-          rchi[(int64_t)pos * S + c] = rchi[(int64_t)(pos - 1) * S + c];
-          rhit[(int64_t)pos * S + c] = rhit[(int64_t)(pos - 1) * S + c];
-          --pos;
+      if constexpr (sizeof(TS) == 4) {
+        // two hits per step, their loads issued together (in double the
+        // second hit's registers would spill)
+        for (int32_t j = j0; j < j1; j += 2) {
+          const int64_t h0 = base + j, h1 = base + (j + 1 < j1 ? j + 1 : j);
+          const TS x0 = hb[h0], y0 = hb[a.n_hits + h0], z0 = hb[2 * a.n_hits + h0];
+          const TS x1 = hb[h1], y1 = hb[a.n_hits + h1], z1 = hb[2 * a.n_hits + h1];
+          const int32_t id0 = a.perm[h0], id1 = a.perm[h1];
+          score_hit((double)x0, (double)y0, (double)z0, id0);
+          if (j + 1 < j1) score_hit((double)x1, (double)y1, (double)z1, id1);
         }
-        rchi[(int64_t)pos * S + c] = c2;
-        rhit[(int64_t)pos * S + c] = hid;
-        if (nrec < NC) ++nrec;
+      } else {
+        for (int32_t j = j0; j < j1; ++j) {
+          const int64_t h = base + j;
+          score_hit((double)hb[h], (double)hb[a.n_hits + h], (double)hb[2 * a.n_hits + h], a.perm[h]);
+        }
       }
     }
   }
   if (nrec == 0) {
     if (meta_nm(meta) < a.g.max_missed) {
-      rchi[c] = pchi2;
-      rhit[c] = -1;
+      lc[t] = pchi2;
+      lh[t] = -1;
       nrec = 1;
     } else {
       a.rcount[c] = -2;
       store_ended();
       return;
     }
+  }
+  for (int k = 0; k < nrec; ++k) {
+    a.rchi[(int64_t)k * S + c] = lc[k * B + t];
+    a.rhit[(int64_t)k * S + c] = lh[k * B + t];
   }
   a.rcount[c] = nrec;
 }
@@ -1213,8 +1161,6 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   const int64_t nbins_all = (int64_t)a.n_groups * a.n_bins;
   if (nbins_all > 0 && a.n_bins <= kLdsBins && a.max_group <= kPackMaxHits) {
     hipLaunchKernelGGL((bin_group16_kernel<TS>), dim3(a.n_groups), dim3(kBinThreads), 0, st, a);
-  } else if (nbins_all > 0 && a.n_bins <= kLdsBins) {
-    hipLaunchKernelGGL((bin_group_kernel<TS>), dim3(a.n_groups), dim3(kBinThreads), 0, st, a);
   } else if (nbins_all > 0) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nbins_all, bs)), dim3(bs), 0, st, a.bin_cur, nbins_all, 0);
     if (a.n_hits > 0)
@@ -1236,17 +1182,20 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   else
     hipLaunchKernelGGL((build_seed_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   int cur = 0;
+  // the score kernel's record lists in LDS: max_cands chi2 totals and hit
+  // indices per thread
+  const size_t rec_lds = (size_t)a.g.max_cands * bs * (sizeof(double) + sizeof(int32_t));
   const dim3 rows((unsigned)(kRegions * ((a.RS / bs + kRowChunks - 1) / kRowChunks)));
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     const bool child = l > a.g.n_seed_layers;  // candidates kept on layer l - 1, not yet made
     if (a.g.mat.on && child)
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, true>), rows, dim3(bs), 0, st, a, l, cur);
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, true>), rows, dim3(bs), rec_lds, st, a, l, cur);
     else if (a.g.mat.on)
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, false>), rows, dim3(bs), 0, st, a, l, cur);
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, false>), rows, dim3(bs), rec_lds, st, a, l, cur);
     else if (child)
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, true>), rows, dim3(bs), 0, st, a, l, cur);
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, true>), rows, dim3(bs), rec_lds, st, a, l, cur);
     else
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, false>), rows, dim3(bs), 0, st, a, l, cur);
+      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, false>), rows, dim3(bs), rec_lds, st, a, l, cur);
     launch_merge<TS>(a, l, cur, st);
     cur ^= 1;
   }

@@ -47,9 +47,9 @@ def oracle_batch(orc, bs, **kw):
 
 @pytest.mark.parametrize("case", ["packed", "wide_group", "many_bins"])
 def test_bins_match_oracle(k, orc, case):
-    """The three binning paths: groups of at most 32,768 hits (16-bit LDS
-    tables), a group above that (32-bit LDS table), and a table of more than
-    32,768 bins (multi-kernel path)."""
+    """The binning paths: groups of at most 32,768 hits (one block per group,
+    16-bit LDS tables), and the multi-kernel path over all hits for a group
+    above that and for a table of more than 32,768 bins."""
     nz, nphi = 64, 512
     if case == "packed":
         bs = small_batch(1, 3, 400, n_layers=6)

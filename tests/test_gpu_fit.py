@@ -8,6 +8,8 @@ FP32 bulk (covariance in float) meets 1e-4 at the 99.9th percentile; its
 tail is the float covariance's, so FP32_PROP (float state propagation,
 double covariance) is held to 1e-4 on every track.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -220,6 +222,12 @@ def test_autotune_keeps_results(ctx10):
         ref = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="fused", prec=pp), fs.n)
         ctx10.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], prec=pp)
         assert '"tuned": true' in ctx10.tuned_shape(prec, fs.n)
+        shape = json.loads(ctx10.tuned_shape(prec, fs.n, trials=True))
+        trials = shape["trials"]   # [block, waves per SIMD, persistent, ms] per shape
+        assert len(trials) == 24 and len({tuple(t[:3]) for t in trials}) == 24
+        best = min(trials, key=lambda t: t[3])
+        assert [best[0], best[1], bool(best[2])] == [shape["block"], shape["waves_per_simd"], shape["persistent"]]
+        assert abs(best[3] - shape["ms"]) < 1e-3
         g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="auto", prec=pp), fs.n)
         for key in ref:
             assert np.array_equal(ref[key], g[key]), (prec, key, ctx10.tuned_shape(prec, fs.n))
