@@ -93,7 +93,7 @@ def parse():
                          "launch shape and its throughput from 1e3 to 1e7 tracks")
     ap.add_argument("--no-build", action="store_true", help="skip the building measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
-    ap.add_argument("--serve-events", type=int, default=200)
+    ap.add_argument("--serve-events", type=int, default=500)
     ap.add_argument("--rates", type=str, default="500,2000")
     return ap.parse_args()
 
@@ -102,7 +102,8 @@ def serving_measurement(ktf, tg, n_events, rates):
     """Poisson arrivals of building events (5,000 tracks, 10% heavy events of
     20,000-50,000 tracks, 17 layers, 20% noise) into the continuous-batching
     loop (build + final fit per event), against the plain FP64 path serving
-    one event at a time."""
+    one event at a time, both closed-loop (its service time) and under the
+    same arrivals (its queueing)."""
     import threading
     arrivals, ntr, rng = tg.config5_stream(n_events=n_events, rate=1.0)
     det = tg.barrel(17)
@@ -164,7 +165,10 @@ def serving_measurement(ktf, tg, n_events, rates):
     ctx.close()
     ctx1 = ktf.Context.for_detector(det, hbm_budget_bytes=16 << 30, max_inflight=1)
     run(ctx1, 1e9, "fp64", sequential=True)
+    # closed loop: each event submitted when the previous one is done (the
+    # service time alone); then the same Poisson arrivals, queueing
     out["fp64_one_at_a_time"] = run(ctx1, 1e9, "fp64", sequential=True)
+    out["fp64_one_at_a_time_poisson"] = {str(r): run(ctx1, r, "fp64") for r in rates}
     ctx1.close()
     return out
 

@@ -146,6 +146,33 @@ static hipError_t ensure_pinned(void** p, size_t* have, size_t want) {
   return e;
 }
 
+// Byte offsets of a batch's outputs in the lane's output buffer: the part
+// the host reads (hit indices and the final fit's results) comes first and
+// is the only part copied back; the building's own fit outputs follow.
+struct OutLayout {
+  size_t hit, f_state, f_cov, f_chi2, f_nu, f_st, host;
+  size_t b_state, b_cov, b_chi2, b_nh, b_st, total;
+};
+
+template <typename TS>
+static OutLayout out_layout(int L, int64_t Np) {
+  OutLayout o;
+  o.hit = 0;
+  o.f_state = align256(o.hit + sizeof(int32_t) * L * Np);
+  o.f_cov = align256(o.f_state + sizeof(TS) * 6 * Np);
+  o.f_chi2 = align256(o.f_cov + sizeof(TS) * 21 * Np);
+  o.f_nu = align256(o.f_chi2 + sizeof(double) * Np);
+  o.f_st = align256(o.f_nu + sizeof(int32_t) * Np);
+  o.host = align256(o.f_st + sizeof(uint32_t) * Np);
+  o.b_state = o.host;
+  o.b_cov = align256(o.b_state + sizeof(TS) * 6 * Np);
+  o.b_chi2 = align256(o.b_cov + sizeof(TS) * 21 * Np);
+  o.b_nh = align256(o.b_chi2 + sizeof(double) * Np);
+  o.b_st = align256(o.b_nh + sizeof(int32_t) * Np);
+  o.total = align256(o.b_st + sizeof(uint32_t) * Np);
+  return o;
+}
+
 template <typename TS>
 static int launch_batch_t(ktf_ctx* c, Lane& ln) {
   const ktf_config& cfg = c->cfg;
@@ -194,14 +221,11 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
     int64_t sb = 0, hb = 0;
     for (ServeEvent* ev : ln.batch) {
       const int64_t n = ev->n_seeds, nh = ev->n_hits;
-      for (int k = 0; k < 3; ++k)
-        for (int64_t j = 0; j < nh; ++j) hh[k * H + hb + j] = (TS)ev->hits[k * nh + j];
-      for (int k = 0; k < 6; ++k)
-        for (int64_t j = 0; j < n; ++j) st[k * N + sb + j] = (TS)ev->state[k * n + j];
-      for (int k = 0; k < 21; ++k)
-        for (int64_t j = 0; j < n; ++j) cv[k * N + sb + j] = (TS)ev->cov[k * n + j];
-      for (int k = 0; k < NSL; ++k)
-        for (int64_t j = 0; j < n; ++j) sh[k * N + sb + j] = ev->seed_hit[k * n + j];
+      // rows of the event into rows of the batch (plain copies in float)
+      for (int k = 0; k < 3; ++k) std::copy_n(ev->hits.data() + k * nh, nh, hh + k * H + hb);
+      for (int k = 0; k < 6; ++k) std::copy_n(ev->state.data() + k * n, n, st + k * N + sb);
+      for (int k = 0; k < 21; ++k) std::copy_n(ev->cov.data() + k * n, n, cv + k * N + sb);
+      for (int k = 0; k < NSL; ++k) std::copy_n(ev->seed_hit.data() + k * n, n, sh + k * N + sb);
       memcpy(qq + sb, ev->q.data(), n);
       sb += n;
       hb += nh;
@@ -211,19 +235,12 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
     return hip_fail(c, e, "serve H2D");
   char* D = static_cast<char*>(ln.in.p);
 
-  // outputs of building and fit
-  size_t b_hit = 0;
-  size_t b_state = align256(b_hit + sizeof(int32_t) * L * Np);
-  size_t b_cov = align256(b_state + sizeof(TS) * 6 * Np);
-  size_t b_chi2 = align256(b_cov + sizeof(TS) * 21 * Np);
-  size_t b_nh = align256(b_chi2 + sizeof(double) * Np);
-  size_t b_st = align256(b_nh + sizeof(int32_t) * Np);
-  size_t f_state = align256(b_st + sizeof(uint32_t) * Np);
-  size_t f_cov = align256(f_state + sizeof(TS) * 6 * Np);
-  size_t f_chi2 = align256(f_cov + sizeof(TS) * 21 * Np);
-  size_t f_nu = align256(f_chi2 + sizeof(double) * Np);
-  size_t f_st = align256(f_nu + sizeof(int32_t) * Np);
-  size_t out_bytes = align256(f_st + sizeof(uint32_t) * Np);
+  // outputs of building and fit: what goes back to the host first (hit
+  // indices, the fit's results), then the building's own fit outputs
+  const OutLayout ol = out_layout<TS>(L, Np);
+  const size_t b_hit = ol.hit, f_state = ol.f_state, f_cov = ol.f_cov, f_chi2 = ol.f_chi2, f_nu = ol.f_nu,
+               f_st = ol.f_st, b_state = ol.b_state, b_cov = ol.b_cov, b_chi2 = ol.b_chi2, b_nh = ol.b_nh,
+               b_st = ol.b_st, out_bytes = ol.total;
   if ((e = ln.out.ensure(out_bytes)) != hipSuccess) return hip_fail(c, e, "serve outputs");
   char* O = static_cast<char*>(ln.out.p);
   ktf_event_batch bt;
@@ -271,16 +288,12 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
                        reinterpret_cast<uint32_t*>(O + f_st), bo.status);
   }
   // results back: hit indices and the fit's outputs
-  if ((e = ensure_pinned(&ln.pin_out, &ln.pin_out_bytes, out_bytes)) != hipSuccess) return hip_fail(c, e, "serve staging");
-  if ((e = hipMemcpyAsync(ln.pin_out, O, out_bytes, hipMemcpyDeviceToHost, ln.stream)) != hipSuccess)
+  if ((e = ensure_pinned(&ln.pin_out, &ln.pin_out_bytes, ol.host)) != hipSuccess) return hip_fail(c, e, "serve staging");
+  if ((e = hipMemcpyAsync(ln.pin_out, O, ol.host, hipMemcpyDeviceToHost, ln.stream)) != hipSuccess)
     return hip_fail(c, e, "serve D2H");
   if ((e = hipEventRecord(ln.done, ln.stream)) != hipSuccess) return hip_fail(c, e, "serve event");
   // remember the layout for unpacking
   ln.busy = true;
-  (void)b_state;
-  (void)b_cov;
-  (void)b_chi2;
-  (void)b_nh;
   return KTF_OK;
 }
 
@@ -288,24 +301,14 @@ template <typename TS>
 static void unpack_batch_t(ktf_ctx* c, Lane& ln) {
   const int L = c->cfg.n_layers;
   const int64_t N = ln.N, Np = std::max<int64_t>(N, 1);
-  size_t b_hit = 0;
-  size_t b_state = align256(b_hit + sizeof(int32_t) * L * Np);
-  size_t b_cov = align256(b_state + sizeof(TS) * 6 * Np);
-  size_t b_chi2 = align256(b_cov + sizeof(TS) * 21 * Np);
-  size_t b_nh = align256(b_chi2 + sizeof(double) * Np);
-  size_t b_st = align256(b_nh + sizeof(int32_t) * Np);
-  size_t f_state = align256(b_st + sizeof(uint32_t) * Np);
-  size_t f_cov = align256(f_state + sizeof(TS) * 6 * Np);
-  size_t f_chi2 = align256(f_cov + sizeof(TS) * 21 * Np);
-  size_t f_nu = align256(f_chi2 + sizeof(double) * Np);
-  size_t f_st = align256(f_nu + sizeof(int32_t) * Np);
+  const OutLayout ol = out_layout<TS>(L, Np);
   const char* O = static_cast<const char*>(ln.pin_out);
-  const int32_t* hit = reinterpret_cast<const int32_t*>(O + b_hit);
-  const TS* st = reinterpret_cast<const TS*>(O + f_state);
-  const TS* cv = reinterpret_cast<const TS*>(O + f_cov);
-  const double* c2 = reinterpret_cast<const double*>(O + f_chi2);
-  const int32_t* nu = reinterpret_cast<const int32_t*>(O + f_nu);
-  const uint32_t* ss = reinterpret_cast<const uint32_t*>(O + f_st);
+  const int32_t* hit = reinterpret_cast<const int32_t*>(O + ol.hit);
+  const TS* st = reinterpret_cast<const TS*>(O + ol.f_state);
+  const TS* cv = reinterpret_cast<const TS*>(O + ol.f_cov);
+  const double* c2 = reinterpret_cast<const double*>(O + ol.f_chi2);
+  const int32_t* nu = reinterpret_cast<const int32_t*>(O + ol.f_nu);
+  const uint32_t* ss = reinterpret_cast<const uint32_t*>(O + ol.f_st);
   int64_t sb = 0;
   for (ServeEvent* ev : ln.batch) {
     const int64_t n = ev->n_seeds;
@@ -315,17 +318,12 @@ static void unpack_batch_t(ktf_ctx* c, Lane& ln) {
     ev->r_chi2.resize(n);
     ev->r_nh.resize(n);
     ev->r_st.resize(n);
-    for (int l = 0; l < L; ++l)
-      for (int64_t j = 0; j < n; ++j) ev->r_hit[l * n + j] = hit[l * N + sb + j];
-    for (int k = 0; k < 6; ++k)
-      for (int64_t j = 0; j < n; ++j) ev->r_state[k * n + j] = (float)st[k * N + sb + j];
-    for (int k = 0; k < 21; ++k)
-      for (int64_t j = 0; j < n; ++j) ev->r_cov[k * n + j] = (float)cv[k * N + sb + j];
-    for (int64_t j = 0; j < n; ++j) {
-      ev->r_chi2[j] = c2[sb + j];
-      ev->r_nh[j] = nu[sb + j];
-      ev->r_st[j] = ss[sb + j];
-    }
+    for (int l = 0; l < L; ++l) std::copy_n(hit + l * N + sb, n, ev->r_hit.data() + l * n);
+    for (int k = 0; k < 6; ++k) std::copy_n(st + k * N + sb, n, ev->r_state.data() + k * n);
+    for (int k = 0; k < 21; ++k) std::copy_n(cv + k * N + sb, n, ev->r_cov.data() + k * n);
+    std::copy_n(c2 + sb, n, ev->r_chi2.data());
+    std::copy_n(nu + sb, n, ev->r_nh.data());
+    std::copy_n(ss + sb, n, ev->r_st.data());
     sb += n;
   }
 }
