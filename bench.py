@@ -108,8 +108,10 @@ def serving_measurement(ktf, tg, n_events, rates):
     arrivals, ntr, rng = tg.config5_stream(n_events=n_events, rate=1.0)
     det = tg.barrel(17)
     evs = [tg.make_build_event(rng, int(n), det) for n in ntr]
-    host = [dict(hit_off=e.hit_off, hits=e.hits, state=e.state, cov=e.cov, q=e.q, seed_hit=e.seed_hit)
-            for e in evs]
+    # the client hands over float32 arrays, as the C-ABI takes them
+    f32 = lambda x: np.ascontiguousarray(x, np.float32)
+    host = [dict(hit_off=e.hit_off, hits=f32(e.hits), state=f32(e.state), cov=f32(e.cov), q=e.q,
+                 seed_hit=e.seed_hit) for e in evs]
 
     def run(ctx, rate, prec, sequential=False):
         lat, tracks = [], 0

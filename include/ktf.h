@@ -276,7 +276,9 @@ typedef struct {
   double *chi2;             /* host [n_seeds]: final fit chi2                    */
   int32_t *n_hits;          /* host [n_seeds]                                    */
   uint32_t *status;         /* host [n_seeds]                                    */
-  double t_submit, t_admit, t_done; /* seconds on the library's monotonic clock  */
+  double t_submit, t_admit, t_done; /* seconds on the library's monotonic clock:
+                                       entry of ktf_submit (the copy-in counts),
+                                       admission onto a lane, results on the host */
 } ktf_result_host;
 
 /* Copy the event into library staging and queue it; returns a ticket.  The

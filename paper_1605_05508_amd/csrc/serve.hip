@@ -462,6 +462,7 @@ extern "C" {
 double ktf_now(void) { return now_s(); }
 
 int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
+  const double t_entry = now_s();  // latency counts the copy-in below
   if (!c || !ev || !ticket) return KTF_EINVAL;
   const ktf_config& cfg = c->cfg;
   const int L = cfg.n_layers, NSL = cfg.n_seed_layers;
@@ -490,7 +491,7 @@ int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
   e->q.assign(ev->charge, ev->charge + n);
   e->seed_hit.assign(ev->seed_hit, ev->seed_hit + (size_t)NSL * n);
   e->footprint = fp;
-  e->t_submit = now_s();
+  e->t_submit = t_entry;
   ServeState* S = c->serve;
   {
     std::lock_guard<std::mutex> g(S->mu);
