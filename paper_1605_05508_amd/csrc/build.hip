@@ -71,10 +71,10 @@ struct BuildArgs {
   int32_t* perm;           // [n_hits]: local index of the hit at each binned position
   int32_t* perm_raw;       // [n_hits]: the same before ordering within bins
   int32_t* sev;            // [sp]: event of each seed
-  int32_t* cseed[2];       // [S]: seed of each dense candidate row
+  int32_t* cinfo[2];       // [S]: event << 1 | (charge > 0) of each dense candidate row
   int32_t* cstart[2];      // [sp]: first dense row of each seed's candidates
   int32_t* sel_parent;     // [S]: per child row, its parent's row
-  int32_t* sel_hit;        // [S]: per child row, the hit it takes (-1: missed layer)
+  int32_t* sel_hit;        // [S]: per child row, the hit it takes as an index into hits (-1: missed layer)
   double* sel_chi2;        // [S]: per child row, its chi2 total
   unsigned* ccount;        // [n_layers][kRegions][kCtrStride]: rows used per region after each layer
   void* hb;                // [3][n_hits]: binned coordinates
@@ -117,6 +117,12 @@ __device__ __forceinline__ int find_event(const int64_t* off, int n, int64_t j) 
   }
   return lo;
 }
+
+// a candidate row's event and charge, so that scoring reads neither the
+// seed's event nor its charge through the seed index
+__device__ __forceinline__ int32_t pack_info(int e, int8_t q) { return (e << 1) | (q > 0 ? 1 : 0); }
+__device__ __forceinline__ int info_event(int32_t i) { return i >> 1; }
+__device__ __forceinline__ double info_charge(int32_t i) { return (i & 1) ? 1.0 : -1.0; }
 
 __device__ __forceinline__ uint32_t pack_meta(int nh, int nm, uint32_t st) {
   return (uint32_t)nh | ((uint32_t)nm << 8) | (st << 16);
@@ -613,7 +619,7 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
     store_cand<TS, TP>(a.cpos[0], a.cmom[0], a.ccov[0], a.S, row, x, P);
     a.cchi2[0][row] = chi2;
     a.cmeta[0][row] = pack_meta(nh, 0, status);
-    a.cseed[0][row] = (int32_t)s;
+    a.cinfo[0][row] = pack_info(a.sev[s], a.q[s]);
   }
 }
 
@@ -627,7 +633,7 @@ __device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32
 // state on layer l with the Kalman update of the hit it took (a missed layer
 // keeps the propagated state); returns its meta word.
 template <typename TS, typename TP>
-__device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int from, int64_t c, int64_t s,
+__device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int from, int64_t c,
                                                TrackState<TP>& x, TP P[21]) {
   const int64_t p = a.sel_parent[c];
   const int32_t h = a.sel_hit[c];
@@ -637,9 +643,8 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
   load_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], a.S, p, xq, Pq);
   int cnh = meta_nh(pm), cnm = meta_nm(pm);
   if (h >= 0) {
-    const int64_t hi = a.hit_off[(int64_t)a.sev[s] * a.g.n_layers + l] + h;
     const TS* hits = static_cast<const TS*>(a.hits);
-    const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
+    const double m[3] = {(double)hits[h], (double)hits[a.hp + h], (double)hits[2 * a.hp + h]};
     Residual R;
     residual(xq, Pq, m, hit_res(a), R);  // scored positive definite already
     apply_update(xq, Pq, R, x, P);
@@ -663,16 +668,16 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
 // than the few registers the cap spills in double.)
 template <typename TS, typename TP, bool MAT, bool CHILD>
 __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, int64_t c) {
-  const int64_t s = a.cseed[cur][c];
+  const int32_t info = a.cinfo[cur][c];
   const int L = a.g.n_layers, NC = a.g.max_cands;
   const int64_t S = a.S;
-  const int e = a.sev[s];
+  const int e = info_event(info);
   TrackState<TP> x;
   TP P[21];
   uint32_t meta;
   double pchi2;
   if constexpr (CHILD) {
-    meta = make_child<TS, TP>(a, l - 1, cur ^ 1, c, s, x, P);
+    meta = make_child<TS, TP>(a, l - 1, cur ^ 1, c, x, P);
     pchi2 = a.sel_chi2[c];
     a.cmeta[cur][c] = meta;
     a.cchi2[cur][c] = pchi2;
@@ -686,11 +691,11 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     if constexpr (CHILD) {
       TrackState<TP> xc;
       TP Pc[21];
-      make_child<TS, TP>(a, l - 1, cur ^ 1, c, s, xc, Pc);
+      make_child<TS, TP>(a, l - 1, cur ^ 1, c, xc, Pc);
       store_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], S, c, xc, Pc);
     }
   };
-  const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
+  const TP k = (TP)(kCLight * info_charge(info) * a.g.bz);
   TrackState<TP> xp;
   Jac<TP> F;
   // the material of the layer being left
@@ -905,9 +910,14 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   const bool real = s < a.n_seeds;
   int nlive = 0;
   int64_t pbase = 0;
+  int32_t info = 0;
+  int64_t hbase = 0;  // the seed's event's first hit on layer l
   if (real) {  // cstart is only meaningful for a seed with candidates
     nlive = a.count[(int64_t)(l - 1) * sp + s];
     pbase = a.cstart[cur][s];
+    const int e = a.sev[s];
+    info = pack_info(e, a.q[s]);
+    hbase = a.hit_off[(int64_t)e * a.g.n_layers + l];
   }
   int rc[PPL], nh[PPL], hd[PPL], hh[PPL], pre_h[PPL][3];
   double pchi[PPL], hc[PPL], pre_c[PPL][3];
@@ -1031,10 +1041,11 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     const int pk = pick_s[ls][k];
     a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = pk >> 8;
     a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = phit_s[ls][k];
+    const int32_t h = phit_s[ls][k];
     a.sel_parent[first + k] = (int32_t)(pbase + (pk >> 8));
-    a.sel_hit[first + k] = phit_s[ls][k];
+    a.sel_hit[first + k] = h >= 0 ? (int32_t)(hbase + h) : -1;
     a.sel_chi2[first + k] = pchi_s[ls][k];
-    a.cseed[cur ^ 1][first + k] = (int32_t)s;
+    a.cinfo[cur ^ 1][first + k] = info;
   }
 }
 
@@ -1042,10 +1053,9 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
 // from their parents' propagated states and stored for the final choice.
 template <typename TS, typename TP>
 __device__ __forceinline__ void clone_row(const BuildArgs& a, int l, int to, int64_t c) {
-  const int64_t s = a.cseed[to][c];
   TrackState<TP> x;
   TP P[21];
-  const uint32_t meta = make_child<TS, TP>(a, l, to ^ 1, c, s, x, P);
+  const uint32_t meta = make_child<TS, TP>(a, l, to ^ 1, c, x, P);
   store_cand<TS, TP>(a.cpos[to], a.cmom[to], a.ccov[to], a.S, c, x, P);
   a.cchi2[to][c] = a.sel_chi2[c];
   a.cmeta[to][c] = meta;
@@ -1376,8 +1386,8 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     return hip_fail(c, e, "list workspace");
   {
     int32_t* p = static_cast<int32_t*>(c->b_list.p);
-    a.cseed[0] = p;
-    a.cseed[1] = p + S;
+    a.cinfo[0] = p;
+    a.cinfo[1] = p + S;
     a.sel_parent = p + 2 * S;
     a.sel_hit = p + 3 * S;
     a.cstart[0] = p + 4 * S;
