@@ -214,7 +214,8 @@ typedef struct {
   int64_t seed_pitch;       /* >= seed_off[n_events]                              */
   const void *seed_state;   /* device [6][seed_pitch]                            */
   const void *seed_cov;     /* device [21][seed_pitch]                           */
-  const int8_t *charge;     /* device [seed_pitch]                               */
+  const int8_t *charge;     /* device [seed_pitch]: > 0 positive, else negative
+                               (unit charge)                                     */
   const int32_t *seed_hit;  /* device [n_seed_layers][seed_pitch]: index of the
                                seed's hit on each seed layer, -1 = none         */
   ktf_precision prec;
@@ -264,7 +265,7 @@ typedef struct {
   const float *hits;        /* host [3][hit_off[n_layers]] (SoA)                 */
   const float *seed_state;  /* host [6][n_seeds]                                 */
   const float *seed_cov;    /* host [21][n_seeds]                                */
-  const int8_t *charge;     /* host [n_seeds]                                    */
+  const int8_t *charge;     /* host [n_seeds]: > 0 positive, else negative     */
   const int32_t *seed_hit;  /* host [n_seed_layers][n_seeds]                     */
   ktf_precision prec;       /* arithmetic of build and fit for this event        */
 } ktf_event_host;

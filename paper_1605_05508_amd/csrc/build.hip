@@ -88,7 +88,7 @@ struct BuildArgs {
   void* pmom[2];
   void* pcov[2];
   double* rchi;            // [max_cands][S]
-  int32_t* rhit;           // [max_cands][S]: original hit index
+  int32_t* rhit;           // [max_cands][S]: hit index within its (event, layer)
   int32_t* rcount;         // [S]: records, -1 ended (no reach), -2 ended (missed too often)
   int32_t* hist;           // [L][max_cands][2][sp]
   int32_t* count;          // [L][sp]
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
     for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * a.sp + s];
 #pragma unroll
     for (int c = 0; c < 21; ++c) P[c] = (TP)cv[c * a.sp + s];
-    const TP k = (TP)(kCLight * (double)a.q[s] * a.g.bz);
+    const TP k = (TP)(kCLight * (a.q[s] > 0 ? 1.0 : -1.0) * a.g.bz);
     const HitRes hr = hit_res(a);
     const TS* hits = static_cast<const TS*>(a.hits);
     for (int l = 0; l < NSL; ++l) {
