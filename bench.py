@@ -210,11 +210,13 @@ def build_measurement(ctx_cls, tg, torch, reps=5, orc=None, bs=None, precs=("fp3
     bs = tg.config3() if bs is None else bs
     ctx = ctx_cls.for_detector(bs.det)
     out = {"events": bs.n_events, "seeds": bs.n_seeds, "hits": int(bs.hits.shape[1])}
+    hits_by_prec = {}
     for prec in precs:
         d = build_inputs(bs, prec)
         o = ctx.build(d)
         ms = time_build(ctx, d, o, reps, torch)
         hit = o["hit_idx"].cpu().numpy()[:, :bs.n_seeds]
+        hits_by_prec[prec] = hit
         out[prec] = {"ms": round(ms, 3), "seeds_per_s": round(bs.n_seeds / (ms * 1e-3)),
                      "events_per_s": round(bs.n_events / (ms * 1e-3), 1),
                      **build_efficiency(hit, bs.true_idx)}
@@ -242,6 +244,11 @@ def build_measurement(ctx_cls, tg, torch, reps=5, orc=None, bs=None, precs=("fp3
                                       "eta_bins": 21, "same_hits_as_generation_order": bool(np.array_equal(hite, hit))}
             del de, oe
         del d, o
+    if "fp32b" in hits_by_prec and "fp64" in hits_by_prec:
+        # the FP64 build equals the oracle's bit for bit (tests); FP32 bulk
+        # may differ only where a decision was a near-tie
+        diff = (hits_by_prec["fp32b"] != hits_by_prec["fp64"]).any(axis=0)
+        out["fp32b_seeds_differing_from_fp64"] = int(diff.sum())
     if orc is not None:
         m = 100
         t0 = time.perf_counter()
