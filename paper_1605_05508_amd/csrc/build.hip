@@ -868,8 +868,22 @@ struct MHead {
   int hit;
 };
 
+// all terms evaluated (no short circuit), so that the choice compiles to
+// compares and selects rather than branches
 __device__ __forceinline__ bool mhead_better(const MHead& x, const MHead& y) {
-  return x.key > y.key || (x.key == y.key && (x.c < y.c || (x.c == y.c && (x.pj >> 8) < (y.pj >> 8))));
+  const bool gt = x.key > y.key, eq = x.key == y.key;
+  const bool cl = x.c < y.c, ce = x.c == y.c;
+  const bool pl = (x.pj >> 8) < (y.pj >> 8);
+  return gt | (eq & (cl | (ce & pl)));
+}
+
+// w = the better of w and h
+__device__ __forceinline__ void mhead_take(MHead& w, const MHead& h) {
+  const bool b = mhead_better(h, w);
+  w.key = b ? h.key : w.key;
+  w.c = b ? h.c : w.c;
+  w.pj = b ? h.pj : w.pj;
+  w.hit = b ? h.hit : w.hit;
 }
 
 template <int CTRL>
@@ -885,14 +899,14 @@ __device__ __forceinline__ void quad_best(MHead& h) {
     MHead o{dpp_i<0xB1>(h.key), __longlong_as_double(((int64_t)dpp_i<0xB1>((int)(cb >> 32)) << 32) |
                                                      (uint32_t)dpp_i<0xB1>((int)cb)),
             dpp_i<0xB1>(h.pj), dpp_i<0xB1>(h.hit)};  // lanes q ^ 1
-    if (mhead_better(o, h)) h = o;
+    mhead_take(h, o);
   }
   {
     const int64_t cb = __double_as_longlong(h.c);
     MHead o{dpp_i<0x4E>(h.key), __longlong_as_double(((int64_t)dpp_i<0x4E>((int)(cb >> 32)) << 32) |
                                                      (uint32_t)dpp_i<0x4E>((int)cb)),
             dpp_i<0x4E>(h.pj), dpp_i<0x4E>(h.hit)};  // lanes q ^ 2
-    if (mhead_better(o, h)) h = o;
+    mhead_take(h, o);
   }
 }
 
@@ -963,7 +977,10 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   for (int u = 0; u < PPL; ++u) {
     const int j = q + 4 * u;
     const MHead h{(j < nlive && rc[u] <= 0) ? nh[u] + 1 : 0, pchi[u], j << 8, 0};
-    if (u == 0 || mhead_better(h, eb)) eb = h;
+    if (u == 0)
+      eb = h;
+    else
+      mhead_take(eb, h);
   }
   quad_best(eb);
   if (eb.key > 0) {
@@ -993,15 +1010,18 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       }
     }
   }
-  // k-way merge of the parents' lists
+  // k-way merge of the parents' lists.  A list's records all give the same
+  // hit count (a missed-layer record is a list of its own), so a head's
+  // key stays fixed until its list runs out.
+  int hk[PPL];
+#pragma unroll
+  for (int u = 0; u < PPL; ++u) hk[u] = rc[u] > 0 ? nh[u] + (hh[u] >= 0 ? 1 : 0) + 1 : 0;
   int nsel = 0;
   for (int k = 0; k < NC; ++k) {
-    MHead w{0, 0.0, 0, 0};
+    MHead w{hk[0], hc[0], (q << 8) | hd[0], hh[0]};
 #pragma unroll
-    for (int u = 0; u < PPL; ++u) {
-      const MHead h{hd[u] < rc[u] ? nh[u] + (hh[u] >= 0 ? 1 : 0) + 1 : 0, hc[u], ((q + 4 * u) << 8) | hd[u],
-                    hh[u]};
-      if (u == 0 || mhead_better(h, w)) w = h;
+    for (int u = 1; u < PPL; ++u) {
+      mhead_take(w, MHead{hk[u], hc[u], ((q + 4 * u) << 8) | hd[u], hh[u]});
     }
     quad_best(w);
     if (w.key == 0) break;  // quad-uniform
@@ -1010,21 +1030,34 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       phit_s[ls][k] = w.hit;
       pchi_s[ls][k] = w.c;
     }
+    // the owner lane advances that parent's head (selects, not branches;
+    // records beyond the prefetched ones are loaded, rarely)
     const int wj = w.pj >> 8;
-    if ((wj & 3) == q) {  // the owner lane advances that parent's head
+    int64_t far = -1;  // row of a record beyond the prefetched ones, to load
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+      const bool adv = wj == q + 4 * u;
+      const int nx = hd[u] + 1;
+      const bool more = nx < rc[u];
+      if (adv && more && nx >= 4) far = (int64_t)nx * S + pbase + wj;
+      // the prefetched records move up one place
+      hd[u] = adv ? nx : hd[u];
+      hc[u] = adv ? pre_c[u][0] : hc[u];
+      hh[u] = adv ? pre_h[u][0] : hh[u];
+      pre_c[u][0] = adv ? pre_c[u][1] : pre_c[u][0];
+      pre_h[u][0] = adv ? pre_h[u][1] : pre_h[u][0];
+      pre_c[u][1] = adv ? pre_c[u][2] : pre_c[u][1];
+      pre_h[u][1] = adv ? pre_h[u][2] : pre_h[u][1];
+      hk[u] = adv && !more ? 0 : hk[u];
+    }
+    if (far >= 0) {
+      const double fc = a.rchi[far];
+      const int fh = a.rhit[far];
 #pragma unroll
       for (int u = 0; u < PPL; ++u) {
-        if ((wj >> 2) == u) {
-          const int nx = ++hd[u];
-          if (nx < rc[u]) {
-            if (nx < 4) {
-              hc[u] = nx == 1 ? pre_c[u][0] : nx == 2 ? pre_c[u][1] : pre_c[u][2];
-              hh[u] = nx == 1 ? pre_h[u][0] : nx == 2 ? pre_h[u][1] : pre_h[u][2];
-            } else {
-              hc[u] = a.rchi[(int64_t)nx * S + pbase + wj];
-              hh[u] = a.rhit[(int64_t)nx * S + pbase + wj];
-            }
-          }
+        if (wj == q + 4 * u) {
+          hc[u] = fc;
+          hh[u] = fh;
         }
       }
     }
