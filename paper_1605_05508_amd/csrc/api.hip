@@ -309,10 +309,10 @@ int ktf_tuned_shape(ktf_ctx* c, ktf_precision prec, int64_t n, char* buf, size_t
                     std::to_string(t.waves) + ", \"persistent\": " + (t.persistent ? "true" : "false") +
                     ", \"blocks_per_cu\": " + std::to_string(t.persistent_blocks);
     char num[32];
-    snprintf(num, sizeof num, "%.4f", t.ms);
+    snprintf(num, sizeof num, "%.6f", t.ms);
     s += std::string(", \"ms\": ") + num + ", \"tuned\": true, \"trials\": [";
     for (size_t i = 0; i < t.trials.size(); ++i) {
-      snprintf(num, sizeof num, "%.4f", t.trials[i].ms);
+      snprintf(num, sizeof num, "%.6f", t.trials[i].ms);
       s += std::string(i ? ", " : "") + "[" + std::to_string(t.trials[i].block) + ", " +
            std::to_string(t.trials[i].waves) + ", " + (t.trials[i].persistent ? "1" : "0") + ", " + num + "]";
     }

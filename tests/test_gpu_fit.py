@@ -225,9 +225,10 @@ def test_autotune_keeps_results(ctx10):
         shape = json.loads(ctx10.tuned_shape(prec, fs.n, trials=True))
         trials = shape["trials"]   # [block, waves per SIMD, persistent, ms] per shape
         assert len(trials) == 24 and len({tuple(t[:3]) for t in trials}) == 24
-        best = min(trials, key=lambda t: t[3])
-        assert [best[0], best[1], bool(best[2])] == [shape["block"], shape["waves_per_simd"], shape["persistent"]]
-        assert abs(best[3] - shape["ms"]) < 1e-3
+        chosen = [t for t in trials if [t[0], t[1], bool(t[2])] ==
+                  [shape["block"], shape["waves_per_simd"], shape["persistent"]]]
+        assert len(chosen) == 1 and chosen[0][3] <= min(t[3] for t in trials) + 1e-6   # the fastest
+        assert abs(chosen[0][3] - shape["ms"]) < 1e-6
         g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="auto", prec=pp), fs.n)
         for key in ref:
             assert np.array_equal(ref[key], g[key]), (prec, key, ctx10.tuned_shape(prec, fs.n))
