@@ -657,6 +657,7 @@ def main():
             acc[name] = {"e_pos_max": float(e_pos.max()), "e_mom_max": float(e_mom.max()),
                          "e_mom_p999": float(np.quantile(e_mom, 0.999)),
                          "e_rel_max": float(param_rel_errors(gs, o).max()),
+                         "tracks_e_mom_above_1e-4": int(np.sum(e_mom > 1e-4)),
                          "e_mom_max_by_pt": {f"{lo:g}-{hi:g}": float(e_mom[(ptv >= lo) & (ptv < hi)].max(initial=0.0))
                                              for lo, hi in ((0.5, 2), (2, 10), (10, 30), (30, 100))},
                          "pull_rms_ratio": {kk: round(float(np.sqrt(np.mean(pg[kk] ** 2)) /
