@@ -773,43 +773,48 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     Residual R;
     if (residual(xp, Pp, m, hr, R) && R.chi2 < cut) insert(pchi2 + R.chi2, hid);
   };
-  for (int zb = zlo; zb <= zhi; ++zb) {
-    // up to two contiguous runs of phi bins (wrap-around)
-    int runs[2][2];
-    int nrun;
-    if (full_phi) {
-      runs[0][0] = 0; runs[0][1] = nphi - 1; nrun = 1;
+  auto scan_range = [&](int32_t j0, int32_t j1) {
+    if constexpr (sizeof(TS) == 4) {
+      // two hits per step, their loads issued together (in double the
+      // second hit's registers would spill)
+      for (int32_t j = j0; j < j1; j += 2) {
+        const int64_t h0 = base + j, h1 = base + (j + 1 < j1 ? j + 1 : j);
+        const TS x0 = hb[h0], y0 = hb[a.n_hits + h0], z0 = hb[2 * a.n_hits + h0];
+        const TS x1 = hb[h1], y1 = hb[a.n_hits + h1], z1 = hb[2 * a.n_hits + h1];
+        const int32_t id0 = a.perm[h0], id1 = a.perm[h1];
+        score_hit((double)x0, (double)y0, (double)z0, id0);
+        if (j + 1 < j1) score_hit((double)x1, (double)y1, (double)z1, id1);
+      }
     } else {
-      const int a0 = ((plo % nphi) + nphi) % nphi;
-      const int a1 = a0 + (phi_hi - plo);
-      if (a1 < nphi) {
-        runs[0][0] = a0; runs[0][1] = a1; nrun = 1;
-      } else {
-        runs[0][0] = a0; runs[0][1] = nphi - 1;
-        runs[1][0] = 0; runs[1][1] = a1 - nphi; nrun = 2;
+      for (int32_t j = j0; j < j1; ++j) {
+        const int64_t h = base + j;
+        score_hit((double)hb[h], (double)hb[a.n_hits + h], (double)hb[2 * a.n_hits + h], a.perm[h]);
       }
     }
-    for (int ri = 0; ri < nrun; ++ri) {
-      const int32_t j0 = off[zb * nphi + runs[ri][0]];
-      const int32_t j1 = off[zb * nphi + runs[ri][1] + 1];
-      if constexpr (sizeof(TS) == 4) {
-        // two hits per step, their loads issued together (in double the
-        // second hit's registers would spill)
-        for (int32_t j = j0; j < j1; j += 2) {
-          const int64_t h0 = base + j, h1 = base + (j + 1 < j1 ? j + 1 : j);
-          const TS x0 = hb[h0], y0 = hb[a.n_hits + h0], z0 = hb[2 * a.n_hits + h0];
-          const TS x1 = hb[h1], y1 = hb[a.n_hits + h1], z1 = hb[2 * a.n_hits + h1];
-          const int32_t id0 = a.perm[h0], id1 = a.perm[h1];
-          score_hit((double)x0, (double)y0, (double)z0, id0);
-          if (j + 1 < j1) score_hit((double)x1, (double)y1, (double)z1, id1);
-        }
-      } else {
-        for (int32_t j = j0; j < j1; ++j) {
-          const int64_t h = base + j;
-          score_hit((double)hb[h], (double)hb[a.n_hits + h], (double)hb[2 * a.n_hits + h], a.perm[h]);
-        }
-      }
+  };
+  // up to two contiguous runs of phi bins (wrap-around), the same in every
+  // z row of the window
+  int lo0 = 0, hi0 = nphi - 1, lo1 = 0, hi1 = -1;
+  if (!full_phi) {
+    lo0 = ((plo % nphi) + nphi) % nphi;
+    const int a1 = lo0 + (phi_hi - plo);
+    if (a1 < nphi) {
+      hi0 = a1;
+    } else {
+      hi0 = nphi - 1;
+      hi1 = a1 - nphi;
     }
+  }
+  // the next row's first run is looked up while this row's hits are scored
+  int32_t nj0 = off[zlo * nphi + lo0], nj1 = off[zlo * nphi + hi0 + 1];
+  for (int zb = zlo; zb <= zhi; ++zb) {
+    const int32_t j0 = nj0, j1 = nj1;
+    if (zb < zhi) {
+      nj0 = off[(zb + 1) * nphi + lo0];
+      nj1 = off[(zb + 1) * nphi + hi0 + 1];
+    }
+    scan_range(j0, j1);
+    if (hi1 >= lo1) scan_range(off[zb * nphi + lo1], off[zb * nphi + hi1 + 1]);
   }
   if (nrec == 0) {
     if (meta_nm(meta) < a.g.max_missed) {
