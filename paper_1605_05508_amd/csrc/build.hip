@@ -14,8 +14,8 @@
 //           parent rank, lower hit index, a missed layer last);
 //   clone   applying each kept record's update to its parent's propagated
 //           state (the child) is folded into the next layer's score, which
-//           needs the child anyway; only the children of the last layer
-//           are cloned by a kernel of their own;
+//           needs the child anyway; of the last layer's children only the
+//           one the final choice takes is made;
 //   final   one lane per seed: the best survivor or ended candidate, hit
 //           indices recovered by walking the per-layer (parent, hit) records.
 //
@@ -498,7 +498,7 @@ __device__ __forceinline__ unsigned* region_ctr(const BuildArgs& a, int l, int r
   return a.ccount + ((int64_t)l * kRegions + r) * kCtrStride;
 }
 
-// The row kernels (score, clone) run one lane per live candidate row after
+// The row kernel (score) runs one lane per live candidate row after
 // layer l.  A launch has kRegions * k blocks: block b takes region
 // b % kRegions and, within it, the kRowChunks chunks b / kRegions + j k
 // (j = 0 .. kRowChunks - 1) of blockDim rows, each while it holds live
@@ -1087,25 +1087,12 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   }
 }
 
-// The children kept on the last layer (dense rows of buffer `to`), made
-// from their parents' propagated states and stored for the final choice.
-template <typename TS, typename TP>
-__device__ __forceinline__ void clone_row(const BuildArgs& a, int l, int to, int64_t c) {
-  TrackState<TP> x;
-  TP P[21];
-  const uint32_t meta = make_child<TS, TP>(a, l, to ^ 1, c, x, P);
-  store_cand<TS, TP>(a.cpos[to], a.cmom[to], a.ccov[to], a.S, c, x, P);
-  a.cchi2[to][c] = a.sel_chi2[c];
-  a.cmeta[to][c] = meta;
-}
-
-template <typename TS, typename TP>
-__global__ __launch_bounds__(256) void build_clone_kernel(BuildArgs a, int l, int to) {
-  ROW_CHUNKS(a, l, (clone_row<TS, TP>(a, l, to, c)));
-}
-
 // ------------------------------------------------------------------ final
-template <typename TS, typename TP>
+// One lane per seed.  LAZY: the survivors are the last layer's children,
+// not yet made; they are ranked from their records (the parent's hits plus
+// the one taken, the chi2 total) and only the chosen one is made.
+// Otherwise (no building layer) they are the stored seed fits.
+template <typename TS, typename TP, bool LAZY>
 __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n_seeds) return;
@@ -1117,8 +1104,15 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
   int bnh = 0;
   double bc2 = 0.0;
   for (int r = 0; r < nalive; ++r) {
-    const int nh = meta_nh(a.cmeta[cur][base + r]);
-    const double c2 = a.cchi2[cur][base + r];
+    int nh;
+    double c2;
+    if constexpr (LAZY) {
+      nh = meta_nh(a.cmeta[cur ^ 1][a.sel_parent[base + r]]) + (a.sel_hit[base + r] >= 0 ? 1 : 0);
+      c2 = a.sel_chi2[base + r];
+    } else {
+      nh = meta_nh(a.cmeta[cur][base + r]);
+      c2 = a.cchi2[cur][base + r];
+    }
     if (best_r < 0 || final_less(nh, c2, L, r, bnh, bc2, L, best_r)) {
       best_r = r;
       bnh = nh;
@@ -1142,6 +1136,9 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
     load_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
     meta = a.bmeta[s];
     c2 = a.bchi2[s];
+  } else if constexpr (LAZY) {
+    meta = make_child<TS, TP>(a, L - 1, cur ^ 1, base + rank, x, P);
+    c2 = a.sel_chi2[base + rank];
   } else {
     load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, base + rank, x, P);
     meta = a.cmeta[cur][base + rank];
@@ -1247,9 +1244,10 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
     launch_merge<TS>(a, l, cur, st);
     cur ^= 1;
   }
-  if (a.g.n_layers > a.g.n_seed_layers)  // the last layer's children, for the final choice
-    hipLaunchKernelGGL((build_clone_kernel<TS, TP>), rows, dim3(bs), 0, st, a, a.g.n_layers - 1, cur);
-  hipLaunchKernelGGL((build_final_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
+  if (a.g.n_layers > a.g.n_seed_layers)  // the last layer's children are made for the chosen one only
+    hipLaunchKernelGGL((build_final_kernel<TS, TP, true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
+  else
+    hipLaunchKernelGGL((build_final_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
   return hipGetLastError();
 }
 
