@@ -307,7 +307,6 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
     sum += (int32_t)((v & 0xffffu) + (v >> 16));
   }
   const int lane = tid & 63, wave = tid >> 6;
-  constexpr int nw = kBinThreads / 64;
   int32_t x = sum;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {

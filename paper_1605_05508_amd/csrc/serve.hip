@@ -279,7 +279,7 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
                        H, bo.hit_idx, reinterpret_cast<TS*>(FI + fin_h), reinterpret_cast<uint8_t*>(FI + fin_v));
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "serve gather");
     ktf_fit_in fi{N, N, bt.prec, D + o_state, D + o_cov, bt.charge, FI + fin_h,
-                  reinterpret_cast<const uint8_t*>(FI + fin_v)};
+                  reinterpret_cast<const uint8_t*>(FI + fin_v), 1};  // one pass
     ktf_fit_out fo{O + f_state, O + f_cov, reinterpret_cast<double*>(O + f_chi2),
                    reinterpret_cast<int32_t*>(O + f_nu), reinterpret_cast<uint32_t*>(O + f_st)};
     rc = ktf_fit(ln.sub, &fi, &fo, KTF_FIT_FUSED, ln.stream);
