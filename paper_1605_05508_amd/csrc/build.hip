@@ -586,8 +586,8 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
         const int64_t hi = a.hit_off[g] + h;
         const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
         Residual R;
-        if (residual(xp, Pp, m, hr, R)) {
-          apply_update(xp, Pp, R, x, P);
+        if (residual(x, P, m, hr, R)) {
+          apply_update(x, P, R, x, P);  // in place
           chi2 += R.chi2;
           ++nh;
           used = h;
@@ -637,21 +637,16 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
   const int64_t p = a.sel_parent[c];
   const int32_t h = a.sel_hit[c];
   const uint32_t pm = a.cmeta[from][p];
-  TrackState<TP> xq;
-  TP Pq[21];
-  load_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], a.S, p, xq, Pq);
+  load_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], a.S, p, x, P);
   int cnh = meta_nh(pm), cnm = meta_nm(pm);
   if (h >= 0) {
     const TS* hits = static_cast<const TS*>(a.hits);
     const double m[3] = {(double)hits[h], (double)hits[a.hp + h], (double)hits[2 * a.hp + h]};
     Residual R;
-    residual(xq, Pq, m, hit_res(a), R);  // scored positive definite already
-    apply_update(xq, Pq, R, x, P);
+    residual(x, P, m, hit_res(a), R);  // scored positive definite already
+    apply_update(x, P, R, x, P);       // in place
     ++cnh;
   } else {
-    x = xq;
-#pragma unroll
-    for (int i = 0; i < 21; ++i) P[i] = Pq[i];
     ++cnm;
   }
   return pack_meta(cnh, cnm, meta_st(pm));

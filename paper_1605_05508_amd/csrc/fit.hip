@@ -81,23 +81,21 @@ __device__ __forceinline__ void fit_pass(const FitArgs& a, int64_t i, uint32_t v
       cov_propagate(P, F, Pp);
     }
     at = l;
-    bool used = false;
+    // the update works in place on the propagated state, so that a layer
+    // without an update needs no per-lane selection of the result
     if ((vmask >> l) & 1u) {
       Residual R;
       if (residual(xp, Pp, m, hr, R)) {
-        apply_update(xp, Pp, R, x, P);
+        apply_update(xp, Pp, R, xp, Pp);
         chi2 += R.chi2;
         ++nupd;
-        used = true;
       } else {
         status |= kSNotPD;
       }
     }
-    if (!used) {
-      x = xp;
+    x = xp;
 #pragma unroll
-      for (int c = 0; c < 21; ++c) P[c] = Pp[c];
-    }
+    for (int c = 0; c < 21; ++c) P[c] = Pp[c];
     if (!finite_state(x, P)) {
       status |= kNonFinite;
       break;
@@ -274,25 +272,21 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void fi
   } else {
     TP Pp[21];
     cov_propagate(P, F, Pp);
-    bool used = false;
     if (a.valid == nullptr || a.valid[l * p + i]) {
       const TS* h = static_cast<const TS*>(a.hits) + (int64_t)l * 3 * p;
       const double m[3] = {(double)h[i], (double)h[p + i], (double)h[2 * p + i]};
       Residual R;
       if (residual(xp, Pp, m, hr, R)) {
-        apply_update(xp, Pp, R, x, P);
+        apply_update(xp, Pp, R, xp, Pp);  // in place
         chi2 += R.chi2;
         ++nupd;
-        used = true;
       } else {
         status |= kSNotPD;
       }
     }
-    if (!used) {
-      x = xp;
+    x = xp;
 #pragma unroll
-      for (int c = 0; c < 21; ++c) P[c] = Pp[c];
-    }
+    for (int c = 0; c < 21; ++c) P[c] = Pp[c];
     if (!finite_state(x, P)) status |= kNonFinite;
   }
   TS* so = static_cast<TS*>(a.state_o);

@@ -430,7 +430,9 @@ KTF_HD bool residual(const TrackState<T>& xp, const C Pp[21], const double m[3],
 }
 
 // State and covariance update given the residual; writes into x (state
-// type T) and P (covariance type C).
+// type T) and P (covariance type C), which may be xp and Pp themselves (the
+// gain is formed from Pp before any element of P is written, and each
+// element of P is written after its own element of Pp is read).
 // Joseph form expanded: P+ = P' - K B^T - B K^T + K S K^T
 //                          = P' - K D^T - D K^T  with D = B - (K S)/2,
 // which needs only K and D per row (S symmetric).
