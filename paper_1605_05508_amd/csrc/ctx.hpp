@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <cstdio>
@@ -18,20 +19,29 @@
 
 namespace ktf {
 
-// grow-only device buffer owned by the context
+// grow-only device buffer owned by the context.  A regrowth frees and
+// reallocates, which waits for the device, so it grows geometrically (to
+// at least twice its size): a workload that varies regrows a few times,
+// not at every new maximum.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   hipError_t ensure(size_t want) {
     if (want <= bytes) return hipSuccess;
+    const size_t b = std::max(want + want / 4, 2 * bytes);
     if (p) {
       hipError_t e = hipFree(p);
       p = nullptr;
       bytes = 0;
       if (e != hipSuccess) return e;
     }
-    size_t b = want + want / 4;
     hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess && b > want + want / 4) {  // the doubling does not fit: the request alone
+      (void)hipGetLastError();
+      e = hipMalloc(&p, want + want / 4);
+      if (e == hipSuccess) bytes = want + want / 4;
+      return e;
+    }
     if (e == hipSuccess) bytes = b;
     return e;
   }

@@ -135,13 +135,20 @@ __global__ void or_status(int64_t N, uint32_t* a, const uint32_t* b) {
 // ------------------------------------------------------------- batching
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// pinned staging of a lane, grown geometrically like the device buffers
+// (pinning host memory takes milliseconds)
 static hipError_t ensure_pinned(void** p, size_t* have, size_t want) {
   if (*have >= want) return hipSuccess;
+  size_t b = std::max(want + want / 4, 2 * *have);
   if (*p) (void)hipHostFree(*p);
   *p = nullptr;
   *have = 0;
-  const size_t b = want + want / 4;
   hipError_t e = hipHostMalloc(p, b, 0);
+  if (e != hipSuccess && b > want + want / 4) {  // the doubling does not fit: the request alone
+    (void)hipGetLastError();
+    b = want + want / 4;
+    e = hipHostMalloc(p, b, 0);
+  }
   if (e == hipSuccess) *have = b;
   return e;
 }
