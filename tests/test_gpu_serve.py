@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import trackgen as tg
-from helpers import fp64_close
+from helpers import build_inputs, fp64_close, host
 
 pytestmark = pytest.mark.gpu
 
@@ -115,4 +115,27 @@ def test_unknown_ticket(k):
     wait(ctx, t, evs[0].n_seeds)
     with pytest.raises(k.KtfError):
         ctx.poll(t, evs[0].n_seeds)  # already collected
+    ctx.close()
+
+
+def test_material_and_heavy_event_in_the_mix(k):
+    """Serving on a detector with layer material, a mix that holds an event
+    whose layers have more than 32,768 hits (the multi-kernel binning path)
+    beside small ones: every event's hits equal those of a direct build of
+    that event, and its result is the same alone and in the mix."""
+    rng = np.random.default_rng(6)
+    det = tg.barrel(17, x0=0.01, eloss=0.036)
+    evs = [tg.make_build_event(rng, n, det) for n in (300, 28000, 500)]
+    assert np.diff(evs[1].hit_off).max() > 32768
+    ctx = k.Context.for_detector(det)
+    direct = []
+    for ev in evs:
+        direct.append(host(ctx.build(build_inputs(ev, "fp64")), ev.n_seeds)["hit_idx"])
+    alone = [wait(ctx, ctx.submit(host_event(ev, "fp64")), ev.n_seeds) for ev in evs]
+    tickets = [ctx.submit(host_event(ev, "fp64")) for ev in evs]
+    mix = [wait(ctx, t, ev.n_seeds) for t, ev in zip(tickets, evs)]
+    for d, a, m in zip(direct, alone, mix):
+        assert np.array_equal(a["hit_idx"], d)
+        for key in ("hit_idx", "state", "cov", "chi2", "nhits", "status"):
+            assert np.array_equal(a[key], m[key]), key
     ctx.close()
