@@ -153,6 +153,59 @@ static hipError_t ensure_pinned(void** p, size_t* have, size_t want) {
   return e;
 }
 
+// Row copies between an event's host arrays and a batch's pinned staging.
+// A large batch's rows take a millisecond or more on one core, on the
+// path of every event in it, so above a few MB they are spread over a few
+// host threads.
+struct RowCopy {
+  const void* src;
+  void* dst;
+  int64_t n;
+  int kind;  // 0: float -> float, 1: float -> double, 2: double -> float, 3: 4-byte words, 4: bytes
+};
+
+static void run_copy(const RowCopy& t) {
+  switch (t.kind) {
+    case 0: std::copy_n(static_cast<const float*>(t.src), t.n, static_cast<float*>(t.dst)); break;
+    case 1: std::copy_n(static_cast<const float*>(t.src), t.n, static_cast<double*>(t.dst)); break;
+    case 2: std::copy_n(static_cast<const double*>(t.src), t.n, static_cast<float*>(t.dst)); break;
+    case 3: std::copy_n(static_cast<const int32_t*>(t.src), t.n, static_cast<int32_t*>(t.dst)); break;
+    default: memcpy(t.dst, t.src, (size_t)t.n); break;
+  }
+}
+
+// element sizes of a copy kind's source and destination
+static int src_size(int kind) { return kind == 2 ? 8 : kind == 4 ? 1 : 4; }
+static int dst_size(int kind) { return kind == 1 ? 8 : kind == 4 ? 1 : 4; }
+
+static void run_copies(const std::vector<RowCopy>& rows) {
+  size_t bytes = 0;
+  for (const RowCopy& t : rows) bytes += (size_t)t.n * src_size(t.kind);
+  const int nt = bytes > ((size_t)4 << 20) ? 4 : 1;
+  if (nt == 1) {
+    for (const RowCopy& t : rows) run_copy(t);
+    return;
+  }
+  // rows cut into pieces of at most 256K elements, dealt round robin
+  std::vector<RowCopy> tasks;
+  constexpr int64_t kPiece = 256 * 1024;
+  for (const RowCopy& t : rows)
+    for (int64_t o = 0; o < t.n; o += kPiece)
+      tasks.push_back({static_cast<const char*>(t.src) + o * src_size(t.kind),
+                       static_cast<char*>(t.dst) + o * dst_size(t.kind), std::min(kPiece, t.n - o), t.kind});
+  std::vector<std::thread> th;
+  for (int w = 1; w < nt; ++w)
+    th.emplace_back([&tasks, w, nt] {
+      for (size_t i = w; i < tasks.size(); i += nt) run_copy(tasks[i]);
+    });
+  for (size_t i = 0; i < tasks.size(); i += nt) run_copy(tasks[i]);
+  for (std::thread& x : th) x.join();
+}
+
+// the copy kind from float rows into TS rows, and back
+template <typename TS> constexpr int kind_in() { return sizeof(TS) == 8 ? 1 : 0; }
+template <typename TS> constexpr int kind_out() { return sizeof(TS) == 8 ? 2 : 0; }
+
 // Byte offsets of a batch's outputs in the lane's output buffer: the part
 // the host reads (hit indices and the final fit's results) comes first and
 // is the only part copied back; the building's own fit outputs follow.
@@ -226,17 +279,19 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
     int32_t* sh = reinterpret_cast<int32_t*>(P + o_sh);
     int8_t* qq = reinterpret_cast<int8_t*>(P + o_q);
     int64_t sb = 0, hb = 0;
+    std::vector<RowCopy> tasks;
     for (ServeEvent* ev : ln.batch) {
       const int64_t n = ev->n_seeds, nh = ev->n_hits;
-      // rows of the event into rows of the batch (plain copies in float)
-      for (int k = 0; k < 3; ++k) std::copy_n(ev->hits.data() + k * nh, nh, hh + k * H + hb);
-      for (int k = 0; k < 6; ++k) std::copy_n(ev->state.data() + k * n, n, st + k * N + sb);
-      for (int k = 0; k < 21; ++k) std::copy_n(ev->cov.data() + k * n, n, cv + k * N + sb);
-      for (int k = 0; k < NSL; ++k) std::copy_n(ev->seed_hit.data() + k * n, n, sh + k * N + sb);
-      memcpy(qq + sb, ev->q.data(), n);
+      // rows of the event into rows of the batch
+      for (int k = 0; k < 3; ++k) tasks.push_back({ev->hits.data() + k * nh, hh + k * H + hb, nh, kind_in<TS>()});
+      for (int k = 0; k < 6; ++k) tasks.push_back({ev->state.data() + k * n, st + k * N + sb, n, kind_in<TS>()});
+      for (int k = 0; k < 21; ++k) tasks.push_back({ev->cov.data() + k * n, cv + k * N + sb, n, kind_in<TS>()});
+      for (int k = 0; k < NSL; ++k) tasks.push_back({ev->seed_hit.data() + k * n, sh + k * N + sb, n, 3});
+      tasks.push_back({ev->q.data(), qq + sb, n, 4});
       sb += n;
       hb += nh;
     }
+    run_copies(tasks);
   }
   if ((e = hipMemcpyAsync(ln.in.p, P, in_bytes, hipMemcpyHostToDevice, ln.stream)) != hipSuccess)
     return hip_fail(c, e, "serve H2D");
@@ -317,6 +372,7 @@ static void unpack_batch_t(ktf_ctx* c, Lane& ln) {
   const int32_t* nu = reinterpret_cast<const int32_t*>(O + ol.f_nu);
   const uint32_t* ss = reinterpret_cast<const uint32_t*>(O + ol.f_st);
   int64_t sb = 0;
+  std::vector<RowCopy> tasks;
   for (ServeEvent* ev : ln.batch) {
     const int64_t n = ev->n_seeds;
     ev->r_hit.resize((size_t)L * n);
@@ -325,14 +381,15 @@ static void unpack_batch_t(ktf_ctx* c, Lane& ln) {
     ev->r_chi2.resize(n);
     ev->r_nh.resize(n);
     ev->r_st.resize(n);
-    for (int l = 0; l < L; ++l) std::copy_n(hit + l * N + sb, n, ev->r_hit.data() + l * n);
-    for (int k = 0; k < 6; ++k) std::copy_n(st + k * N + sb, n, ev->r_state.data() + k * n);
-    for (int k = 0; k < 21; ++k) std::copy_n(cv + k * N + sb, n, ev->r_cov.data() + k * n);
-    std::copy_n(c2 + sb, n, ev->r_chi2.data());
-    std::copy_n(nu + sb, n, ev->r_nh.data());
-    std::copy_n(ss + sb, n, ev->r_st.data());
+    for (int l = 0; l < L; ++l) tasks.push_back({hit + l * N + sb, ev->r_hit.data() + l * n, n, 3});
+    for (int k = 0; k < 6; ++k) tasks.push_back({st + k * N + sb, ev->r_state.data() + k * n, n, kind_out<TS>()});
+    for (int k = 0; k < 21; ++k) tasks.push_back({cv + k * N + sb, ev->r_cov.data() + k * n, n, kind_out<TS>()});
+    tasks.push_back({c2 + sb, ev->r_chi2.data(), 8 * n, 4});
+    tasks.push_back({nu + sb, ev->r_nh.data(), n, 3});
+    tasks.push_back({ss + sb, ev->r_st.data(), n, 3});
     sb += n;
   }
+  run_copies(tasks);
 }
 
 static void scheduler(ktf_ctx* c) {
@@ -492,11 +549,16 @@ int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
   e->n_hits = nh;
   e->prec = ev->prec;
   e->hit_off.assign(ev->hit_off, ev->hit_off + L + 1);
-  e->hits.assign(ev->hits, ev->hits + 3 * nh);
-  e->state.assign(ev->seed_state, ev->seed_state + 6 * n);
-  e->cov.assign(ev->seed_cov, ev->seed_cov + 21 * n);
-  e->q.assign(ev->charge, ev->charge + n);
-  e->seed_hit.assign(ev->seed_hit, ev->seed_hit + (size_t)NSL * n);
+  e->hits.resize(3 * nh);
+  e->state.resize(6 * n);
+  e->cov.resize(21 * n);
+  e->q.resize(n);
+  e->seed_hit.resize((size_t)NSL * n);
+  run_copies({{ev->hits, e->hits.data(), 3 * nh, 0},
+              {ev->seed_state, e->state.data(), 6 * n, 0},
+              {ev->seed_cov, e->cov.data(), 21 * n, 0},
+              {ev->charge, e->q.data(), n, 4},
+              {ev->seed_hit, e->seed_hit.data(), (int64_t)NSL * n, 3}});
   e->footprint = fp;
   e->t_submit = t_entry;
   ServeState* S = c->serve;
