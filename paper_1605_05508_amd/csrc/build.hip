@@ -762,12 +762,8 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     lh[pos * B + t] = hid;
     if (nrec < NC) ++nrec;
   };
-  auto score_hit = [&](double m0, double m1, double m2, int32_t hid) {
-    const double m[3] = {m0, m1, m2};
-    Residual R;
-    if (residual(xp, Pp, m, hr, R) && R.chi2 < cut) insert(pchi2 + R.chi2, hid);
-  };
-  auto scan_range = [&](int32_t j0, int32_t j1) {
+  // each hit's loads are issued before it is scored; score(m0, m1, m2, id)
+  auto scan_range = [&](int32_t j0, int32_t j1, auto&& score) {
     if constexpr (sizeof(TS) == 4) {
       // two hits per step, their loads issued together (in double the
       // second hit's registers would spill)
@@ -776,13 +772,13 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
         const TS x0 = hb[h0], y0 = hb[a.n_hits + h0], z0 = hb[2 * a.n_hits + h0];
         const TS x1 = hb[h1], y1 = hb[a.n_hits + h1], z1 = hb[2 * a.n_hits + h1];
         const int32_t id0 = a.perm[h0], id1 = a.perm[h1];
-        score_hit((double)x0, (double)y0, (double)z0, id0);
-        if (j + 1 < j1) score_hit((double)x1, (double)y1, (double)z1, id1);
+        score((double)x0, (double)y0, (double)z0, id0);
+        if (j + 1 < j1) score((double)x1, (double)y1, (double)z1, id1);
       }
     } else {
       for (int32_t j = j0; j < j1; ++j) {
         const int64_t h = base + j;
-        score_hit((double)hb[h], (double)hb[a.n_hits + h], (double)hb[2 * a.n_hits + h], a.perm[h]);
+        score((double)hb[h], (double)hb[a.n_hits + h], (double)hb[2 * a.n_hits + h], a.perm[h]);
       }
     }
   };
@@ -799,16 +795,43 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
       hi1 = a1 - nphi;
     }
   }
-  // the next row's first run is looked up while this row's hits are scored
-  int32_t nj0 = off[zlo * nphi + lo0], nj1 = off[zlo * nphi + hi0 + 1];
-  for (int zb = zlo; zb <= zhi; ++zb) {
-    const int32_t j0 = nj0, j1 = nj1;
-    if (zb < zhi) {
-      nj0 = off[(zb + 1) * nphi + lo0];
-      nj1 = off[(zb + 1) * nphi + hi0 + 1];
+  auto scan_window = [&](auto&& score) {
+    // the next row's first run is looked up while this row's hits are scored
+    int32_t nj0 = off[zlo * nphi + lo0], nj1 = off[zlo * nphi + hi0 + 1];
+    for (int zb = zlo; zb <= zhi; ++zb) {
+      const int32_t j0 = nj0, j1 = nj1;
+      if (zb < zhi) {
+        nj0 = off[(zb + 1) * nphi + lo0];
+        nj1 = off[(zb + 1) * nphi + hi0 + 1];
+      }
+      scan_range(j0, j1, score);
+      if (hi1 >= lo1) scan_range(off[zb * nphi + lo1], off[zb * nphi + hi1 + 1], score);
     }
-    scan_range(j0, j1);
-    if (hi1 >= lo1) scan_range(off[zb * nphi + lo1], off[zb * nphi + hi1 + 1]);
+  };
+  if (hr.sr2 == hr.srphi2) {
+    // equal radial and tangential resolutions: the hit covariance is
+    // diag(sr^2, sr^2, sz^2) wherever the hit lies in phi, so S and its
+    // inverse belong to the candidate and each hit costs only its residual
+    // and the quadratic form (the per-hit form below rounds V's transverse
+    // terms differently, by an ulp of sr^2)
+    const double Sc[6] = {(double)Pp[pidx(0, 0)] + hr.sr2, (double)Pp[pidx(0, 1)],
+                          (double)Pp[pidx(0, 2)], (double)Pp[pidx(1, 1)] + hr.sr2,
+                          (double)Pp[pidx(1, 2)], (double)Pp[pidx(2, 2)] + hr.sz2};
+    double Si[6];
+    const double p0 = xp.pos[0], p1 = xp.pos[1], p2 = xp.pos[2];
+    if (sym3_inverse(Sc, Si)) {
+      scan_window([&](double m0, double m1, double m2, int32_t hid) {
+        const double r[3] = {m0 - p0, m1 - p1, m2 - p2};
+        const double c2 = quad3(Si, r);
+        if (c2 < cut) insert(pchi2 + c2, hid);
+      });
+    }
+  } else {
+    scan_window([&](double m0, double m1, double m2, int32_t hid) {
+      const double m[3] = {m0, m1, m2};
+      Residual R;
+      if (residual(xp, Pp, m, hr, R) && R.chi2 < cut) insert(pchi2 + R.chi2, hid);
+    });
   }
   if (nrec == 0) {
     if (meta_nm(meta) < a.g.max_missed) {

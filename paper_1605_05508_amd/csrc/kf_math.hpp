@@ -395,6 +395,32 @@ struct Residual {
   double chi2;
 };
 
+// Inverse of the symmetric 3x3 S (packed 00 01 02 11 12 22) by cofactors
+// over the determinant; returns whether S is positive definite (Sylvester).
+KTF_HD bool sym3_inverse(const double S[6], double Si[6]) {
+  const double S00 = S[0], S01 = S[1], S02 = S[2], S11 = S[3], S12 = S[4], S22 = S[5];
+  const double c00 = S11 * S22 - S12 * S12;
+  const double c01 = S02 * S12 - S01 * S22;
+  const double c02 = S01 * S12 - S02 * S11;
+  const double c11 = S00 * S22 - S02 * S02;
+  const double c12 = S01 * S02 - S00 * S12;
+  const double c22 = S00 * S11 - S01 * S01;
+  const double det = S00 * c00 + S01 * c01 + S02 * c02;
+  const bool pd = S00 > 0.0 && c22 > 0.0 && det > 0.0;
+  const double idet = rcp_nr(det);
+  Si[0] = c00 * idet; Si[1] = c01 * idet; Si[2] = c02 * idet;
+  Si[3] = c11 * idet; Si[4] = c12 * idet; Si[5] = c22 * idet;
+  return pd;
+}
+
+// r^T Si r for the packed symmetric Si
+KTF_HD double quad3(const double Si[6], const double r[3]) {
+  const double Sr0 = Si[0] * r[0] + Si[1] * r[1] + Si[2] * r[2];
+  const double Sr1 = Si[1] * r[0] + Si[3] * r[1] + Si[4] * r[2];
+  const double Sr2 = Si[2] * r[0] + Si[4] * r[1] + Si[5] * r[2];
+  return r[0] * Sr0 + r[1] * Sr1 + r[2] * Sr2;
+}
+
 template <typename T, typename C>
 KTF_HD bool residual(const TrackState<T>& xp, const C Pp[21], const double m[3],
                      const HitRes& hr, Residual& o) {
@@ -411,21 +437,8 @@ KTF_HD bool residual(const TrackState<T>& xp, const C Pp[21], const double m[3],
   const double S02 = (double)Pp[pidx(0, 2)], S11 = (double)Pp[pidx(1, 1)] + V11;
   const double S12 = (double)Pp[pidx(1, 2)], S22 = (double)Pp[pidx(2, 2)] + hr.sz2;
   o.S[0] = S00; o.S[1] = S01; o.S[2] = S02; o.S[3] = S11; o.S[4] = S12; o.S[5] = S22;
-  const double c00 = S11 * S22 - S12 * S12;
-  const double c01 = S02 * S12 - S01 * S22;
-  const double c02 = S01 * S12 - S02 * S11;
-  const double c11 = S00 * S22 - S02 * S02;
-  const double c12 = S01 * S02 - S00 * S12;
-  const double c22 = S00 * S11 - S01 * S01;
-  const double det = S00 * c00 + S01 * c01 + S02 * c02;
-  const bool pd = S00 > 0.0 && c22 > 0.0 && det > 0.0;
-  const double idet = rcp_nr(det);
-  o.Si[0] = c00 * idet; o.Si[1] = c01 * idet; o.Si[2] = c02 * idet;
-  o.Si[3] = c11 * idet; o.Si[4] = c12 * idet; o.Si[5] = c22 * idet;
-  const double Sr0 = o.Si[0] * o.r[0] + o.Si[1] * o.r[1] + o.Si[2] * o.r[2];
-  const double Sr1 = o.Si[1] * o.r[0] + o.Si[3] * o.r[1] + o.Si[4] * o.r[2];
-  const double Sr2 = o.Si[2] * o.r[0] + o.Si[4] * o.r[1] + o.Si[5] * o.r[2];
-  o.chi2 = o.r[0] * Sr0 + o.r[1] * Sr1 + o.r[2] * Sr2;
+  const bool pd = sym3_inverse(o.S, o.Si);
+  o.chi2 = quad3(o.Si, o.r);
   return pd;
 }
 
