@@ -867,19 +867,24 @@ __device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, i
   return r1 < r2;
 }
 
-// Four lanes per seed (a quad): lane q owns the seed's parents q, q + 4, ...
-// (PPL = ceil(max_cands / 4) slots) and holds each one's record-list head
-// (chi2, hit) in registers, with the next three records prefetched in the
-// same pass of independent loads.  The max_cands best heads by the ranking
-// (more hits, lower chi2, lower parent, lower hit; a missed layer counts no
-// hit) are taken one at a time: each lane's best slot, then the quad's best
-// by two DPP exchanges, so the dependent chain per pick stays in registers.
-// Parents that ended this layer compete for the seed's best ended candidate
-// the same way.  The kept records become the seed's children: contiguous
-// rows of the next buffer, in pick order, reserved for the whole block at
-// once.
+// LPS lanes per seed (1, 2 or 4, inside one quad): lane q owns the seed's
+// parents q, q + LPS, ... (PPL = ceil(max_cands / LPS) slots) and holds each
+// one's record-list head (chi2, hit) in registers, with the next three
+// records prefetched in the same pass of independent loads.  The max_cands
+// best heads by the ranking (more hits, lower chi2, lower parent, lower hit;
+// a missed layer counts no hit) are taken one at a time: each lane's best
+// slot, then the group's best by DPP exchanges, so the dependent chain per
+// pick stays in registers.  Parents that ended this layer compete for the
+// seed's best ended candidate the same way.  The kept records become the
+// seed's children: contiguous rows of the next buffer, in pick order,
+// reserved for the whole block at once.
+//
+// Fewer lanes per seed issue fewer instructions per seed (a lane-local
+// compare costs less than an exchange, and a group's lanes all execute
+// every pick) but hold more parents' heads in registers.
 constexpr int kMergeThreads = 256;
-constexpr int kMergeSeeds = kMergeThreads / 4;
+constexpr int merge_lanes(int max_cands) { return max_cands <= 4 ? 1 : (max_cands <= 10 ? 2 : 4); }
+constexpr int merge_seeds(int lps) { return kMergeThreads / lps; }
 
 // a record-list head as ranked by the merge: key = 0 for none, else the hit
 // count it gives plus one; pj = parent << 8 | record
@@ -913,36 +918,44 @@ __device__ __forceinline__ int dpp_i(int v) {
   return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
 }
 
-// best of the quad; every lane ends with the same head (a strict total
-// order: parents are distinct)
-__device__ __forceinline__ void quad_best(MHead& h) {
-  {
-    const int64_t cb = __double_as_longlong(h.c);
-    MHead o{dpp_i<0xB1>(h.key), __longlong_as_double(((int64_t)dpp_i<0xB1>((int)(cb >> 32)) << 32) |
-                                                     (uint32_t)dpp_i<0xB1>((int)cb)),
-            dpp_i<0xB1>(h.pj), dpp_i<0xB1>(h.hit)};  // lanes q ^ 1
-    mhead_take(h, o);
-  }
-  {
-    const int64_t cb = __double_as_longlong(h.c);
-    MHead o{dpp_i<0x4E>(h.key), __longlong_as_double(((int64_t)dpp_i<0x4E>((int)(cb >> 32)) << 32) |
-                                                     (uint32_t)dpp_i<0x4E>((int)cb)),
-            dpp_i<0x4E>(h.pj), dpp_i<0x4E>(h.hit)};  // lanes q ^ 2
-    mhead_take(h, o);
-  }
+template <int CTRL>
+__device__ __forceinline__ void dpp_take(MHead& h) {
+  const int64_t cb = __double_as_longlong(h.c);
+  const MHead o{dpp_i<CTRL>(h.key),
+                __longlong_as_double(((int64_t)dpp_i<CTRL>((int)(cb >> 32)) << 32) |
+                                     (uint32_t)dpp_i<CTRL>((int)cb)),
+                dpp_i<CTRL>(h.pj), dpp_i<CTRL>(h.hit)};
+  mhead_take(h, o);
 }
 
-template <typename TS, int PPL>
+// best of the seed's LPS lanes; every one ends with the same head (a strict
+// total order: parents are distinct)
+template <int LPS>
+__device__ __forceinline__ void group_best(MHead& h) {
+  if constexpr (LPS >= 2) dpp_take<0xB1>(h);  // lanes q ^ 1
+  if constexpr (LPS == 4) dpp_take<0x4E>(h);  // lanes q ^ 2
+}
+
+// the value of the group's first lane
+template <int LPS>
+__device__ __forceinline__ int group_first(int v) {
+  if constexpr (LPS == 4) return dpp_i<0x00>(v);  // quad lanes 0,0,0,0
+  if constexpr (LPS == 2) return dpp_i<0xA0>(v);  // quad lanes 0,0,2,2
+  return v;
+}
+
+template <typename TS, int LPS, int PPL>
 __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a, int l, int cur) {
+  constexpr int SB = merge_seeds(LPS);
   __shared__ int wtot[kMergeThreads / 64 + 1];
-  __shared__ int pick_s[kMergeSeeds][4 * PPL];  // parent | record << 8
-  __shared__ int phit_s[kMergeSeeds][4 * PPL];
-  __shared__ double pchi_s[kMergeSeeds][4 * PPL];
+  __shared__ int pick_s[SB][LPS * PPL];  // parent << 8 | record
+  __shared__ int phit_s[SB][LPS * PPL];
+  __shared__ double pchi_s[SB][LPS * PPL];
   const int NC = a.g.max_cands;
   const int tid = threadIdx.x;
-  const int q = tid & 3, ls = tid >> 2;
+  const int q = tid % LPS, ls = tid / LPS;
   const int64_t sp = a.sp, S = a.S;
-  const int64_t s = (int64_t)blockIdx.x * kMergeSeeds + ls;
+  const int64_t s = (int64_t)blockIdx.x * SB + ls;
   const bool real = s < a.n_seeds;
   int nlive = 0;
   int64_t pbase = 0;
@@ -959,7 +972,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   double pchi[PPL], hc[PPL], pre_c[PPL][3];
 #pragma unroll
   for (int u = 0; u < PPL; ++u) {
-    const int j = q + 4 * u;
+    const int j = q + LPS * u;
     const int64_t p = pbase + j;
     rc[u] = 0;
     nh[u] = 0;
@@ -977,7 +990,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   }
 #pragma unroll
   for (int u = 0; u < PPL; ++u) {
-    const int64_t p = pbase + q + 4 * u;
+    const int64_t p = pbase + q + LPS * u;
     if (rc[u] > 1) {
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
@@ -993,29 +1006,29 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       }
     }
   }
-  // best ended parent (quad-uniform result)
+  // best ended parent (the same in all the seed's lanes)
   MHead eb{0, 0.0, 0, 0};
 #pragma unroll
   for (int u = 0; u < PPL; ++u) {
-    const int j = q + 4 * u;
+    const int j = q + LPS * u;
     const MHead h{(j < nlive && rc[u] <= 0) ? nh[u] + 1 : 0, pchi[u], j << 8, 0};
     if (u == 0)
       eb = h;
     else
       mhead_take(eb, h);
   }
-  quad_best(eb);
+  group_best<LPS>(eb);
   if (eb.key > 0) {
     const int e_nh = eb.key - 1, ej = eb.pj >> 8;
     const int be = a.bend[s];
     if (be < 0 || final_less(e_nh, eb.c, l, ej, meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s])) {
-      // the quad copies the ended candidate element by element
+      // the seed's lanes copy the ended candidate element by element
       const int64_t pe = pbase + ej;
       const TS* mo = static_cast<const TS*>(a.cmom[cur]);
       const TS* co = static_cast<const TS*>(a.ccov[cur]);
       TS* bm = static_cast<TS*>(a.bmom);
       TS* bc = static_cast<TS*>(a.bcov);
-      for (int e = q; e < 27; e += 4) {
+      for (int e = q; e < 27; e += LPS) {
         if (e < 3)
           a.bpos[e * sp + s] = a.cpos[cur][e * S + pe];
         else if (e < 6)
@@ -1043,10 +1056,10 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     MHead w{hk[0], hc[0], (q << 8) | hd[0], hh[0]};
 #pragma unroll
     for (int u = 1; u < PPL; ++u) {
-      mhead_take(w, MHead{hk[u], hc[u], ((q + 4 * u) << 8) | hd[u], hh[u]});
+      mhead_take(w, MHead{hk[u], hc[u], ((q + LPS * u) << 8) | hd[u], hh[u]});
     }
-    quad_best(w);
-    if (w.key == 0) break;  // quad-uniform
+    group_best<LPS>(w);
+    if (w.key == 0) break;  // uniform over the seed's lanes
     if (q == 0) {
       pick_s[ls][k] = w.pj;
       phit_s[ls][k] = w.hit;
@@ -1058,7 +1071,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     int64_t far = -1;  // row of a record beyond the prefetched ones, to load
 #pragma unroll
     for (int u = 0; u < PPL; ++u) {
-      const bool adv = wj == q + 4 * u;
+      const bool adv = wj == q + LPS * u;
       const int nx = hd[u] + 1;
       const bool more = nx < rc[u];
       if (adv && more && nx >= 4) far = (int64_t)nx * S + pbase + wj;
@@ -1077,7 +1090,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       const int fh = a.rhit[far];
 #pragma unroll
       for (int u = 0; u < PPL; ++u) {
-        if (wj == q + 4 * u) {
+        if (wj == q + LPS * u) {
           hc[u] = fc;
           hh[u] = fh;
         }
@@ -1087,12 +1100,12 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   }
   const int reg = block_region();
   const int local = (int)block_reserve(region_ctr(a, l, reg), q == 0 ? nsel : 0, wtot);
-  const int64_t first = reg * a.RS + dpp_i<0x00>(local);  // lane 0 of the quad
+  const int64_t first = reg * a.RS + group_first<LPS>(local);
   if (real && q == 0) {
     a.count[(int64_t)l * sp + s] = nsel;
     if (nsel > 0) a.cstart[cur ^ 1][s] = (int32_t)first;
   }
-  for (int k = q; k < nsel; k += 4) {
+  for (int k = q; k < nsel; k += LPS) {
     const int pk = pick_s[ls][k];
     a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = pk >> 8;
     a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = phit_s[ls][k];
@@ -1193,28 +1206,39 @@ static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) 
 
 // Rows per region: enough for the blocks that reserve in one region (at
 // most ceil(blocks / kRegions), see block_region), for the seed kernel (256 seeds of one row
-// each per block) and for the merge (kMergeSeeds seeds of up to max_cands
+// each per block) and for the merge (merge_seeds seeds of up to max_cands
 // rows each per block); a multiple of 256 rows (the row-kernel block).
 static int64_t region_rows(int64_t n_seeds, int nc) {
-  const int64_t sb = kMergeSeeds;
+  const int64_t sb = merge_seeds(merge_lanes(nc));
   const int64_t per_merge = (((n_seeds + sb - 1) / sb + kRegions - 1) / kRegions) * sb * nc;
   const int64_t per_seed = (((n_seeds + 255) / 256 + kRegions - 1) / kRegions) * 256;
   const int64_t r = std::max<int64_t>(std::max(per_merge, per_seed), 1);
   return (r + 255) / 256 * 256;
 }
 
+template <typename TS, int LPS, int PPL>
+static void launch_merge_as(const BuildArgs& a, int l, int cur, hipStream_t st) {
+  const dim3 grid(nblk(a.n_seeds, merge_seeds(LPS))), block(kMergeThreads);
+  hipLaunchKernelGGL((build_merge_kernel<TS, LPS, PPL>), grid, block, 0, st, a, l, cur);
+}
+
+// parents per lane: max_cands over the lanes per seed, rounded up
 template <typename TS>
 static void launch_merge(const BuildArgs& a, int l, int cur, hipStream_t st) {
-  const dim3 grid(nblk(a.n_seeds, kMergeSeeds)), block(kMergeThreads);
-  const int ppl = (a.g.max_cands + 3) / 4;  // parents per lane
-  if (ppl <= 1)
-    hipLaunchKernelGGL((build_merge_kernel<TS, 1>), grid, block, 0, st, a, l, cur);
-  else if (ppl == 2)
-    hipLaunchKernelGGL((build_merge_kernel<TS, 2>), grid, block, 0, st, a, l, cur);
-  else if (ppl == 3)
-    hipLaunchKernelGGL((build_merge_kernel<TS, 3>), grid, block, 0, st, a, l, cur);
-  else
-    hipLaunchKernelGGL((build_merge_kernel<TS, 4>), grid, block, 0, st, a, l, cur);
+  const int nc = a.g.max_cands, lps = merge_lanes(nc), ppl = (nc + lps - 1) / lps;
+  if (lps == 1) {
+    if (ppl <= 2)
+      launch_merge_as<TS, 1, 2>(a, l, cur, st);
+    else
+      launch_merge_as<TS, 1, 4>(a, l, cur, st);
+  } else if (lps == 2) {
+    if (ppl <= 3)
+      launch_merge_as<TS, 2, 3>(a, l, cur, st);
+    else
+      launch_merge_as<TS, 2, 5>(a, l, cur, st);
+  } else {
+    launch_merge_as<TS, 4, 4>(a, l, cur, st);
+  }
 }
 
 template <typename TS, typename TP>
