@@ -968,8 +968,9 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     info = pack_info(e, a.q[s]);
     hbase = a.hit_off[(int64_t)e * a.g.n_layers + l];
   }
-  int rc[PPL], nh[PPL], hd[PPL], hh[PPL], pre_h[PPL][3];
-  double pchi[PPL], hc[PPL], pre_c[PPL][3];
+  constexpr int PF = 3;  // records prefetched behind each head
+  int rc[PPL], nh[PPL], hd[PPL], hh[PPL], pre_h[PPL][PF];
+  double pchi[PPL], hc[PPL], pre_c[PPL][PF];
 #pragma unroll
   for (int u = 0; u < PPL; ++u) {
     const int j = q + LPS * u;
@@ -993,14 +994,14 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     const int64_t p = pbase + q + LPS * u;
     if (rc[u] > 1) {
 #pragma unroll
-      for (int v = 0; v < 3; ++v) {
+      for (int v = 0; v < PF; ++v) {
         const int64_t ri = (int64_t)min(v + 1, rc[u] - 1) * S + p;
         pre_c[u][v] = a.rchi[ri];
         pre_h[u][v] = a.rhit[ri];
       }
     } else {
 #pragma unroll
-      for (int v = 0; v < 3; ++v) {
+      for (int v = 0; v < PF; ++v) {
         pre_c[u][v] = 0.0;
         pre_h[u][v] = -1;
       }
@@ -1068,24 +1069,26 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     // the owner lane advances that parent's head (selects, not branches;
     // records beyond the prefetched ones are loaded, rarely)
     const int wj = w.pj >> 8;
-    int64_t far = -1;  // row of a record beyond the prefetched ones, to load
+    int nxw = 0;  // the owner lane's next record, where its list has one
 #pragma unroll
     for (int u = 0; u < PPL; ++u) {
       const bool adv = wj == q + LPS * u;
       const int nx = hd[u] + 1;
       const bool more = nx < rc[u];
-      if (adv && more && nx >= 4) far = (int64_t)nx * S + pbase + wj;
+      nxw = adv && more ? nx : nxw;
       // the prefetched records move up one place
       hd[u] = adv ? nx : hd[u];
       hc[u] = adv ? pre_c[u][0] : hc[u];
       hh[u] = adv ? pre_h[u][0] : hh[u];
-      pre_c[u][0] = adv ? pre_c[u][1] : pre_c[u][0];
-      pre_h[u][0] = adv ? pre_h[u][1] : pre_h[u][0];
-      pre_c[u][1] = adv ? pre_c[u][2] : pre_c[u][1];
-      pre_h[u][1] = adv ? pre_h[u][2] : pre_h[u][1];
+#pragma unroll
+      for (int v = 0; v + 1 < PF; ++v) {
+        pre_c[u][v] = adv ? pre_c[u][v + 1] : pre_c[u][v];
+        pre_h[u][v] = adv ? pre_h[u][v + 1] : pre_h[u][v];
+      }
       hk[u] = adv && !more ? 0 : hk[u];
     }
-    if (far >= 0) {
+    if (nxw > PF) {  // a record beyond the prefetched ones
+      const int64_t far = (int64_t)nxw * S + pbase + wj;
       const double fc = a.rchi[far];
       const int fh = a.rhit[far];
 #pragma unroll
