@@ -448,6 +448,31 @@ __device__ __forceinline__ void store_cand(double* pos, void* mom, void* cov, in
   for (int k = 0; k < 21; ++k) c[k * S + slot] = (TS)P[k];
 }
 
+// Streaming accesses (each element touched once per launch) carry the
+// non-temporal hint, so that they do not evict the hit bins and offsets
+// that a launch's candidates search over and over from L2.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+template <typename TS, typename TP>
+__device__ __forceinline__ void store_cand_nt(double* pos, void* mom, void* cov, int64_t S,
+                                              int64_t slot, const TrackState<TP>& x, const TP P[21]) {
+  TS* m = static_cast<TS*>(mom);
+  TS* c = static_cast<TS*>(cov);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) st_nt(pos + k * S + slot, x.pos[k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) st_nt(m + k * S + slot, (TS)x.mom[k]);
+#pragma unroll
+  for (int k = 0; k < 21; ++k) st_nt(c + k * S + slot, (TS)P[k]);
+}
+
 __device__ __forceinline__ HitRes hit_res(const BuildArgs& a) {
   return HitRes{a.g.hr.sr2, a.g.hr.srphi2, a.g.hr.sz2};
 }
@@ -634,8 +659,8 @@ __device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32
 template <typename TS, typename TP>
 __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int from, int64_t c,
                                                TrackState<TP>& x, TP P[21]) {
-  const int64_t p = a.sel_parent[c];
-  const int32_t h = a.sel_hit[c];
+  const int64_t p = ld_nt(a.sel_parent + c);
+  const int32_t h = ld_nt(a.sel_hit + c);
   const uint32_t pm = a.cmeta[from][p];
   load_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], a.S, p, x, P);
   int cnh = meta_nh(pm), cnm = meta_nm(pm);
@@ -662,7 +687,7 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
 // than the few registers the cap spills in double.)
 template <typename TS, typename TP, bool MAT, bool CHILD>
 __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, int64_t c) {
-  const int32_t info = a.cinfo[cur][c];
+  const int32_t info = ld_nt(a.cinfo[cur] + c);
   const int L = a.g.n_layers, NC = a.g.max_cands;
   const int64_t S = a.S;
   const int e = info_event(info);
@@ -672,9 +697,9 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   double pchi2;
   if constexpr (CHILD) {
     meta = make_child<TS, TP>(a, l - 1, cur ^ 1, c, x, P);
-    pchi2 = a.sel_chi2[c];
-    a.cmeta[cur][c] = meta;
-    a.cchi2[cur][c] = pchi2;
+    pchi2 = ld_nt(a.sel_chi2 + c);
+    st_nt(a.cmeta[cur] + c, meta);
+    st_nt(a.cchi2[cur] + c, pchi2);
   } else {
     load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], S, c, x, P);
     meta = a.cmeta[cur][c];
@@ -703,7 +728,7 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   }
   TP Pp[21];
   cov_propagate(P, F, Pp);
-  store_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], S, c, xp, Pp);
+  store_cand_nt<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], S, c, xp, Pp);
 
   // search window: for any unit vector u, chi2 < cut implies
   // |u.d| < sqrt(cut u^T S u) (Cauchy-Schwarz in the S^-1 metric); with u
@@ -845,10 +870,10 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     }
   }
   for (int k = 0; k < nrec; ++k) {
-    a.rchi[(int64_t)k * S + c] = lc[k * B + t];
-    a.rhit[(int64_t)k * S + c] = lh[k * B + t];
+    st_nt(a.rchi + (int64_t)k * S + c, lc[k * B + t]);
+    st_nt(a.rhit + (int64_t)k * S + c, lh[k * B + t]);
   }
-  a.rcount[c] = nrec;
+  st_nt(a.rcount + c, (int32_t)nrec);
 }
 
 template <typename TS, typename TP, bool MAT, bool CHILD>
