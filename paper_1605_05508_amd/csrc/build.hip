@@ -1158,23 +1158,19 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
   const int NC = a.g.max_cands;
   const int nalive = a.count[(int64_t)(L - 1) * a.sp + s];
   const int64_t base = nalive > 0 ? a.cstart[cur][s] : 0;
-  int best_r = -1;
+  // The survivors are in rank order, and the rank order (more hits, then
+  // lower chi2, then the pick order) is the final key among candidates that
+  // all end on the last layer: the best survivor is the first.
+  const int best_r = nalive > 0 ? 0 : -1;
   int bnh = 0;
   double bc2 = 0.0;
-  for (int r = 0; r < nalive; ++r) {
-    int nh;
-    double c2;
+  if (nalive > 0) {
     if constexpr (LAZY) {
-      nh = meta_nh(a.cmeta[cur ^ 1][a.sel_parent[base + r]]) + (a.sel_hit[base + r] >= 0 ? 1 : 0);
-      c2 = a.sel_chi2[base + r];
+      bnh = meta_nh(a.cmeta[cur ^ 1][a.sel_parent[base]]) + (a.sel_hit[base] >= 0 ? 1 : 0);
+      bc2 = a.sel_chi2[base];
     } else {
-      nh = meta_nh(a.cmeta[cur][base + r]);
-      c2 = a.cchi2[cur][base + r];
-    }
-    if (best_r < 0 || final_less(nh, c2, L, r, bnh, bc2, L, best_r)) {
-      best_r = r;
-      bnh = nh;
-      bc2 = c2;
+      bnh = meta_nh(a.cmeta[cur][base]);
+      bc2 = a.cchi2[cur][base];
     }
   }
   const int be = a.bend[s];
