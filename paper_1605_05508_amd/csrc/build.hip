@@ -138,8 +138,22 @@ __device__ __forceinline__ int hit_bin_of(double x, double y, double z, double z
 #pragma clang fp contract(off)
   const double zf = floor((z + zh) * nz / (2.0 * zh));
   const int zb = zf < 0.0 ? 0 : (zf > nz - 1 ? nz - 1 : (int)zf);
-  const double phi = atan2(y, x);
-  int pb = (int)floor((phi + kPi) * nphi / (2.0 * kPi));
+  // the phi bin from a float estimate of its position, unless that lies
+  // within 1e-5 rad of a bin edge: the float angle's error (coordinates
+  // rounded to float, atan2f, the sum and the scale) is below 2e-6 rad, so
+  // away from an edge it floors to the same bin as the double form, which
+  // decides the rest
+  const float uf = (atan2f((float)y, (float)x) + (float)kPi) * ((float)nphi / (float)(2.0 * kPi));
+  const float mf = 1e-5f * ((float)nphi / (float)(2.0 * kPi));
+  const float fl = floorf(uf);
+  const float fr = uf - fl;
+  int pb;
+  if (fr > mf && fr < 1.0f - mf) {
+    pb = (int)fl;
+  } else {
+    const double phi = atan2(y, x);
+    pb = (int)floor((phi + kPi) * nphi / (2.0 * kPi));
+  }
   pb = ((pb % nphi) + nphi) % nphi;
   return zb * nphi + pb;
 }

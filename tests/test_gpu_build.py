@@ -75,6 +75,44 @@ def test_bins_match_oracle(k, orc, case):
                 assert np.array_equal(perm[a:b], op), (prec, e, l)
 
 
+def test_bins_at_phi_edges(k, orc):
+    """Hits on and within a few 1e-5 rad of phi-bin edges (and on the
+    negative x axis, where phi wraps): the kernel takes a float estimate of
+    the phi bin away from the edges and the double form near them, so every
+    hit must land in the oracle's bin.  Coordinates are float-representable,
+    so both precisions see the same hits."""
+    nz, nphi = 64, 512
+    bs = small_batch(7, 2, 1500, n_layers=4)
+    rng = np.random.default_rng(77)
+    deltas = np.array([0.0, 1e-9, -1e-9, 1e-7, -1e-7, 6e-7, -6e-7, 2e-6, -2e-6,
+                       9e-6, -9e-6, 1.1e-5, -1.1e-5, 3e-5, -3e-5])
+    L = bs.det.n_layers
+    for g in range(bs.n_events * L):
+        a, b = bs.hit_off[g], bs.hit_off[g + 1]
+        n = b - a
+        edges = rng.integers(0, nphi, size=n)
+        th = -np.pi + edges * (2 * np.pi / nphi) + deltas[rng.integers(0, len(deltas), size=n)]
+        r = bs.det.radii[g % L]
+        x, y = r * np.cos(th), r * np.sin(th)
+        x[:8], y[:8] = -r, 0.0  # phi = pi exactly
+        x[8:12], y[8:12] = -r, -0.0
+        x[12:16], y[12:16] = 0.0, r
+        bs.hits[0, a:b] = x.astype(np.float32)
+        bs.hits[1, a:b] = y.astype(np.float32)
+        bs.hits[2, a:b] = rng.uniform(-99.0, 99.0, n).astype(np.float32)
+    ctx = ctx_for(k, bs.det, n_zbins=nz, n_phibins=nphi)
+    for prec in ("fp64", "fp32b"):
+        offs, perm = ctx.bin_hits(build_inputs(bs, prec, hit_pad=64))
+        offs, perm = offs.cpu().numpy(), perm.cpu().numpy()
+        for e in range(bs.n_events):
+            for l in range(L):
+                g = e * L + l
+                oo, op = orc.bin_layer(bs.layer_hits(e, l), 100.0, nz, nphi)
+                a, b = bs.hit_off[g], bs.hit_off[g + 1]
+                assert np.array_equal(offs[g], oo), (prec, e, l)
+                assert np.array_equal(perm[a:b], op), (prec, e, l)
+
+
 @pytest.mark.parametrize("ghosts", [False, True])
 def test_fp64_build_matches_oracle(k, orc, ghosts):
     bs = small_batch(2, 3, 300, ghosts=ghosts)
