@@ -68,7 +68,7 @@ struct BuildArgs {
   int32_t* bin_off;        // [n_groups][n_bins+1]
   int32_t* bin_cur;        // [n_groups][n_bins]
   int32_t* hit_bin;        // [n_hits]
-  int32_t* perm;           // [n_hits]: local index of the hit at each binned position
+  int32_t* perm;           // [n_hits]: local index of the hit at each binned position (binning alone; null when building: the records hold it)
   int32_t* perm_raw;       // [n_hits]: the same before ordering within bins
   int32_t* sev;            // [sp]: event of each seed
   int32_t* cinfo[2];       // [S]: event << 1 | (charge > 0) of each dense candidate row
@@ -77,7 +77,7 @@ struct BuildArgs {
   int32_t* sel_hit;        // [S]: per child row, the hit it takes as an index into hits (-1: missed layer)
   double* sel_chi2;        // [S]: per child row, its chi2 total
   unsigned* ccount;        // [n_layers][kRegions][kCtrStride]: rows used per region after each layer
-  void* hb;                // [3][n_hits]: binned coordinates
+  void* hb;                // [n_hits] BinHit<TS>: binned coordinates and local index
   // candidates (double buffered), propagated parents, records
   double* cpos[2];
   void* cmom[2];
@@ -134,6 +134,19 @@ __device__ __forceinline__ uint32_t meta_st(uint32_t m) { return m >> 16; }
 // bin of a hit: zbin = floor((z + zh) nz / (2 zh)) clamped, phibin =
 // floor((atan2(y, x) + pi) nphi / (2 pi)) mod nphi; same arithmetic order in
 // double as the definition, no contraction.
+// A binned hit as the window scan reads it: its coordinates and its index
+// within the group in one record (one 16-byte load in float, two in
+// double), so a window's run of hits is one run of records.
+template <typename TS> struct BinHit;
+template <> struct __align__(16) BinHit<float> {
+  float x, y, z;
+  int32_t id;
+};
+template <> struct __align__(16) BinHit<double> {
+  double x, y, z;
+  int32_t id, pad;
+};
+
 __device__ __forceinline__ int hit_bin_of(double x, double y, double z, double zh, int nz, int nphi) {
 #pragma clang fp contract(off)
   const double zf = floor((z + zh) * nz / (2.0 * zh));
@@ -247,12 +260,14 @@ __global__ void bin_rank_kernel(BuildArgs a) {
   int32_t rank = 0;
   for (int32_t k = lo; k < hi; ++k) rank += a.perm_raw[base + k] < jl ? 1 : 0;
   const int64_t dst = base + lo + rank;
-  a.perm[dst] = jl;
+  if (a.perm) a.perm[dst] = jl;
   const TS* h = static_cast<const TS*>(a.hits);
-  TS* o = static_cast<TS*>(a.hb);
-  o[dst] = h[j];
-  o[a.n_hits + dst] = h[a.hp + j];
-  o[2 * a.n_hits + dst] = h[2 * a.hp + j];
+  BinHit<TS> r;
+  r.x = h[j];
+  r.y = h[a.hp + j];
+  r.z = h[2 * a.hp + j];
+  r.id = jl;
+  static_cast<BinHit<TS>*>(a.hb)[dst] = r;
 }
 
 constexpr int kBinThreads = 1024;
@@ -396,7 +411,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
     for (int u = 0; u < kBinBatch; ++u)
       if (dst[bi][u] >= 0) permr[dst[bi][u]] = (uint16_t)(bi * kBinBatch * kBinThreads + u * kBinThreads + tid);
   __syncthreads();
-  TS* o = static_cast<TS*>(a.hb);
+  BinHit<TS>* o = static_cast<BinHit<TS>*>(a.hb);
   for (int32_t i0 = 0; i0 < n; i0 += kBinBatch * kBinThreads) {
     int32_t jj[kBinBatch];
     TS x[kBinBatch], y[kBinBatch], z[kBinBatch];
@@ -420,10 +435,13 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
       const int32_t i = i0 + u * kBinThreads + tid;
       if (i < n) {
         const int64_t d = base + i;
-        a.perm[d] = jj[u];
-        o[d] = x[u];
-        o[a.n_hits + d] = y[u];
-        o[2 * a.n_hits + d] = z[u];
+        if (a.perm) a.perm[d] = jj[u];
+        BinHit<TS> r;
+        r.x = x[u];
+        r.y = y[u];
+        r.z = z[u];
+        r.id = jj[u];
+        o[d] = r;
       }
     }
   }
@@ -779,7 +797,7 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   const int g = e * L + l;
   const int32_t* off = a.bin_off + (int64_t)g * (a.n_bins + 1);
   const int64_t base = a.hit_off[g];
-  const TS* hb = static_cast<const TS*>(a.hb);
+  const BinHit<TS>* hb = static_cast<const BinHit<TS>*>(a.hb);
   const HitRes hr = hit_res(a);
   // the candidate's sorted record list lives in LDS while the window is
   // scanned (rows [k][blockDim] of the dynamic shared memory: chi2 totals,
@@ -808,16 +826,14 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
       // second hit's registers would spill)
       for (int32_t j = j0; j < j1; j += 2) {
         const int64_t h0 = base + j, h1 = base + (j + 1 < j1 ? j + 1 : j);
-        const TS x0 = hb[h0], y0 = hb[a.n_hits + h0], z0 = hb[2 * a.n_hits + h0];
-        const TS x1 = hb[h1], y1 = hb[a.n_hits + h1], z1 = hb[2 * a.n_hits + h1];
-        const int32_t id0 = a.perm[h0], id1 = a.perm[h1];
-        score((double)x0, (double)y0, (double)z0, id0);
-        if (j + 1 < j1) score((double)x1, (double)y1, (double)z1, id1);
+        const BinHit<TS> r0 = hb[h0], r1 = hb[h1];
+        score((double)r0.x, (double)r0.y, (double)r0.z, r0.id);
+        if (j + 1 < j1) score((double)r1.x, (double)r1.y, (double)r1.z, r1.id);
       }
     } else {
       for (int32_t j = j0; j < j1; ++j) {
-        const int64_t h = base + j;
-        score((double)hb[h], (double)hb[a.n_hits + h], (double)hb[2 * a.n_hits + h], a.perm[h]);
+        const BinHit<TS> r = hb[base + j];
+        score(r.x, r.y, r.z, r.id);
       }
     }
   };
@@ -1431,9 +1447,11 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.perm = static_cast<int32_t*>(c->b_perm.p);
   a.hit_bin = a.perm + nhits;
   a.perm_raw = a.hit_bin + nhits;
-  if ((e = c->b_binned.ensure(ts * 3 * (size_t)nhits)) != hipSuccess) return hip_fail(c, e, "bin workspace");
+  const size_t rec = ts == 4 ? sizeof(BinHit<float>) : sizeof(BinHit<double>);
+  if ((e = c->b_binned.ensure(rec * (size_t)nhits)) != hipSuccess) return hip_fail(c, e, "bin workspace");
   a.hb = c->b_binned.p;
   if (bins_only) return KTF_OK;
+  a.perm = nullptr;  // building reads the local indices from the records
 
   const int64_t S = std::max<int64_t>(a.S, 1);
   const size_t cand_bytes = (size_t)S * (3 * 8 + 24 * ts + 8 + 4);
