@@ -968,6 +968,16 @@ __device__ __forceinline__ void mhead_take(MHead& w, const MHead& h) {
   w.hit = b ? h.hit : w.hit;
 }
 
+// w = the better of w and h where h's parent is known to come after w's
+// (a lane's own slots, taken in order): a tie in hits and chi2 keeps w
+__device__ __forceinline__ void mhead_take_later(MHead& w, const MHead& h) {
+  const bool b = (h.key > w.key) | ((h.key == w.key) & (h.c < w.c));
+  w.key = b ? h.key : w.key;
+  w.c = b ? h.c : w.c;
+  w.pj = b ? h.pj : w.pj;
+  w.hit = b ? h.hit : w.hit;
+}
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
   return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
@@ -1071,7 +1081,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     if (u == 0)
       eb = h;
     else
-      mhead_take(eb, h);
+      mhead_take_later(eb, h);
   }
   group_best<LPS>(eb);
   if (eb.key > 0) {
@@ -1112,7 +1122,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     MHead w{hk[0], hc[0], (q << 8) | hd[0], hh[0]};
 #pragma unroll
     for (int u = 1; u < PPL; ++u) {
-      mhead_take(w, MHead{hk[u], hc[u], ((q + LPS * u) << 8) | hd[u], hh[u]});
+      mhead_take_later(w, MHead{hk[u], hc[u], ((q + LPS * u) << 8) | hd[u], hh[u]});
     }
     group_best<LPS>(w);
     if (w.key == 0) break;  // uniform over the seed's lanes
