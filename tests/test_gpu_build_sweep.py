@@ -1,7 +1,8 @@
 """A sweep of building configurations against the FP64 oracle: for a fixed
 list of seeded cases (layer counts, beam widths, missed-layer allowances,
 chi2 cuts, with and without layer material, ghost hits that make
-candidates branch, several events of uneven size in one batch), the FP64
+candidates branch, several events of uneven size in one batch; the beam
+widths cover every lanes-per-seed and slots-per-lane form of the merge), the FP64
 GPU build must give every seed exactly the oracle's hits, hit count and
 status, and its chi2 within 1e-10."""
 import numpy as np
@@ -22,6 +23,9 @@ CASES = [
     (106, 8, 10, 2, 60.0, 0.02, (100,)),
     (107, 14, 3, 0, 30.0, 0.005, (60, 220, 10)),
     (108, 17, 10, 1, 30.0, 0.01, (250,)),
+    (109, 11, 6, 1, 30.0, 0.0, (150, 90)),
+    (110, 9, 12, 2, 40.0, 0.0, (120,)),
+    (111, 8, 2, 1, 30.0, 0.0, (200,)),
 ]
 
 
