@@ -279,7 +279,8 @@ typedef struct {
   uint32_t *status;         /* host [n_seeds]                                    */
   double t_submit, t_admit, t_done; /* seconds on the library's monotonic clock:
                                        entry of ktf_submit (the copy-in counts),
-                                       admission onto a lane, results on the host */
+                                       admission onto a lane, results ready to
+                                       collect (copied out of the batch) */
 } ktf_result_host;
 
 /* Copy the event into library staging and queue it; returns a ticket.  The

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <memory>
 
 #include "ctx.hpp"
 #include "kf_math.hpp"
@@ -19,28 +20,52 @@
 namespace ktf {
 
 constexpr int kLanes = 4;                 // streams with their own workspace
+constexpr size_t kPoolEvents = 16;        // collected events kept for reuse
+constexpr size_t kPoolEventBytes = 64ull << 20;  // ... each holding at most this much host memory
 constexpr int64_t kMaxBatchSeeds = 131072;  // bound on one batch's work (latency)
+
+// A host buffer that keeps its pages between events: grown geometrically
+// and never zero-filled, so a reused event neither allocates nor faults.
+template <typename T>
+struct HostBuf {
+  std::unique_ptr<T[]> p;
+  size_t cap = 0;
+  T* get(size_t n) {
+    if (n > cap) {
+      const size_t c = std::max(n, cap + cap / 2);
+      p.reset(new T[c]);
+      cap = c;
+    }
+    return p.get();
+  }
+  T* data() const { return p.get(); }
+  size_t bytes() const { return cap * sizeof(T); }
+};
 
 struct ServeEvent {
   uint64_t ticket = 0;
   int64_t n_seeds = 0, n_hits = 0;
   ktf_precision prec = KTF_FP32_BULK;
   std::vector<int64_t> hit_off;  // [L+1]
-  std::vector<float> hits;       // [3][n_hits]
-  std::vector<float> state;      // [6][n]
-  std::vector<float> cov;        // [21][n]
-  std::vector<int8_t> q;
-  std::vector<int32_t> seed_hit; // [nsl][n]
+  HostBuf<float> hits;           // [3][n_hits]
+  HostBuf<float> state;          // [6][n]
+  HostBuf<float> cov;            // [21][n]
+  HostBuf<int8_t> q;
+  HostBuf<int32_t> seed_hit;     // [nsl][n]
   size_t footprint = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   bool done = false;
   int error = 0;
   // results
-  std::vector<int32_t> r_hit;    // [L][n]
-  std::vector<float> r_state, r_cov;
-  std::vector<double> r_chi2;
-  std::vector<int32_t> r_nh;
-  std::vector<uint32_t> r_st;
+  HostBuf<int32_t> r_hit;        // [L][n]
+  HostBuf<float> r_state, r_cov;
+  HostBuf<double> r_chi2;
+  HostBuf<int32_t> r_nh;
+  HostBuf<uint32_t> r_st;
+  size_t held_bytes() const {
+    return hits.bytes() + state.bytes() + cov.bytes() + q.bytes() + seed_hit.bytes() + r_hit.bytes() +
+           r_state.bytes() + r_cov.bytes() + r_chi2.bytes() + r_nh.bytes() + r_st.bytes();
+  }
 };
 
 struct Lane {
@@ -64,6 +89,9 @@ struct ServeState {
   std::condition_variable cv;
   std::deque<ServeEvent*> queue;
   std::map<uint64_t, ServeEvent*> tickets;
+  // collected events kept for reuse with their host buffers (at most
+  // kPoolEvents of them)
+  std::vector<ServeEvent*> pool;
   Lane lanes[kLanes];
   uint64_t next_ticket = 1;
   size_t inflight_bytes = 0;
@@ -375,18 +403,15 @@ static void unpack_batch_t(ktf_ctx* c, Lane& ln) {
   std::vector<RowCopy> tasks;
   for (ServeEvent* ev : ln.batch) {
     const int64_t n = ev->n_seeds;
-    ev->r_hit.resize((size_t)L * n);
-    ev->r_state.resize(6 * n);
-    ev->r_cov.resize(21 * n);
-    ev->r_chi2.resize(n);
-    ev->r_nh.resize(n);
-    ev->r_st.resize(n);
-    for (int l = 0; l < L; ++l) tasks.push_back({hit + l * N + sb, ev->r_hit.data() + l * n, n, 3});
-    for (int k = 0; k < 6; ++k) tasks.push_back({st + k * N + sb, ev->r_state.data() + k * n, n, kind_out<TS>()});
-    for (int k = 0; k < 21; ++k) tasks.push_back({cv + k * N + sb, ev->r_cov.data() + k * n, n, kind_out<TS>()});
-    tasks.push_back({c2 + sb, ev->r_chi2.data(), 8 * n, 4});
-    tasks.push_back({nu + sb, ev->r_nh.data(), n, 3});
-    tasks.push_back({ss + sb, ev->r_st.data(), n, 3});
+    int32_t* r_hit = ev->r_hit.get((size_t)L * n);
+    float* r_state = ev->r_state.get(6 * n);
+    float* r_cov = ev->r_cov.get(21 * n);
+    for (int l = 0; l < L; ++l) tasks.push_back({hit + l * N + sb, r_hit + l * n, n, 3});
+    for (int k = 0; k < 6; ++k) tasks.push_back({st + k * N + sb, r_state + k * n, n, kind_out<TS>()});
+    for (int k = 0; k < 21; ++k) tasks.push_back({cv + k * N + sb, r_cov + k * n, n, kind_out<TS>()});
+    tasks.push_back({c2 + sb, ev->r_chi2.get(n), 8 * n, 4});
+    tasks.push_back({nu + sb, ev->r_nh.get(n), n, 3});
+    tasks.push_back({ss + sb, ev->r_st.get(n), n, 3});
     sb += n;
   }
   run_copies(tasks);
@@ -403,10 +428,14 @@ static void scheduler(ktf_ctx* c) {
       if (!ln.busy) continue;
       hipError_t q = hipEventQuery(ln.done);
       if (q == hipErrorNotReady) continue;
-      const double t = now_s();
       if (q == hipSuccess) {
+        // the lane and its events' result buffers belong to this thread
+        // until the events are marked done: submissions and polls go on
+        lk.unlock();
         if (ln.prec == KTF_FP64) unpack_batch_t<double>(c, ln); else unpack_batch_t<float>(c, ln);
+        lk.lock();
       }
+      const double t = now_s();  // the results can be collected from here on
       for (ServeEvent* ev : ln.batch) {
         ev->done = true;
         ev->error = q == hipSuccess ? 0 : KTF_EDEVICE;
@@ -513,6 +542,7 @@ void serve_shutdown(ktf_ctx* c) {
     if (ln.sub) ktf_destroy(ln.sub);
   }
   for (auto& kv : S->tickets) delete kv.second;
+  for (ServeEvent* e : S->pool) delete e;
   delete S;
   c->serve = nullptr;
 }
@@ -544,24 +574,41 @@ int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
                 (unsigned long long)cfg.hbm_budget_bytes);
   int rc = ensure_serving(c);
   if (rc) return rc;
-  ServeEvent* e = new ServeEvent();
+  ServeState* S = c->serve;
+  ServeEvent* e = nullptr;
+  {
+    // a collected event whose buffers already hold this one's hits, else
+    // the largest one kept
+    std::lock_guard<std::mutex> g(S->mu);
+    const size_t need = (size_t)(3 * nh);
+    int fit = -1, big = -1;
+    for (int i = 0; i < (int)S->pool.size(); ++i) {
+      const size_t cap = S->pool[i]->hits.cap;
+      if (cap >= need && (fit < 0 || cap < S->pool[fit]->hits.cap)) fit = i;
+      if (big < 0 || cap > S->pool[big]->hits.cap) big = i;
+    }
+    const int pick = fit >= 0 ? fit : big;
+    if (pick >= 0) {
+      e = S->pool[pick];
+      S->pool[pick] = S->pool.back();
+      S->pool.pop_back();
+    }
+  }
+  if (!e) e = new ServeEvent();
+  e->done = false;
+  e->error = 0;
+  e->t_admit = e->t_done = 0;
   e->n_seeds = n;
   e->n_hits = nh;
   e->prec = ev->prec;
   e->hit_off.assign(ev->hit_off, ev->hit_off + L + 1);
-  e->hits.resize(3 * nh);
-  e->state.resize(6 * n);
-  e->cov.resize(21 * n);
-  e->q.resize(n);
-  e->seed_hit.resize((size_t)NSL * n);
-  run_copies({{ev->hits, e->hits.data(), 3 * nh, 0},
-              {ev->seed_state, e->state.data(), 6 * n, 0},
-              {ev->seed_cov, e->cov.data(), 21 * n, 0},
-              {ev->charge, e->q.data(), n, 4},
-              {ev->seed_hit, e->seed_hit.data(), (int64_t)NSL * n, 3}});
+  run_copies({{ev->hits, e->hits.get(3 * nh), 3 * nh, 0},
+              {ev->seed_state, e->state.get(6 * n), 6 * n, 0},
+              {ev->seed_cov, e->cov.get(21 * n), 21 * n, 0},
+              {ev->charge, e->q.get(n), n, 4},
+              {ev->seed_hit, e->seed_hit.get((size_t)NSL * n), (int64_t)NSL * n, 3}});
   e->footprint = fp;
   e->t_submit = t_entry;
-  ServeState* S = c->serve;
   {
     std::lock_guard<std::mutex> g(S->mu);
     e->ticket = S->next_ticket++;
@@ -601,6 +648,13 @@ int ktf_poll(ktf_ctx* c, uint64_t ticket, ktf_result_host* out) {
   out->t_submit = e->t_submit;
   out->t_admit = e->t_admit;
   out->t_done = e->t_done;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->pool.size() < kPoolEvents && e->held_bytes() <= kPoolEventBytes) {
+      S->pool.push_back(e);
+      e = nullptr;
+    }
+  }
   delete e;
   return rc ? fail(c, rc, "ktf_poll: event failed on the device") : KTF_OK;
 }
