@@ -583,8 +583,11 @@ constexpr int kRowChunks = 4;
 // seed phase: fit each seed over the seed layers with its own hits.  MAT:
 // the material of the layer being left goes onto a copy of the state, so
 // that a seed that cannot reach the next layer ends with its filtered state.
+// Held to two waves per SIMD (the double form with material needs more
+// registers than that allows without heavy spills, and runs at one).
 template <typename TS, typename TP, bool MAT>
-__global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAT && sizeof(TP) == 8 ? 1 : 2)))
+void build_seed_kernel(BuildArgs a) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = s < a.n_seeds;
   const int L = a.g.n_layers, NSL = a.g.n_seed_layers;
@@ -607,7 +610,29 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
     const TP k = (TP)(kCLight * (a.q[s] > 0 ? 1.0 : -1.0) * a.g.bz);
     const HitRes hr = hit_res(a);
     const TS* hits = static_cast<const TS*>(a.hits);
+    // a seed layer's hit is loaded while the layer before is fitted (the
+    // indices do not depend on the fit); an index outside the layer's hit
+    // list counts as no hit
+    auto load_hit = [&](int l, int32_t& h, double m[3]) {
+      const int g = e * L + l;
+      const int32_t h0 = a.seed_hit[l * a.sp + s];
+      const int64_t lo = a.hit_off[g];
+      h = (h0 >= 0 && h0 < a.hit_off[g + 1] - lo) ? h0 : -1;
+      m[0] = m[1] = m[2] = 0.0;
+      if (h >= 0) {
+        const int64_t hi = lo + h;
+        m[0] = (double)hits[hi];
+        m[1] = (double)hits[a.hp + hi];
+        m[2] = (double)hits[2 * a.hp + hi];
+      }
+    };
+    int32_t h_next;
+    double m_next[3];
+    load_hit(0, h_next, m_next);
     for (int l = 0; l < NSL; ++l) {
+      const int32_t h = h_next;
+      const double m[3] = {m_next[0], m_next[1], m_next[2]};
+      if (l + 1 < NSL) load_hit(l + 1, h_next, m_next);
       TrackState<TP> xp;
       Jac<TP> F;
       TP Pp[21];
@@ -631,17 +656,11 @@ __global__ __launch_bounds__(256) void build_seed_kernel(BuildArgs a) {
         cov_propagate(P, F, Pp);
       }
       reached = l + 1;
-      const int g = e * L + l;
-      const int32_t h0 = a.seed_hit[l * a.sp + s];
-      // an index outside the layer's hit list counts as no hit
-      const int32_t h = (h0 >= 0 && h0 < a.hit_off[g + 1] - a.hit_off[g]) ? h0 : -1;
       int32_t used = -1;
       x = xp;
 #pragma unroll
       for (int c = 0; c < 21; ++c) P[c] = Pp[c];
       if (h >= 0) {
-        const int64_t hi = a.hit_off[g] + h;
-        const double m[3] = {(double)hits[hi], (double)hits[a.hp + hi], (double)hits[2 * a.hp + hi]};
         Residual R;
         if (residual(x, P, m, hr, R)) {
           apply_update(x, P, R, x, P);  // in place
