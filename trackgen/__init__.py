@@ -416,7 +416,7 @@ def three_hit_seed(h1, h2, h3, q, bz, *, pt_cap=1000.0, f_par=0.3, f_perp=0.02,
 
 @dataclasses.dataclass
 class FitSet:
-    """Inputs of a batched fit plus the truth needed to judge it."""
+    """Inputs of a batched fit plus the truth needed to evaluate it."""
     det: Detector
     state: np.ndarray      # [6, n] seed state at layer 1
     cov: np.ndarray        # [21, n] packed seed covariance
