@@ -1205,62 +1205,59 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
 }
 
 // ------------------------------------------------------------------ final
-// One lane per seed.  LAZY: the survivors are the last layer's children,
-// not yet made; they are ranked from their records (the parent's hits plus
-// the one taken, the chi2 total) and only the chosen one is made.
-// Otherwise (no building layer) they are the stored seed fits.
-template <typename TS, typename TP, bool LAZY>
-__global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n_seeds) return;
+// The seed's final choice: the best survivor or the best ended candidate.
+// LAZY: the survivors are the last layer's children, not yet made, ranked
+// from their records (the parent's hits plus the one taken, the chi2
+// total); otherwise (no building layer) they are the stored seed fits.
+struct FinalChoice {
+  bool from_ended;
+  int end_layer, rank;
+  int64_t base;  // the seed's first survivor row
+};
+
+template <bool LAZY>
+__device__ __forceinline__ FinalChoice final_choice(const BuildArgs& a, int cur, int64_t s) {
   const int L = a.g.n_layers;
-  const int NC = a.g.max_cands;
   const int nalive = a.count[(int64_t)(L - 1) * a.sp + s];
-  const int64_t base = nalive > 0 ? a.cstart[cur][s] : 0;
+  FinalChoice f{false, L, -1, nalive > 0 ? (int64_t)a.cstart[cur][s] : 0};
   // The survivors are in rank order, and the rank order (more hits, then
   // lower chi2, then the pick order) is the final key among candidates that
   // all end on the last layer: the best survivor is the first.
-  const int best_r = nalive > 0 ? 0 : -1;
   int bnh = 0;
   double bc2 = 0.0;
   if (nalive > 0) {
+    f.rank = 0;
     if constexpr (LAZY) {
-      bnh = meta_nh(a.cmeta[cur ^ 1][a.sel_parent[base]]) + (a.sel_hit[base] >= 0 ? 1 : 0);
-      bc2 = a.sel_chi2[base];
+      bnh = meta_nh(a.cmeta[cur ^ 1][a.sel_parent[f.base]]) + (a.sel_hit[f.base] >= 0 ? 1 : 0);
+      bc2 = a.sel_chi2[f.base];
     } else {
-      bnh = meta_nh(a.cmeta[cur][base]);
-      bc2 = a.cchi2[cur][base];
+      bnh = meta_nh(a.cmeta[cur][f.base]);
+      bc2 = a.cchi2[cur][f.base];
     }
   }
   const int be = a.bend[s];
-  bool from_ended = false;
-  int end_layer = L, rank = best_r;
-  if (be >= 0 && (best_r < 0 || final_less(meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s], bnh,
-                                            bc2, L, best_r))) {
-    from_ended = true;
-    end_layer = be;
-    rank = a.brank[s];
+  if (be >= 0 && (f.rank < 0 || final_less(meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s], bnh, bc2, L,
+                                           f.rank))) {
+    f.from_ended = true;
+    f.end_layer = be;
+    f.rank = a.brank[s];
   }
-  TrackState<TP> x;
-  TP P[21];
-  uint32_t meta;
-  double c2;
-  if (from_ended) {
-    load_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
-    meta = a.bmeta[s];
-    c2 = a.bchi2[s];
-  } else if constexpr (LAZY) {
-    meta = make_child<TS, TP>(a, L - 1, cur ^ 1, base + rank, x, P);
-    c2 = a.sel_chi2[base + rank];
-  } else {
-    load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, base + rank, x, P);
-    meta = a.cmeta[cur][base + rank];
-    c2 = a.cchi2[cur][base + rank];
-  }
-  // walk the (parent, hit) records back from the end layer
-  for (int l = L - 1; l >= end_layer; --l) a.o_hit[(int64_t)l * a.sp + s] = -1;
-  int r = rank;
-  for (int l = end_layer - 1; l >= 0; --l) {
+  return f;
+}
+
+// One lane per seed: the chosen candidate's hits, walking the (parent, hit)
+// records back from its end layer.  A kernel of its own: the walk is a
+// chain of dependent loads, which wants many waves in flight, while making
+// the chosen child needs the registers of a Kalman update.
+template <bool LAZY>
+__global__ __launch_bounds__(256) void build_backtrack_kernel(BuildArgs a, int cur) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  const int L = a.g.n_layers, NC = a.g.max_cands;
+  const FinalChoice f = final_choice<LAZY>(a, cur, s);
+  for (int l = L - 1; l >= f.end_layer; --l) a.o_hit[(int64_t)l * a.sp + s] = -1;
+  int r = f.rank;
+  for (int l = f.end_layer - 1; l >= 0; --l) {
     if (r < 0 || r >= NC) {  // no record: nothing further back
       a.o_hit[(int64_t)l * a.sp + s] = -1;
       continue;
@@ -1268,6 +1265,33 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
     const int64_t hb = ((int64_t)l * NC + r) * 2 * a.sp;
     a.o_hit[(int64_t)l * a.sp + s] = a.hist[hb + a.sp + s];
     r = a.hist[hb + s];
+  }
+}
+
+// One lane per seed: the chosen candidate's state, covariance, chi2, hit
+// count and status (LAZY: the chosen child is made here, the only one of
+// the last layer's children that is).
+template <typename TS, typename TP, bool LAZY>
+__global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  const int L = a.g.n_layers;
+  const FinalChoice f = final_choice<LAZY>(a, cur, s);
+  TrackState<TP> x;
+  TP P[21];
+  uint32_t meta;
+  double c2;
+  if (f.from_ended) {
+    load_cand<TS, TP>(a.bpos, a.bmom, a.bcov, a.sp, s, x, P);
+    meta = a.bmeta[s];
+    c2 = a.bchi2[s];
+  } else if constexpr (LAZY) {
+    meta = make_child<TS, TP>(a, L - 1, cur ^ 1, f.base + f.rank, x, P);
+    c2 = a.sel_chi2[f.base + f.rank];
+  } else {
+    load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], a.S, f.base + f.rank, x, P);
+    meta = a.cmeta[cur][f.base + f.rank];
+    c2 = a.cchi2[cur][f.base + f.rank];
   }
   TS* so = static_cast<TS*>(a.o_state);
   TS* co = static_cast<TS*>(a.o_cov);
@@ -1368,10 +1392,13 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
     launch_merge<TS>(a, l, cur, st);
     cur ^= 1;
   }
-  if (a.g.n_layers > a.g.n_seed_layers)  // the last layer's children are made for the chosen one only
+  if (a.g.n_layers > a.g.n_seed_layers) {  // the last layer's children are made for the chosen one only
+    hipLaunchKernelGGL((build_backtrack_kernel<true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
     hipLaunchKernelGGL((build_final_kernel<TS, TP, true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
-  else
+  } else {
+    hipLaunchKernelGGL((build_backtrack_kernel<false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
     hipLaunchKernelGGL((build_final_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
+  }
   return hipGetLastError();
 }
 
