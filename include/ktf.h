@@ -186,6 +186,29 @@ int ktf_autotune_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, void 
  * at len - 1 characters; 4096 bytes hold every shape. */
 int ktf_tuned_shape(ktf_ctx *ctx, ktf_precision prec, int64_t n, char *buf, size_t len);
 
+/* Bytes of the device scratch array behind ktf_fit_noalloc (one copy per
+ * GPU, held until the process ends). */
+#define KTF_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* ktf_fit without any device allocation, for callers that cannot allocate
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same inputs, outputs, results and stream semantics as
+ * ktf_fit; the caller still owns every input and output buffer.  The modes
+ * that need scratch take it from a static device array of
+ * KTF_NOALLOC_SCRATCH_BYTES per GPU instead of the context's workspace:
+ * KTF_FIT_PERSISTENT its tile counter (256 bytes), KTF_FIT_SWEEP per track
+ * the end layer (1 byte) and, for KTF_FP32_BULK, the double position (24
+ * bytes), i.e. 256 + pitch rounded up to 256 + 24 * pitch bytes in all.
+ * KTF_FIT_AUTO, KTF_FIT_FUSED and the iterated refit need none.  Returns
+ * KTF_EINVAL for a sweep that does not fit the array (about 1.34 M tracks
+ * of float storage, 33 M of double), for KTF_FIT_SWEEP_GRAPH (building a
+ * graph allocates), or when the current device is not the context's.
+ * Every call on a GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap in time on one GPU race, so order them on one
+ * stream or synchronize between them. */
+int ktf_fit_noalloc(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, ktf_fit_mode mode,
+                    void *hip_stream);
+
 /* --------------------------------------------------------------- building
  * Combinatorial track building with the clone engine (Sec. 3, 3.1), for a
  * batch of independent events.  Per layer the hits are binned (n_zbins x

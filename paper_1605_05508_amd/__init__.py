@@ -27,7 +27,8 @@ MAX_LAYERS = 32
 
 EXPORTS = ["ktf_create", "ktf_destroy", "ktf_last_error", "ktf_fit", "ktf_autotune_fit",
            "ktf_tuned_shape", "ktf_build", "ktf_bin_hits", "ktf_submit", "ktf_poll", "ktf_now",
-           "ktf_serving_stats"]
+           "ktf_serving_stats", "ktf_fit_noalloc"]
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class KtfError(RuntimeError):
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.ktf_last_error.argtypes = [vp]
     lib.ktf_last_error.restype = C.c_char_p
     lib.ktf_fit.argtypes = [vp, C.POINTER(_FitIn), C.POINTER(_FitOut), C.c_int, vp]
+    lib.ktf_fit_noalloc.argtypes = [vp, C.POINTER(_FitIn), C.POINTER(_FitOut), C.c_int, vp]
     lib.ktf_autotune_fit.argtypes = [vp, C.POINTER(_FitIn), C.POINTER(_FitOut), vp]
     lib.ktf_tuned_shape.argtypes = [vp, C.c_int, C.c_int64, C.c_char_p, C.c_size_t]
     lib.ktf_build.argtypes = [vp, C.POINTER(_EventBatch), C.POINTER(_BuildOut), vp]
@@ -230,6 +232,17 @@ class Context:
         fin, fout = self._fit_structs(state, cov, q, hits, valid, out, prec, passes)
         self._check(self._lib.ktf_fit(self._h, C.byref(fin), C.byref(fout), MODES[mode],
                                       _stream_handle(stream)), "ktf_fit")
+        return out
+
+    def fit_noalloc(self, state, cov, q, hits, valid=None, *, out, mode="fused", stream=None, prec=None,
+                    passes=1):
+        """ktf_fit_noalloc: the fit with the library allocating no device memory
+        (scratch from its static per-GPU array).  The caller passes the outputs
+        (see alloc_fit_out); modes 'auto', 'fused', 'persistent', 'sweep'."""
+        self._validate_fit(state, cov, q, hits, valid)
+        fin, fout = self._fit_structs(state, cov, q, hits, valid, out, prec, passes)
+        self._check(self._lib.ktf_fit_noalloc(self._h, C.byref(fin), C.byref(fout), MODES[mode],
+                                              _stream_handle(stream)), "ktf_fit_noalloc")
         return out
 
     def autotune_fit(self, state, cov, q, hits, valid=None, *, out=None, stream=None, prec=None):

@@ -55,7 +55,7 @@ static int size_class(int64_t n) {
   return k;
 }
 
-static int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* out) {
+int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* out) {
   if (!c || !in || !out) return fail(c, KTF_EINVAL, "ktf_fit: null argument");
   if (in->n < 0 || in->pitch < in->n)
     return fail(c, KTF_EINVAL, "ktf_fit: n=%lld pitch=%lld", (long long)in->n, (long long)in->pitch);
@@ -73,6 +73,20 @@ static int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* o
 
 // blocks per CU for the persistent kernel, from the occupancy calculator
 int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves);
+
+// the launch shape the tuner chose for (prec, size class of n); false (and
+// the arguments unchanged) when none was tuned
+bool tuned_launch(ktf_ctx* c, ktf_precision prec, int64_t n, int& bs, int& waves, bool& persistent) {
+  auto it = c->tuned.find({(int)prec, size_class(n)});
+  if (it == c->tuned.end()) return false;
+  bs = it->second.block;
+  waves = it->second.waves;
+  persistent = it->second.persistent;
+  return true;
+}
+
+// device address of the allocation-free entry point's scratch (noalloc.hip)
+hipError_t noalloc_init(int device);
 
 static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode, int bs, int waves,
                    bool persistent, hipStream_t st) {
@@ -176,6 +190,7 @@ int ktf_create(const ktf_config* cfg, ktf_ctx** out) {
     c->gcn_arch = prop.gcnArchName;
     e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
   }
+  if (e == hipSuccess) e = noalloc_init(c->device);
   if (e != hipSuccess) {
     delete c;
     return KTF_EDEVICE;
@@ -218,15 +233,7 @@ int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mod
   int bs = 256, waves = 1;
   bool persistent = false;
   switch (mode) {
-    case KTF_FIT_AUTO: {
-      auto it = c->tuned.find({(int)in->prec, size_class(in->n)});
-      if (it != c->tuned.end()) {
-        bs = it->second.block;
-        waves = it->second.waves;
-        persistent = it->second.persistent;
-      }
-      break;
-    }
+    case KTF_FIT_AUTO: (void)tuned_launch(c, in->prec, in->n, bs, waves, persistent); break;
     case KTF_FIT_FUSED: break;
     case KTF_FIT_PERSISTENT: persistent = true; break;
     case KTF_FIT_SWEEP:
