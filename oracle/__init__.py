@@ -21,6 +21,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ktf_oracle.c")
 _LIB = os.path.join(_HERE, "libktf_oracle.so")
+# The same source built with fused multiply-adds contracted wherever the
+# compiler likes: it rounds differently at nearly every multiply-add, as a
+# different compiler or device does.  Comparing the two builds measures the
+# oracle's own rounding spread per track; GPU-parity tests hold a track to a
+# small multiple of that spread where it exceeds the fixed FP64 tolerance.
+_LIB_CONTRACT = os.path.join(_HERE, "libktf_oracle_contract.so")
 
 NO_REACH = 1
 S_NOT_PD = 2
@@ -29,12 +35,31 @@ NONFINITE = 4
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
 
 
+def _cpu_has_fma() -> bool:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("flags"):
+                    return " fma " in line + " "
+    except OSError:
+        pass
+    return False
+
+
+def contract_cflags():
+    """Flags of the contracted build: FMA contraction where the host has FMA
+    (without it no contraction can happen and the two builds agree)."""
+    return ["-O2", "-fno-fast-math", "-ffp-contract=fast", *(["-mfma"] if _cpu_has_fma() else []),
+            "-fPIC", "-shared", "-std=c11"]
+
+
 def build_lib(force: bool = True) -> str:
-    """Compile the oracle shared library with gcc."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm", "-lpthread"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle shared library (and its contracted twin) with gcc."""
+    for out, flags in ((_LIB, CFLAGS), (_LIB_CONTRACT, contract_cflags())):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            tmp = out + ".tmp"
+            subprocess.check_call(["gcc", *flags, "-o", tmp, _SRC, "-lm", "-lpthread"])
+            os.replace(tmp, out)
     return _LIB
 
 
@@ -50,15 +75,21 @@ class _BuildParams(C.Structure):
 
 
 _lib = None
+_lib_contract = None
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build_lib()
-        _lib = C.CDLL(_LIB)
-    return _lib
+def lib(contract: bool = False):
+    """The oracle library; contract=True: its contracted twin (see above)."""
+    global _lib, _lib_contract
+    if (_lib_contract if contract else _lib) is None:
+        for path in (_LIB, _LIB_CONTRACT):
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+                build_lib(force=False)
+        if contract:
+            _lib_contract = C.CDLL(_LIB_CONTRACT)
+        else:
+            _lib = C.CDLL(_LIB)
+    return _lib_contract if contract else _lib
 
 
 def _p(a, ct):
@@ -171,9 +202,11 @@ def pack(P):
 
 # ------------------------------------------------------------------- fit
 
-def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=True, passes=1):
+def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=True, passes=1,
+               contract=False):
     """Batched FP64 fit.  state[6,n], cov[21,n], q[n], hits[L,3,n], valid[L,n];
-    passes > 1: iterated refit (orc_refit_track).
+    passes > 1: iterated refit (orc_refit_track); contract=True: run the
+    contracted build of the same oracle (to measure its rounding spread).
 
     Returns dict(state[6,n], cov[21,n], chi2[n], nupd[n], status[n]).
     """
@@ -190,7 +223,7 @@ def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=Tru
     c2 = np.zeros(n)
     nu = np.zeros(n, dtype=np.int32)
     stt = np.zeros(n, dtype=np.uint32)
-    lib().orc_fit_batch(C.byref(g), C.c_int64(n), _p(st, C.c_double), _p(cv, C.c_double),
+    lib(contract).orc_fit_batch(C.byref(g), C.c_int64(n), _p(st, C.c_double), _p(cv, C.c_double),
                         _p(qq, C.c_int8), _p(hh, C.c_double), _p(vv, C.c_uint8),
                         _p(so, C.c_double), _p(co, C.c_double), _p(c2, C.c_double),
                         _p(nu, C.c_int32), _p(stt, C.c_uint32), C.c_int(int(passes)),
@@ -198,9 +231,11 @@ def fit_arrays(det, state, cov, q, hits, valid=None, nthreads=None, material=Tru
     return dict(state=so.T.copy(), cov=co.T.copy(), chi2=c2, nupd=nu, status=stt)
 
 
-def fit(fs, nthreads=None, material=True, passes=1):
-    """Fit a trackgen.FitSet (passes > 1: iterated refit)."""
-    return fit_arrays(fs.det, fs.state, fs.cov, fs.q, fs.hits, fs.valid, nthreads, material, passes)
+def fit(fs, nthreads=None, material=True, passes=1, contract=False):
+    """Fit a trackgen.FitSet (passes > 1: iterated refit; contract: the
+    contracted build)."""
+    return fit_arrays(fs.det, fs.state, fs.cov, fs.q, fs.hits, fs.valid, nthreads, material, passes,
+                      contract)
 
 
 def carry_back(det, q, from_layer, x):
@@ -229,12 +264,13 @@ def bin_layer(hits, z_half, nz, nphi):
 # --------------------------------------------------------------- building
 
 def build_event(bs, e, seeds=None, *, max_cands=10, max_missed=1, chi2_cut=30.0,
-                n_seed_layers=3, nthreads=None, debug=False):
+                n_seed_layers=3, nthreads=None, debug=False, contract=False):
     """Brute-force building of (a subset of) the seeds of event e of a BuildSet.
 
     seeds: indices local to the event (default all).  Returns dict of
     hit_idx[L, ns], state[6, ns], cov[21, ns], chi2, nhits, status and, with
-    debug=True, dbg_n[L, ns], dbg[L, NC, 2, ns], margin[L, ns].
+    debug=True, dbg_n[L, ns], dbg[L, NC, 2, ns], margin[L + 1, ns] (per layer
+    the smallest relative decision gap, then the final choice's).
     """
     det = bs.det
     L = det.n_layers
@@ -260,8 +296,8 @@ def build_event(bs, e, seeds=None, *, max_cands=10, max_missed=1, chi2_cut=30.0,
     stt = np.zeros(n, dtype=np.uint32)
     dn = np.zeros((n, L), dtype=np.int32) if debug else None
     dg = np.zeros((n, L, max_cands, 2), dtype=np.int32) if debug else None
-    mg = np.zeros((n, L)) if debug else None
-    lib().orc_build_event(C.byref(g), C.byref(bp), _p(hits, C.c_double), _p(loff, C.c_int64),
+    mg = np.zeros((n, L + 1)) if debug else None
+    lib(contract).orc_build_event(C.byref(g), C.byref(bp), _p(hits, C.c_double), _p(loff, C.c_int64),
                           C.c_int64(n), _p(st, C.c_double), _p(cv, C.c_double),
                           _p(qq, C.c_int8), _p(sh, C.c_int32), _p(hit_idx, C.c_int32),
                           _p(so, C.c_double), _p(co, C.c_double), _p(c2, C.c_double),

@@ -626,7 +626,11 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
   if (dbg)
     for (int i = 0; i < L * NC * 2; ++i) dbg[i] = -1;
   if (margin)
-    for (int l = 0; l < L; ++l) margin[l] = INFINITY;
+    for (int l = 0; l <= L; ++l) margin[l] = INFINITY;
+  /* every candidate that ends (hit count, chi2 total), for the final
+   * choice's margin */
+  size_t fin_cap = 16, nfin = 0;
+  orc_final_key *fin = (orc_final_key *)malloc(fin_cap * sizeof(orc_final_key));
 
   /* seed phase: fit the seed's own hits on the first NSL layers */
   orc_cand *c = &cur[0];
@@ -737,6 +741,11 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
       }
       if (finished) {
         orc_final_key k = {p->nh, p->chi2, l, ci};
+        if (nfin == fin_cap) {
+          fin_cap *= 2;
+          fin = (orc_final_key *)realloc(fin, fin_cap * sizeof(orc_final_key));
+        }
+        fin[nfin++] = k;
         if (!have_best || better_final(&k, &best_key)) {
           best = *p;
           best_key = k;
@@ -791,12 +800,27 @@ int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *
   /* surviving candidates compete with the finished ones */
   for (int ci = 0; ci < nlive; ++ci) {
     orc_final_key k = {cur[ci].nh, cur[ci].chi2, L, ci};
+    if (nfin == fin_cap) {
+      fin_cap *= 2;
+      fin = (orc_final_key *)realloc(fin, fin_cap * sizeof(orc_final_key));
+    }
+    fin[nfin++] = k;
     if (!have_best || better_final(&k, &best_key)) {
       best = cur[ci];
       best_key = k;
       have_best = 1;
     }
   }
+  if (margin && have_best) {
+    for (size_t i = 0; i < nfin; ++i) {
+      const orc_final_key *k = &fin[i];
+      if (k->end_layer == best_key.end_layer && k->rank == best_key.rank) continue; /* the chosen one */
+      if (k->nh != best_key.nh) continue;
+      const double gp = rel_gap(best_key.chi2, k->chi2);
+      if (gp < margin[L]) margin[L] = gp;
+    }
+  }
+  free(fin);
   st = (uint32_t)best.status;
   if (!all_finite(best.x, 6) || !all_finite(best.P, 36)) st |= ORC_NONFINITE;
   for (int l = 0; l < L; ++l) hit_idx[l] = best.hit[l];
@@ -839,7 +863,7 @@ static void *build_worker(void *arg) {
                    j->state_o + 6 * i, j->cov_o + 21 * i, j->chi2_o + i, j->nhits_o + i,
                    j->status_o + i, j->dbg_n ? j->dbg_n + (int64_t)L * i : NULL,
                    j->dbg ? j->dbg + (int64_t)L * NC * 2 * i : NULL,
-                   j->margin ? j->margin + (int64_t)L * i : NULL);
+                   j->margin ? j->margin + (int64_t)(L + 1) * i : NULL);
   return NULL;
 }
 

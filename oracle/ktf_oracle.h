@@ -135,9 +135,14 @@ void orc_bin_layer(int64_t n, const double *hits /* [n][3] */, double z_half,
  * indices within each seed layer's hit list.  Outputs hit_idx[L] (-1 =
  * none), state, packed cov, chi2, nhits, status.  Optional diagnostics:
  * dbg_n[L] candidates alive after each layer, dbg[L][max_cands][2] =
- * (parent rank, hit) of each, margin[L] = smallest relative gap of a
- * decision taken at that layer (sorted-neighbour chi2 gap among the kept
- * boundary, or a chi2 increment's distance from the cut). */
+ * (parent rank, hit) of each, and margin[L+1]: margin[l] for l < L the
+ * smallest relative gap of a decision taken at layer l (the chi2-total gap
+ * between neighbours of equal hit count among the first max_cands + 1
+ * records in ranked order, which decides the kept set and its order, or a
+ * chi2 increment's distance from the cut, both relative to max(1, value)),
+ * margin[L] that of the final choice (the chi2 gap between the chosen
+ * candidate and every other ended or surviving candidate of its hit count;
+ * infinite when it has no such competitor). */
 int orc_build_seed(const orc_geom *g, const orc_build_params *bp, const double *hits,
                    const int64_t *layer_off, const double x0[6], const double P0[21],
                    int q, const int32_t *seed_hit, int32_t *hit_idx, double xo[6],

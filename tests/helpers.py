@@ -38,46 +38,87 @@ def sigma_diag(cov):
 
 def diverged(r):
     """Fits the linearised filter lost: a status bit, or chi2/ndf >= 50 with
-    the diffuse-prior ndf 2 n - 5.  Their outputs amplify rounding without
-    bound (chaotic), so parity for them is agreement of the divergence."""
+    the diffuse-prior ndf 2 n - 5."""
     ndf = np.maximum(1, 2 * r["nupd"] - 5)
     return (r["status"] != 0) | (r["chi2"] / ndf >= 50)
 
 
-def fp64_close(g, o, tol=1e-10, check_diverged=True, poor_tol=1e-6):
-    """Per component |a-b| <= tol (|b| + sigma_i); cov |dP_ij| <= tol sqrt(P_ii P_jj)
-    (+ a floor for entries that vanish); chi2 relative.  Diverged fits of the
-    oracle must be diverged on the GPU too and are not compared value by value.
-    Poorly fitted tracks (chi2/(2n-5) >= 5 on the oracle) stretch the
-    linearisation and amplify rounding (measured up to ~5e-8 relative): they
-    are held to poor_tol, with status and hit count exact."""
-    bad = diverged(o)
-    if check_diverged and bad.any():
-        gd = (g["status"] != 0) | (g["chi2"] / np.maximum(1, 2 * g["nupd"] - 5) >= 10)
-        assert np.all(gd[bad]), np.nonzero(bad & ~gd)
-        keep = ~bad
-        g = {k: v[..., keep] for k, v in g.items()}
-        o = {k: v[..., keep] for k, v in o.items()}
-    poor = o["chi2"] / np.maximum(1, 2 * o["nupd"] - 5) >= 5
-    if poor.any() and poor_tol > tol:
-        fp64_close({k: v[..., poor] for k, v in g.items()}, {k: v[..., poor] for k, v in o.items()},
-                   poor_tol, False, poor_tol)
-        g = {k: v[..., ~poor] for k, v in g.items()}
-        o = {k: v[..., ~poor] for k, v in o.items()}
-    sig = sigma_diag(o["cov"])
-    ds = np.abs(g["state"] - o["state"])
-    assert np.all(ds <= tol * (np.abs(o["state"]) + sig)), ds.max()
-    diag = [0, 6, 11, 15, 18, 20]
-    k = 0
-    for i in range(6):
-        for j in range(i, 6):
-            scale = np.sqrt(np.abs(o["cov"][diag[i]] * o["cov"][diag[j]]))
-            d = np.abs(g["cov"][k] - o["cov"][k])
-            assert np.all(d <= tol * scale + 1e-300), (i, j, (d / scale).max())
-            k += 1
-    assert np.all(np.abs(g["chi2"] - o["chi2"]) <= tol * np.maximum(1.0, np.abs(o["chi2"])))
-    assert np.array_equal(g["nupd"], o["nupd"])
-    assert np.array_equal(g["status"].astype(np.uint32), o["status"])
+_DIAG = [0, 6, 11, 15, 18, 20]
+
+
+def norm_dev(a, o):
+    """Per track, the largest normalized difference of a from o: state
+    components |a-b| / (|b| + sigma_i), covariance |dP_ij| / sqrt(P_ii P_jj),
+    chi2 |a-b| / max(1, |b|).  Entries non-finite in o count where a's
+    finiteness differs (inf), else not at all."""
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        sig = sigma_diag(o["cov"])
+        parts = [np.abs(a["state"] - o["state"]) / (np.abs(o["state"]) + sig)]
+        k = 0
+        rows = []
+        for i in range(6):
+            for j in range(i, 6):
+                scale = np.sqrt(np.abs(o["cov"][_DIAG[i]] * o["cov"][_DIAG[j]]))
+                rows.append(np.abs(a["cov"][k] - o["cov"][k]) / scale)
+                k += 1
+        parts.append(np.stack(rows))
+        parts.append((np.abs(a["chi2"] - o["chi2"]) / np.maximum(1.0, np.abs(o["chi2"])))[None])
+        d = np.concatenate(parts, axis=0)
+        fin_o = np.concatenate([np.isfinite(o["state"]), np.isfinite(o["cov"]), np.isfinite(o["chi2"])[None]])
+        fin_a = np.concatenate([np.isfinite(a["state"]), np.isfinite(a["cov"]), np.isfinite(a["chi2"])[None]])
+        d = np.where(fin_o & fin_a, np.nan_to_num(d, nan=0.0, posinf=0.0), 0.0)
+        d = np.where(fin_o != fin_a, np.inf, d)
+    return d.max(axis=0)
+
+
+def perturb_ulp(fs, seed):
+    """The fit set with every seed and hit value moved by one ulp up or down
+    (a fixed random pattern per seed)."""
+    rng = np.random.default_rng(seed)
+    f = lambda a: a * (1 + rng.choice([-1.0, 1.0], a.shape) * 2.0 ** -52)
+    return tg.FitSet(fs.det, f(fs.state), f(fs.cov), fs.q, f(fs.hits), fs.valid, fs.truth_pos,
+                     fs.truth_mom)
+
+
+def spread_of(o, alts):
+    """Per track, the largest norm_dev from the oracle's result o of other
+    results of the same oracle that differ from it only by rounding; they
+    must agree with it on status and hit counts."""
+    for a in alts:
+        assert np.array_equal(a["status"], o["status"]) and np.array_equal(a["nupd"], o["nupd"])
+    return np.max(np.stack([norm_dev(a, o) for a in alts]), axis=0)
+
+
+def oracle_with_spread(orc, fs, n_perturb=4, **kw):
+    """The oracle's fit of fs and its own rounding spread per track: the
+    largest deviation from that fit of the contracted build of the same
+    oracle and of fits of inputs perturbed by one ulp (fixed seeds)."""
+    o = orc.fit(fs, **kw)
+    alts = [orc.fit(fs, contract=True, **kw)]
+    alts += [orc.fit(perturb_ulp(fs, 100 + s), **kw) for s in range(n_perturb)]
+    return o, spread_of(o, alts)
+
+
+def fp64_close(g, o, spread=None, tol=1e-10, k_spread=10.0):
+    """FP64 parity of every track: status and hit counts exact, values within
+    tol by norm_dev.  spread: the oracle's own rounding spread per track
+    (oracle_with_spread); a track whose spread exceeds tol / k_spread --
+    large where the linearisation is stretched (refits, heavy energy loss,
+    fits the filter lost) -- is held to k_spread times its spread."""
+    assert np.array_equal(g["status"].astype(np.uint32), o["status"].astype(np.uint32)), \
+        np.nonzero(g["status"].astype(np.uint32) != o["status"].astype(np.uint32))
+    assert np.array_equal(g["nupd"], o["nupd"]), np.nonzero(g["nupd"] != o["nupd"])
+    t = np.full(o["chi2"].shape, tol)
+    if spread is not None:
+        t = np.maximum(t, k_spread * spread)
+    # a fit that stopped on a non-finite state or covariance (the same bit on
+    # both sides, checked above) has no meaningful values: the oracle's full
+    # 6x6 products turn a 0 * inf into NaN where the kernels' structured
+    # products never form it
+    t = np.where(o["status"].astype(np.uint32) & 4, np.inf, t)
+    d = norm_dev(g, o)
+    bad = np.nonzero(~(d <= t))[0]
+    assert bad.size == 0, (bad[:10], d[bad[:10]], t[bad[:10]])
 
 
 def fp32_errors(g, o, radius):
@@ -142,10 +183,13 @@ def build_inputs(bs, prec, seed_pad=0, hit_pad=0):
 def certified(o_dbg_n, o_dbg, o_margin, g_count, g_hist, tau):
     """Adjudication of a building mismatch of one seed: find the first layer
     whose kept (parent, hit) list differs; the mismatch is certified when
-    the oracle's smallest decision gap at that layer is within tau."""
+    the oracle's smallest decision gap at that layer is within tau.  When
+    every layer's list agrees, the difference is the final choice's, judged
+    by the oracle's final margin (o_margin[L]).  Returns (certified, layer;
+    L for the final choice)."""
     L = o_dbg_n.shape[0]
     for l in range(L):
         n = o_dbg_n[l]
         if g_count[l] != n or not np.array_equal(g_hist[l, :n], o_dbg[l, :n]):
             return bool(o_margin[l] <= tau), l
-    return True, -1
+    return bool(o_margin[L] <= tau), L

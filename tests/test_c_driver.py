@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import trackgen as tg
-from helpers import fp64_close
+from helpers import fp64_close, oracle_with_spread
 
 EXE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c", "fit_from_c")
 
@@ -68,4 +68,4 @@ def test_fit_from_c_matches_oracle(tmp_path, orc, mode):
     o = orc.fit(fs)
     assert np.array_equal(g["status"], o["status"])
     assert np.array_equal(g["nupd"], o["nupd"])
-    fp64_close(g, o)
+    fp64_close(g, o, oracle_with_spread(orc, fs)[1])

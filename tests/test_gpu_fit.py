@@ -2,11 +2,15 @@
 
 The fit is the Kalman filter of Sec. 2 run over each track's layers.  FP64
 path: every output within 1e-10 of the oracle (relative to the value plus
-its own uncertainty); float paths: position error / r and momentum error
+its own uncertainty), or within ten times the oracle's own rounding spread
+where that is larger; float paths: position error / r and momentum error
 / |p| against the FP64 oracle, and pull widths within 1% of the oracle's.
-FP32 bulk (covariance in float) meets 1e-4 at the 99.9th percentile; its
-tail is the float covariance's, so FP32_PROP (float state propagation,
-double covariance) is held to 1e-4 on every track.
+The float path of the headline, FP32_PROP (float storage and state
+propagation, the covariance in double), is held to 1e-4 on every track.
+FP32 bulk (the covariance rounded to float between layers) meets 1e-4 at
+the 99.9th percentile; its tail, up to ~2e-4 on 1e6 tracks at high pT
+where the momentum is known to tens of percent, is the float covariance's
+and is held to the measured bound.
 """
 import json
 
@@ -14,7 +18,8 @@ import numpy as np
 import pytest
 
 import trackgen as tg
-from helpers import fit_inputs, fp32_errors, fp64_close, host, pad_pitch, param_rel_errors, pulls
+from helpers import (fit_inputs, fp32_errors, fp64_close, host, oracle_with_spread, pad_pitch, param_rel_errors,
+                     pulls)
 
 pytestmark = pytest.mark.gpu
 
@@ -35,16 +40,16 @@ def ctx10(k):
 @pytest.fixture(scope="module")
 def c1(orc):
     fs = tg.config1()
-    return fs, orc.fit(fs)
+    return (fs,) + oracle_with_spread(orc, fs)
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_fp64_config1_matches_oracle(ctx10, c1, mode):
-    fs, o = c1
+    fs, o, oc = c1
     d = fit_inputs(fs, "fp64")
     out = ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode)
     g = host(out, fs.n)
-    fp64_close(g, o)
+    fp64_close(g, o, oc)
 
 
 def test_fp64_ragged_and_missing_layers(ctx10, orc):
@@ -56,11 +61,11 @@ def test_fp64_ragged_and_missing_layers(ctx10, orc):
     v[rng.random(v.shape) < 0.15] = 0
     v[0] = 1
     fs.valid = v
-    o = orc.fit(fs)
+    o, oc = oracle_with_spread(orc, fs)
     d = fit_inputs(fs, "fp64", pitch=pad_pitch(fs.n) + 128)
     for mode in MODES:
         out = ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode)
-        fp64_close(host(out, fs.n), o)
+        fp64_close(host(out, fs.n), o, oc)
 
 
 def test_modes_agree(ctx10):
@@ -96,6 +101,12 @@ def test_modes_agree(ctx10):
         assert np.array_equal(f[key], p[key]) and np.array_equal(f[key], f2[key]), ("fp32p", key)
 
 
+# FP32 bulk's documented tail: on 1e6 tracks the largest momentum error is
+# 1.3e-4 of |p| and the largest parameter error 1.9e-4 of |x| + sigma, both
+# at pT > 10 GeV (about 1e-3 sigma there)
+FP32B_TAIL = 2.5e-4
+
+
 def test_fp32_bulk_accuracy_and_pulls(ctx10, orc):
     fs = tg.config2(n=200_000)
     o = orc.fit(fs)
@@ -105,8 +116,8 @@ def test_fp32_bulk_accuracy_and_pulls(ctx10, orc):
     e_pos, e_mom = fp32_errors(g, o, 40.0)
     assert e_pos.max() < 1e-6
     assert np.quantile(e_mom, 0.999) < 1e-4
-    assert e_mom.max() < 5e-4
-    assert np.quantile(param_rel_errors(g, o), 0.999) < 1e-4
+    assert e_mom.max() < FP32B_TAIL
+    assert np.quantile(param_rel_errors(g, o), 0.999) < 1e-4 and param_rel_errors(g, o).max() < FP32B_TAIL
     assert np.abs(g["chi2"] - o["chi2"]).max() / max(1, o["chi2"].max()) < 1e-2
     pg = pulls(g["state"], g["cov"], fs.truth_pos[-1], fs.truth_mom[-1])
     po = pulls(o["state"], o["cov"], fs.truth_pos[-1], fs.truth_mom[-1])
@@ -158,10 +169,10 @@ def test_full_size_sampled(ctx10, orc):
         o = orc.fit(sub)
         gs = {key: v[..., idx] for key, v in g.items()}
         if prec == "fp64":
-            fp64_close(gs, o)
+            fp64_close(gs, o, oracle_with_spread(orc, sub)[1])
         else:
             e_pos, e_mom = fp32_errors(gs, o, 40.0)
-            assert e_mom.max() < (5e-4 if prec == "fp32b" else 1e-4) and e_pos.max() < 1e-6
+            assert e_mom.max() < (FP32B_TAIL if prec == "fp32b" else 1e-4) and e_pos.max() < 1e-6
             if prec == "fp32p":
                 assert param_rel_errors(gs, o).max() < 1e-4
         assert np.all(g["status"] == 0)
@@ -173,7 +184,10 @@ def test_status_flags(ctx10, orc):
     prior, no hits in between so nothing corrects the momentum): NO_REACH,
     with the last state kept.  Tracks 20..24 carry a NaN hit on layer 5: the
     residual covariance is not positive definite there, the hit is skipped
-    (S_NOT_PD) and the fit goes on."""
+    (S_NOT_PD) and the fit goes on.  Tracks 30..34 have no hit on the first
+    layer and a seed covariance with an infinite pz variance (a prior with
+    no information on pz): the propagated covariance is not finite before
+    any S is formed, so the fit stops there with NONFINITE alone."""
     rng = np.random.default_rng(33)
     fs = tg.make_fit_set(rng, 256, tg.barrel(10))
     st = fs.state.copy()
@@ -188,9 +202,12 @@ def test_status_flags(ctx10, orc):
     valid[1:9, :10] = 0
     hits = fs.hits.copy()
     hits[5, 0, 20:25] = np.nan
+    cov[20, 30:35] = np.inf
+    valid[0, 30:35] = 0
     fs2 = tg.FitSet(fs.det, st, cov, fs.q, hits, valid, fs.truth_pos, fs.truth_mom)
-    o = orc.fit(fs2)
+    o, oc = oracle_with_spread(orc, fs2)
     assert np.all(o["status"][:10] == orc.NO_REACH) and np.all(o["status"][20:25] == orc.S_NOT_PD)
+    assert np.all(o["status"][30:35] == orc.NONFINITE) and np.all(o["nupd"][30:35] == 0)
     for prec in ("fp64", "fp32b", "fp32p"):
         d = fit_inputs(fs2, "fp32b" if prec == "fp32p" else prec)
         for mode in (MODES if prec != "fp32p" else ["fused", "persistent"]):
@@ -199,7 +216,7 @@ def test_status_flags(ctx10, orc):
             assert np.array_equal(g["status"].astype(np.uint32), o["status"]), (prec, mode)
             assert np.array_equal(g["nupd"], o["nupd"]), (prec, mode)
         if prec == "fp64":
-            fp64_close(g, o, check_diverged=False)
+            fp64_close(g, o, oc)
 
 
 def test_empty_and_single(ctx10, orc):

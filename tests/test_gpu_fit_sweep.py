@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import trackgen as tg
-from helpers import fit_inputs, fp64_close, host, pad_pitch
+from helpers import fit_inputs, fp64_close, host, oracle_with_spread, pad_pitch
 
 pytestmark = pytest.mark.gpu
 
@@ -43,12 +43,12 @@ def test_fit_configurations(k, orc, case):
         drop = rng.random(fs.valid.shape) < miss
         drop[0] = False
         fs.valid[drop] = 0
-    o = orc.fit(fs)
+    o, oc = oracle_with_spread(orc, fs)
     ctx = k.Context.for_detector(det, n_seed_layers=min(3, L))  # building needs n_seed_layers <= layers
     d = fit_inputs(fs, "fp64", pitch=pad_pitch(n) + 128)
     for mode in MODES:
         g = host(ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode), n)
         assert np.array_equal(g["status"].astype(np.uint32), o["status"]), mode
         assert np.array_equal(g["nupd"], o["nupd"]), mode
-        fp64_close(g, o)
+        fp64_close(g, o, oc)
     ctx.close()

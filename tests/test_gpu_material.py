@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import trackgen as tg
-from helpers import build_inputs, certified, fit_inputs, fp32_errors, fp64_close, host, pad_pitch, pulls
+from helpers import (build_inputs, certified, fit_inputs, fp32_errors, fp64_close, host, oracle_with_spread,
+                     pad_pitch, pulls)
 
 pytestmark = pytest.mark.gpu
 
@@ -35,12 +36,12 @@ def test_fp64_fit_through_material(k, orc):
     """Several tiles and a ragged tail, missing layers, every launch mode."""
     det = tg.barrel(10, x0=0.02, eloss=0.036)
     fs = simulated(det, 3000 + 37, (0.5, 10.0), 41, missing=0.1)
-    o = orc.fit(fs)
+    o, oc = oracle_with_spread(orc, fs)
     ctx = k.Context.for_detector(det)
     d = fit_inputs(fs, "fp64", pitch=pad_pitch(fs.n) + 64)
     for mode in MODES:
         g = host(ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode), fs.n)
-        fp64_close(g, o)
+        fp64_close(g, o, oc)
 
 
 def test_fp64_fit_energy_loss_stops_tracks(k, orc):
@@ -50,20 +51,17 @@ def test_fp64_fit_energy_loss_stops_tracks(k, orc):
     last filtered state."""
     det = tg.barrel(10, x0=0.05, eloss=0.4)
     fs = simulated(det, 2000, (0.15, 0.6), 42)
-    o = orc.fit(fs)
+    o, oc = oracle_with_spread(orc, fs)
     assert 0.01 < np.mean(o["status"] == orc.NO_REACH) < 0.9
     ctx = k.Context.for_detector(det)
     d = fit_inputs(fs, "fp64")
     # at these momenta the energy loss per layer is several percent and the
     # linearised filter is far from linear (chi2/ndf up to ~40 for some
-    # tracks): rounding differences grow to ~1e-9, so values are held to
-    # 1e-7 here (the moderate-material test holds 1e-10); status and layer
-    # counts agree exactly
+    # tracks): the oracle's own rounding spread grows to ~5e-9 on such
+    # tracks, which then hold to ten times their spread
     for mode in MODES:
         g = host(ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode), fs.n)
-        assert np.array_equal(g["status"].astype(np.uint32), o["status"]), mode
-        assert np.array_equal(g["nupd"], o["nupd"]), mode
-        fp64_close(g, o, tol=1e-7, check_diverged=False)
+        fp64_close(g, o, oc)
 
 
 def test_float_fits_through_material(k, orc):
@@ -79,7 +77,10 @@ def test_float_fits_through_material(k, orc):
         assert np.array_equal(g["nupd"], o["nupd"])
         e_pos, e_mom = fp32_errors(g, o, 40.0)
         assert e_pos.max() < 1e-6
-        assert np.quantile(e_mom, 0.999) < 1e-4 and e_mom.max() < (5e-4 if prec == "fp32b" else 1e-4)
+        # FP32 bulk's float covariance leaves a tail above 1e-4 (measured
+        # below 2.5e-4); FP32_PROP, the headline float path, holds 1e-4 on
+        # every track
+        assert np.quantile(e_mom, 0.999) < 1e-4 and e_mom.max() < (2.5e-4 if prec == "fp32b" else 1e-4)
         pg = pulls(g["state"], g["cov"], fs.truth_pos[-1], fs.truth_mom[-1])
         for name in pg:
             rg, ro = np.sqrt(np.mean(pg[name] ** 2)), np.sqrt(np.mean(po[name] ** 2))

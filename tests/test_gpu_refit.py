@@ -2,14 +2,16 @@
 
 Each pass restarts from the previous result carried back through every
 layer and re-linearises around it, so rounding differences feed from pass
-to pass: FP64 values are held to 1e-8 here (measured: states within ~3e-11,
-covariances within ~1.2e-9 on well-fitted tracks after three passes),
-poorly fitted tracks to 1e-6, status and hit counts exactly."""
+to pass, and the oracle's own rounding spread (its contracted build and
+one-ulp input perturbations against its plain fit) reaches ~6e-10 on
+well-fitted and ~8e-7 on poorly fitted tracks after three passes: FP64
+values are held to 1e-10, or to ten times that measured spread where it is
+larger, status and hit counts exactly."""
 import numpy as np
 import pytest
 
 import trackgen as tg
-from helpers import diverged, fit_inputs, fp32_errors, fp64_close, host
+from helpers import diverged, fit_inputs, fp32_errors, fp64_close, host, oracle_with_spread
 
 pytestmark = pytest.mark.gpu
 
@@ -25,21 +27,21 @@ def test_fp64_refit_three_hit_seeds(k, orc):
     ctx = k.Context(fs.det.radii)
     d = fit_inputs(fs, "fp64")
     for passes in (2, 3):
-        o = orc.fit(fs, passes=passes)
+        o, oc = oracle_with_spread(orc, fs, passes=passes)
         for mode in ("fused", "persistent"):
             g = host(ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode, passes=passes), fs.n)
-            fp64_close(g, o, tol=1e-8)
+            fp64_close(g, o, oc)
 
 
 def test_fp64_refit_through_material(k, orc):
     det = tg.barrel(10, x0=0.02, eloss=0.036)
     rng = np.random.default_rng(51)
     fs = tg.make_fit_set(rng, 2000, det, seed_mode="3hit")
-    o = orc.fit(fs, passes=3)
+    o, oc = oracle_with_spread(orc, fs, passes=3)
     ctx = k.Context.for_detector(det)
     d = fit_inputs(fs, "fp64")
     g = host(ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="fused", passes=3), fs.n)
-    fp64_close(g, o, tol=1e-8)
+    fp64_close(g, o, oc)
 
 
 def test_float_refit(k, orc):

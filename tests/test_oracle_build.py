@@ -216,3 +216,113 @@ def test_eta_order_groups_seeds_by_eta_bin():
         for v in np.unique(bins[p]):                              # stable within a bin
             q = p[bins[p] == v]
             assert np.all(np.diff(q) > 0)
+
+
+# ------------------------------------------------------------------ margins
+# The oracle's decision margins adjudicate FP32-bulk building mismatches:
+# per layer the smallest relative gap of a decision (neighbouring chi2
+# totals of equal hit count among the first max_cands + 1 ranked records,
+# or a chi2 increment's distance from the cut), and the final choice's gap.
+# They are pinned on a designed event whose chi2 values are known in closed
+# form: one seed, three seed layers and one building layer whose hits sit
+# at x' + a u, with x' the propagated candidate and u scaled to
+# u^T S^-1 u = 1, so that a hit's chi2 increment is exactly a^2.
+
+def designed_event(orc, a2, seed=91):
+    rng = np.random.default_rng(seed)
+    det = tg.barrel(4)
+    bs = tg.make_build_event(rng, 1, det, noise_frac=0.0, pt_range=(2.0, 3.0))
+    x, P, p_chi2, _ = seed_phase(orc, bs, 0)
+    xp, F, _, rc = orc.propagate(x, int(bs.q[0]), det.bz, det.radii[3])
+    assert rc == 0
+    Pp = orc.cov_propagate(P, F)
+    # equal radial and tangential resolutions: V = diag(s^2, s^2, sz^2) for any hit
+    S = Pp[:3, :3] + np.diag([det.sigma_r ** 2, det.sigma_rphi ** 2, det.sigma_z ** 2])
+    v = np.array([-xp[1], xp[0], 0.3 * det.radii[3]])
+    u = v / math.sqrt(v @ np.linalg.solve(S, v))
+    new = np.stack([xp[:3] + math.sqrt(a) * u for a in a2], axis=1)
+    hits = [bs.layer_hits(0, l) for l in range(3)] + [new]
+    off = np.concatenate([[0], np.cumsum([h.shape[1] for h in hits])]).astype(np.int64)
+    ev = tg.BuildSet(det, 1, off, np.concatenate(hits, axis=1), bs.seed_off, bs.state, bs.cov, bs.q,
+                     bs.seed_hit, bs.true_idx, bs.truth_pos, bs.truth_mom)
+    return ev, p_chi2
+
+
+def rel(a, b):
+    return abs(b - a) / max(1.0, abs(a))
+
+
+@pytest.mark.parametrize("nc,a2,expect,expect_final", [
+    # two close records decide the order of the kept pair
+    (10, [4.0, 4.5, 20.0], lambda p: rel(p + 4.0, p + 4.5), lambda p: rel(p + 4.0, p + 4.5)),
+    # a compatible hit 0.3 below the cut (an incompatible one 0.6 above)
+    (10, [4.0, 10.0, 29.7, 30.6], lambda p: 0.3 / 30.0, lambda p: rel(p + 4.0, p + 10.0)),
+    # an incompatible hit 0.15 above the cut decides too
+    (10, [4.0, 10.0, 30.15], lambda p: 0.15 / 30.0, lambda p: rel(p + 4.0, p + 10.0)),
+    # one candidate kept: the gap beyond the first dropped record is no decision,
+    # and with one survivor the final choice has no competitor
+    (1, [4.0, 6.0, 6.1], lambda p: rel(p + 4.0, p + 6.0), lambda p: math.inf),
+    # two kept: the gap between the last kept and the first dropped decides
+    (2, [4.0, 6.0, 6.1], lambda p: rel(p + 6.0, p + 6.1), lambda p: rel(p + 4.0, p + 6.0)),
+])
+def test_margin_closed_form(orc, nc, a2, expect, expect_final):
+    ev, p = designed_event(orc, a2)
+    o = orc.build_event(ev, 0, max_cands=nc, chi2_cut=CUT, debug=True)
+    order = np.argsort(a2)
+    compatible = [i for i in order if a2[i] < CUT][:nc]
+    assert o["dbg_n"][3, 0] == len(compatible)
+    assert list(o["dbg"][3, :len(compatible), 1, 0]) == compatible   # kept hits by chi2
+    assert o["hit_idx"][3, 0] == compatible[0] and math.isclose(o["chi2"][0], p + a2[compatible[0]],
+                                                                rel_tol=1e-12)
+    assert math.isclose(o["margin"][3, 0], expect(p), rel_tol=1e-9), (o["margin"][3, 0], expect(p))
+    assert np.all(np.isinf(o["margin"][:3, 0]))   # the seed layers take no decision
+    ef = expect_final(p)
+    if math.isinf(ef):
+        assert math.isinf(o["margin"][4, 0])
+    else:
+        assert math.isclose(o["margin"][4, 0], ef, rel_tol=1e-9), (o["margin"][4, 0], ef)
+
+
+def test_final_margin_only_among_equal_hit_counts(orc):
+    """Two candidates leave the building layer (hits at chi2 4 and 25); on a
+    second building layer one hit sits 5 sigma from the second candidate's
+    prediction, away from the first's, which finds nothing and (no missed
+    layer allowed) ends with one hit fewer.  The final choice is then
+    decided by the hit count alone: no chi2 gap is a decision (infinite
+    final margin), and the last layer's margin is the hits' distances from
+    the cut."""
+    det = tg.barrel(5)
+    rng = np.random.default_rng(92)
+    bs = tg.make_build_event(rng, 1, det, noise_frac=0.0, pt_range=(2.0, 3.0))
+    x, P, p, _ = seed_phase(orc, bs, 0)
+    q = int(bs.q[0])
+    xp, F, _, _ = orc.propagate(x, q, det.bz, det.radii[3])
+    Pp = orc.cov_propagate(P, F)
+    V = np.diag([det.sigma_r ** 2, det.sigma_rphi ** 2, det.sigma_z ** 2])
+    S = Pp[:3, :3] + V
+    v = np.array([-xp[1], xp[0], 0.3 * det.radii[3]])
+    u = v / math.sqrt(v @ np.linalg.solve(S, v))
+    l3 = np.stack([xp[:3] + 2.0 * u, xp[:3] + 5.0 * u], axis=1)
+    cand = []
+    for i in range(2):
+        m = l3[:, i]
+        xn, Pn, c2, rc = orc.update(xp, Pp, m, orc.hit_cov(m, det.sigma_r, det.sigma_rphi, det.sigma_z))
+        y, F4, _, rc4 = orc.propagate(xn, q, det.bz, det.radii[4])
+        assert rc == 0 and rc4 == 0
+        cand.append((y, orc.cov_propagate(Pn, F4)))
+    (y0, P0), (y1, P1) = cand
+    S1 = P1[:3, :3] + V
+    d = y1[:3] - y0[:3]
+    h4 = y1[:3] + 5.0 * d / math.sqrt(d @ np.linalg.solve(S1, d))   # chi2 25 for the second
+    c2_first, _ = orc.chi2(y0, P0, h4, orc.hit_cov(h4, det.sigma_r, det.sigma_rphi, det.sigma_z))
+    assert c2_first > CUT
+    hits = [bs.layer_hits(0, l) for l in range(3)] + [l3, h4[:, None]]
+    off = np.concatenate([[0], np.cumsum([h.shape[1] for h in hits])]).astype(np.int64)
+    ev = tg.BuildSet(det, 1, off, np.concatenate(hits, axis=1), bs.seed_off, bs.state, bs.cov, bs.q,
+                     bs.seed_hit, bs.true_idx, bs.truth_pos, bs.truth_mom)
+    o = orc.build_event(ev, 0, max_cands=2, max_missed=0, chi2_cut=CUT, debug=True)
+    assert o["nhits"][0] == 5 and list(o["hit_idx"][3:, 0]) == [1, 0]
+    assert math.isclose(o["chi2"][0], p + 25.0 + 25.0, rel_tol=1e-9)
+    assert math.isclose(o["margin"][3, 0], min(rel(p + 4.0, p + 25.0), 5.0 / 30.0, 26.0 / 30.0), rel_tol=1e-9)
+    assert math.isclose(o["margin"][4, 0], min(5.0 / 30.0, (c2_first - CUT) / CUT), rel_tol=1e-9)
+    assert math.isinf(o["margin"][5, 0])

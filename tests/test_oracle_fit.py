@@ -253,3 +253,103 @@ def test_no_reach_status(orc):
     assert np.all(r < 32.0)
     assert np.all(np.min(np.abs(r[:, None] - np.array(fs.det.radii)[None]), axis=1) < 1e-9)
     assert np.all(o["nupd"] == 1)
+
+
+def test_nonfinite_status(orc):
+    """A prior with an infinite pz variance (no information on pz) and no hit
+    on the first layer: the covariance propagated to that layer is not
+    finite before any residual covariance is formed, so the fit stops there
+    with NONFINITE alone (no S_NOT_PD), no hit used, and the state the seed
+    propagated to the first layer.  The same seeds with finite priors fit
+    cleanly."""
+    fs = consistent_fit_set(6, 26)
+    valid = np.ones((10, 6), np.uint8)
+    valid[0] = 0
+    cov = fs.cov.copy()
+    o_ok = orc.fit_arrays(fs.det, fs.state, cov, fs.q, fs.hits, valid)
+    assert np.all(o_ok["status"] == 0) and np.all(o_ok["nupd"] == 9)
+    cov[20] = np.inf   # the packed (pz, pz) entry
+    o = orc.fit_arrays(fs.det, fs.state, cov, fs.q, fs.hits, valid)
+    assert np.all(o["status"] == orc.NONFINITE)
+    assert np.all(o["nupd"] == 0) and np.all(o["chi2"] == 0.0)
+    for i in range(fs.n):
+        xp, F, s, rc = orc.propagate(fs.state[:, i], int(fs.q[i]), fs.det.bz, fs.det.radii[0], True)
+        assert rc == 0
+        np.testing.assert_array_equal(o["state"][:, i], xp)
+        assert not np.all(np.isfinite(o["cov"][:, i]))
+
+
+def test_ten_percent_prior_pulls_belong_to_the_linearisation(orc):
+    """With the survey's 10% momentum prior the filter's momentum pulls
+    exceed one, while the batch maximum-a-posteriori fit of the same hits
+    with the same prior (Gauss-Newton, numerical Jacobians, its Laplace
+    covariance carried to the last layer) has unit pulls: the prior and the
+    hits are consistent, and the excess is the filter linearising at an
+    estimate 10% off.  (A 3% prior brings the filter's pulls to one, the
+    pin above.)"""
+    n = 240
+    fs = tg.config2(n=n, seed=77)
+    o = orc.fit(fs)
+    ys = np.zeros((6, n))
+    Cs = np.zeros((6, 6, n))
+    for i in range(n):
+        C0 = np_unpack(fs.cov[:, i:i + 1])[0]
+        ys[:, i], Cs[:, :, i] = gauss_newton_map(orc, fs.det, fs.state[:, i], C0, int(fs.q[i]), fs.hits[:, :, i])
+    Cp = np.stack([Cs[i, j] for i in range(6) for j in range(i, 6)])
+    pk = pulls_at(o["state"], o["cov"], fs)
+    pg = pulls_at(ys, Cp, fs)
+    for name in pg:
+        rg = np.sqrt(np.mean(pg[name] ** 2))
+        assert 0.88 <= rg <= 1.12, (name, rg)
+    for name in ("px", "py", "pz"):
+        rk, rg = np.sqrt(np.mean(pk[name] ** 2)), np.sqrt(np.mean(pg[name] ** 2))
+        assert rk / rg > 1.04, (name, rk, rg)
+
+
+def pulls_at(state, cov, fs):
+    x, y = fs.truth_pos[-1][0], fs.truth_pos[-1][1]
+    d = state - np.concatenate([fs.truth_pos[-1], fs.truth_mom[-1]])
+    r = np.hypot(x, y)
+    tx, ty = -y / r, x / r
+    vt = tx * tx * cov[0] + 2 * tx * ty * cov[1] + ty * ty * cov[6]
+    out = {"t": (d[0] * tx + d[1] * ty) / np.sqrt(vt)}
+    for i, name, ci in [(2, "z", 11), (3, "px", 15), (4, "py", 18), (5, "pz", 20)]:
+        out[name] = d[i] / np.sqrt(cov[ci])
+    return out
+
+
+def gauss_newton_map(orc, det, x0, C0, q, hits, iters=12):
+    """Batch MAP fit of the seed-level state (prior plus every hit) by
+    Gauss-Newton with numerical Jacobians; returns the state at the last
+    layer and its covariance (the inverse Gauss-Newton Hessian carried there
+    by the numerical Jacobian of the map)."""
+    W0 = np.linalg.cholesky(np.linalg.inv(C0)).T
+    Vis = [np.linalg.cholesky(np.linalg.inv(orc.hit_cov(hits[l], det.sigma_r, det.sigma_rphi,
+                                                          det.sigma_z))).T
+           for l in range(det.n_layers)]
+
+    def fwd(x):
+        out = [W0 @ (x - x0)]
+        y = x
+        for l, r in enumerate(det.radii):
+            y, F, s, rc = orc.propagate(y, q, det.bz, r, l == 0)
+            out.append(Vis[l] @ (hits[l] - y[:3]))
+        return np.concatenate(out), y
+
+    def jac(f, x):
+        cols = []
+        for j in range(6):
+            h = 1e-7 * max(1.0, abs(x[j]))
+            a, b = x.copy(), x.copy()
+            a[j] += h
+            b[j] -= h
+            cols.append((f(a) - f(b)) / (2 * h))
+        return np.stack(cols, axis=1)
+
+    x = x0.copy()
+    for _ in range(iters):
+        r0, _ = fwd(x)
+        x = x - np.linalg.lstsq(jac(lambda z: fwd(z)[0], x), r0, rcond=None)[0]
+    J = jac(lambda z: fwd(z)[0], x)
+    G = jac(lambda z: fwd(z)[1], x)
+    return fwd(x)[1], G @ np.linalg.pinv(J.T @ J) @ G.T
