@@ -275,28 +275,34 @@ int ktf_bin_hits(ktf_ctx *ctx, const ktf_event_batch *ev, int32_t *offsets, int3
 
 /* ---------------------------------------------------------------- serving
  * Continuous batching: events are submitted from host memory as they
- * arrive; a scheduler thread admits queued events while the in-flight
- * device footprint stays within hbm_budget_bytes and fewer than
- * max_inflight events are in flight, runs build + final fit for each
- * admitted group on its own stream (groups overlap on the device), and
+ * arrive; a scheduler thread admits queued events while the sum of the
+ * in-flight events' device footprints (an estimate of every buffer their
+ * building and fit use; the lanes' grow-only workspaces may hold up to
+ * twice that) stays within hbm_budget_bytes and fewer than max_inflight
+ * events are in flight, runs build + final fit for each admitted group of
+ * one precision on its own stream (groups overlap on the device), and
  * returns results through ktf_poll.  Results are identical to running the
- * event alone.
+ * event alone.  If a group fails to launch, its events are retried one by
+ * one, so a failing event fails alone.
  */
 typedef struct {
   int64_t n_seeds;
   const int64_t *hit_off;   /* host [n_layers+1]                                 */
-  const float *hits;        /* host [3][hit_off[n_layers]] (SoA)                 */
-  const float *seed_state;  /* host [6][n_seeds]                                 */
-  const float *seed_cov;    /* host [21][n_seeds]                                */
+  const void *hits;         /* host [3][hit_off[n_layers]] (SoA), double for
+                               KTF_FP64, float for KTF_FP32_BULK                 */
+  const void *seed_state;   /* host [6][n_seeds], the same type                  */
+  const void *seed_cov;     /* host [21][n_seeds], the same type                 */
   const int8_t *charge;     /* host [n_seeds]: > 0 positive, else negative     */
   const int32_t *seed_hit;  /* host [n_seed_layers][n_seeds]                     */
-  ktf_precision prec;       /* arithmetic of build and fit for this event        */
+  ktf_precision prec;       /* arithmetic of build and fit for this event and
+                               the type of its values (KTF_FP64 or KTF_FP32_BULK) */
 } ktf_event_host;
 
 typedef struct {
   int32_t *hit_idx;         /* host [n_layers][n_seeds]                          */
-  float *state;             /* host [6][n_seeds]: final fit over the built hits  */
-  float *cov;               /* host [21][n_seeds]                                */
+  void *state;              /* host [6][n_seeds]: final fit over the built hits,
+                               in the submitted event's type                     */
+  void *cov;                /* host [21][n_seeds], the same type                 */
   double *chi2;             /* host [n_seeds]: final fit chi2                    */
   int32_t *n_hits;          /* host [n_seeds]                                    */
   uint32_t *status;         /* host [n_seeds]                                    */
@@ -318,6 +324,12 @@ int ktf_poll(ktf_ctx *ctx, uint64_t ticket, ktf_result_host *out);
 double ktf_now(void);
 /* Events queued, in flight and finished-but-uncollected. */
 int ktf_serving_stats(ktf_ctx *ctx, int64_t *queued, int64_t *inflight, int64_t *done);
+/* Testing hook for failure isolation: the next event submitted on ctx
+ * fails when its group is launched, as a launch failure would, before any
+ * device work of the group is enqueued (no kernel ever faults); its
+ * ktf_poll returns KTF_EDEVICE and the other events of its group are
+ * retried alone and complete normally.  Thread-safe. */
+int ktf_debug_fail_next_event(ktf_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ MAX_LAYERS = 32
 
 EXPORTS = ["ktf_create", "ktf_destroy", "ktf_last_error", "ktf_fit", "ktf_autotune_fit",
            "ktf_tuned_shape", "ktf_build", "ktf_bin_hits", "ktf_submit", "ktf_poll", "ktf_now",
-           "ktf_serving_stats", "ktf_fit_noalloc"]
+           "ktf_serving_stats", "ktf_fit_noalloc", "ktf_debug_fail_next_event"]
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
     lib.ktf_now.restype = C.c_double
     lib.ktf_serving_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]
+    lib.ktf_debug_fail_next_event.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -163,6 +164,7 @@ class Context:
                       n_phibins, max_cands, max_missed, n_seed_layers, chi2_cut,
                       int(hbm_budget_bytes), max_inflight, self._x0, eloss_per_x0, mass)
         self.cfg = cfg
+        self._ticket_dtype = {}
         h = C.c_void_p()
         rc = lib.ktf_create(C.byref(cfg), C.byref(h))
         if rc != OK:
@@ -345,30 +347,39 @@ class Context:
 
     # ------------------------------------------------------------- serving
     def submit(self, ev_host) -> int:
-        """Queue one event from host numpy arrays (float32 hits/seeds):
-        hit_off int64 [L+1], hits [3, nh], state [6, n], cov [21, n], q int8 [n],
-        seed_hit int32 [nsl, n]; prec 'fp64' or 'fp32b'."""
+        """Queue one event from host numpy arrays: hit_off int64 [L+1], hits
+        [3, nh], state [6, n], cov [21, n] (float64 for prec 'fp64', float32
+        for 'fp32b'), q int8 [n], seed_hit int32 [nsl, n]."""
         import numpy as np
+        prec = ev_host.get("prec", "fp32b")
+        vt = np.float64 if prec == "fp64" else np.float32
         arrs = dict(hit_off=np.ascontiguousarray(ev_host["hit_off"], dtype=np.int64),
-                    hits=np.ascontiguousarray(ev_host["hits"], dtype=np.float32),
-                    state=np.ascontiguousarray(ev_host["state"], dtype=np.float32),
-                    cov=np.ascontiguousarray(ev_host["cov"], dtype=np.float32),
+                    hits=np.ascontiguousarray(ev_host["hits"], dtype=vt),
+                    state=np.ascontiguousarray(ev_host["state"], dtype=vt),
+                    cov=np.ascontiguousarray(ev_host["cov"], dtype=vt),
                     q=np.ascontiguousarray(ev_host["q"], dtype=np.int8),
                     seed_hit=np.ascontiguousarray(ev_host["seed_hit"], dtype=np.int32))
         n = arrs["q"].shape[0]
         e = _EventHost(n, arrs["hit_off"].ctypes.data, arrs["hits"].ctypes.data,
                        arrs["state"].ctypes.data, arrs["cov"].ctypes.data, arrs["q"].ctypes.data,
-                       arrs["seed_hit"].ctypes.data, PRECS[ev_host.get("prec", "fp32b")])
+                       arrs["seed_hit"].ctypes.data, PRECS[prec])
         t = C.c_uint64()
         self._check(self._lib.ktf_submit(self._h, C.byref(e), C.byref(t)), "ktf_submit")
+        self._ticket_dtype[t.value] = vt
         return t.value
 
+    def debug_fail_next_event(self):
+        """Testing hook: the next submitted event fails at launch (host-forced)."""
+        self._check(self._lib.ktf_debug_fail_next_event(self._h), "ktf_debug_fail_next_event")
+
     def poll(self, ticket, n_seeds):
-        """Returns None while pending, else a dict of host numpy results."""
+        """Returns None while pending, else a dict of host numpy results
+        (state and cov in the submitted event's precision)."""
         import numpy as np
         L = self.n_layers
-        res = dict(hit_idx=np.empty((L, n_seeds), np.int32), state=np.empty((6, n_seeds), np.float32),
-                   cov=np.empty((21, n_seeds), np.float32), chi2=np.empty(n_seeds, np.float64),
+        vt = self._ticket_dtype.get(ticket, np.float32)
+        res = dict(hit_idx=np.empty((L, n_seeds), np.int32), state=np.empty((6, n_seeds), vt),
+                   cov=np.empty((21, n_seeds), vt), chi2=np.empty(n_seeds, np.float64),
                    nhits=np.empty(n_seeds, np.int32), status=np.empty(n_seeds, np.uint32))
         r = _ResultHost(res["hit_idx"].ctypes.data, res["state"].ctypes.data, res["cov"].ctypes.data,
                         res["chi2"].ctypes.data, res["nhits"].ctypes.data, res["status"].ctypes.data,
@@ -376,6 +387,7 @@ class Context:
         rc = self._lib.ktf_poll(self._h, C.c_uint64(ticket), C.byref(r))
         if rc == EAGAIN:
             return None
+        self._ticket_dtype.pop(ticket, None)
         self._check(rc, "ktf_poll")
         res.update(t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done)
         return res

@@ -105,6 +105,7 @@ struct ktf_ctx {
 
   // serving
   ktf::ServeState* serve = nullptr;  // owned; freed by serve_shutdown
+  std::mutex serve_mu;               // guards the creation and shutdown of serve
 
   void set_error(const std::string& s) {
     std::lock_guard<std::mutex> g(err_mu);

@@ -42,23 +42,30 @@ struct HostBuf {
   size_t bytes() const { return cap * sizeof(T); }
 };
 
+// An event's host copies.  Coordinates, states and covariances are kept in
+// the event's own precision (float for KTF_FP32_BULK, double for KTF_FP64),
+// as bytes: a batch holds events of one precision, so every copy between an
+// event and a batch is a plain row copy.
 struct ServeEvent {
   uint64_t ticket = 0;
   int64_t n_seeds = 0, n_hits = 0;
   ktf_precision prec = KTF_FP32_BULK;
+  size_t ts = 4;                 // bytes of one value: 8 for KTF_FP64, else 4
   std::vector<int64_t> hit_off;  // [L+1]
-  HostBuf<float> hits;           // [3][n_hits]
-  HostBuf<float> state;          // [6][n]
-  HostBuf<float> cov;            // [21][n]
+  HostBuf<unsigned char> hits;   // [3][n_hits] values
+  HostBuf<unsigned char> state;  // [6][n]
+  HostBuf<unsigned char> cov;    // [21][n]
   HostBuf<int8_t> q;
   HostBuf<int32_t> seed_hit;     // [nsl][n]
   size_t footprint = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   bool done = false;
   int error = 0;
+  bool fail_injected = false;    // ktf_debug_fail_next_event: fail at launch
+  bool solo = false;             // run in a batch of its own (after a batch failed)
   // results
   HostBuf<int32_t> r_hit;        // [L][n]
-  HostBuf<float> r_state, r_cov;
+  HostBuf<unsigned char> r_state, r_cov;  // [6][n], [21][n] values
   HostBuf<double> r_chi2;
   HostBuf<int32_t> r_nh;
   HostBuf<uint32_t> r_st;
@@ -97,6 +104,7 @@ struct ServeState {
   size_t inflight_bytes = 0;
   int64_t n_inflight = 0, n_done = 0;
   bool stop = false;
+  bool fail_next = false;  // ktf_debug_fail_next_event armed
   std::string error;
   std::thread th;
 };
@@ -188,27 +196,15 @@ static hipError_t ensure_pinned(void** p, size_t* have, size_t want) {
 struct RowCopy {
   const void* src;
   void* dst;
-  int64_t n;
-  int kind;  // 0: float -> float, 1: float -> double, 2: double -> float, 3: 4-byte words, 4: bytes
+  int64_t n;     // elements
+  int size;      // bytes per element
 };
 
-static void run_copy(const RowCopy& t) {
-  switch (t.kind) {
-    case 0: std::copy_n(static_cast<const float*>(t.src), t.n, static_cast<float*>(t.dst)); break;
-    case 1: std::copy_n(static_cast<const float*>(t.src), t.n, static_cast<double*>(t.dst)); break;
-    case 2: std::copy_n(static_cast<const double*>(t.src), t.n, static_cast<float*>(t.dst)); break;
-    case 3: std::copy_n(static_cast<const int32_t*>(t.src), t.n, static_cast<int32_t*>(t.dst)); break;
-    default: memcpy(t.dst, t.src, (size_t)t.n); break;
-  }
-}
-
-// element sizes of a copy kind's source and destination
-static int src_size(int kind) { return kind == 2 ? 8 : kind == 4 ? 1 : 4; }
-static int dst_size(int kind) { return kind == 1 ? 8 : kind == 4 ? 1 : 4; }
+static void run_copy(const RowCopy& t) { memcpy(t.dst, t.src, (size_t)t.n * t.size); }
 
 static void run_copies(const std::vector<RowCopy>& rows) {
   size_t bytes = 0;
-  for (const RowCopy& t : rows) bytes += (size_t)t.n * src_size(t.kind);
+  for (const RowCopy& t : rows) bytes += (size_t)t.n * t.size;
   const int nt = bytes > ((size_t)4 << 20) ? 4 : 1;
   if (nt == 1) {
     for (const RowCopy& t : rows) run_copy(t);
@@ -219,8 +215,8 @@ static void run_copies(const std::vector<RowCopy>& rows) {
   constexpr int64_t kPiece = 256 * 1024;
   for (const RowCopy& t : rows)
     for (int64_t o = 0; o < t.n; o += kPiece)
-      tasks.push_back({static_cast<const char*>(t.src) + o * src_size(t.kind),
-                       static_cast<char*>(t.dst) + o * dst_size(t.kind), std::min(kPiece, t.n - o), t.kind});
+      tasks.push_back({static_cast<const char*>(t.src) + o * t.size, static_cast<char*>(t.dst) + o * t.size,
+                       std::min(kPiece, t.n - o), t.size});
   std::vector<std::thread> th;
   for (int w = 1; w < nt; ++w)
     th.emplace_back([&tasks, w, nt] {
@@ -229,10 +225,6 @@ static void run_copies(const std::vector<RowCopy>& rows) {
   for (size_t i = 0; i < tasks.size(); i += nt) run_copy(tasks[i]);
   for (std::thread& x : th) x.join();
 }
-
-// the copy kind from float rows into TS rows, and back
-template <typename TS> constexpr int kind_in() { return sizeof(TS) == 8 ? 1 : 0; }
-template <typename TS> constexpr int kind_out() { return sizeof(TS) == 8 ? 2 : 0; }
 
 // Byte offsets of a batch's outputs in the lane's output buffer: the part
 // the host reads (hit indices and the final fit's results) comes first and
@@ -268,6 +260,9 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
   const int E = (int)ln.batch.size();
   int64_t N = 0, H = 0;
   for (ServeEvent* ev : ln.batch) {
+    // a failure forced from the host for tests of isolation: before any
+    // device work of the batch is enqueued, as a launch failure would be
+    if (ev->fail_injected) return fail(c, KTF_EDEVICE, "serve: injected failure (ktf_debug_fail_next_event)");
     N += ev->n_seeds;
     H += ev->n_hits;
   }
@@ -311,11 +306,14 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
     for (ServeEvent* ev : ln.batch) {
       const int64_t n = ev->n_seeds, nh = ev->n_hits;
       // rows of the event into rows of the batch
-      for (int k = 0; k < 3; ++k) tasks.push_back({ev->hits.data() + k * nh, hh + k * H + hb, nh, kind_in<TS>()});
-      for (int k = 0; k < 6; ++k) tasks.push_back({ev->state.data() + k * n, st + k * N + sb, n, kind_in<TS>()});
-      for (int k = 0; k < 21; ++k) tasks.push_back({ev->cov.data() + k * n, cv + k * N + sb, n, kind_in<TS>()});
-      for (int k = 0; k < NSL; ++k) tasks.push_back({ev->seed_hit.data() + k * n, sh + k * N + sb, n, 3});
-      tasks.push_back({ev->q.data(), qq + sb, n, 4});
+      const TS* eh = reinterpret_cast<const TS*>(ev->hits.data());
+      const TS* es = reinterpret_cast<const TS*>(ev->state.data());
+      const TS* ec = reinterpret_cast<const TS*>(ev->cov.data());
+      for (int k = 0; k < 3; ++k) tasks.push_back({eh + k * nh, hh + k * H + hb, nh, (int)sizeof(TS)});
+      for (int k = 0; k < 6; ++k) tasks.push_back({es + k * n, st + k * N + sb, n, (int)sizeof(TS)});
+      for (int k = 0; k < 21; ++k) tasks.push_back({ec + k * n, cv + k * N + sb, n, (int)sizeof(TS)});
+      for (int k = 0; k < NSL; ++k) tasks.push_back({ev->seed_hit.data() + k * n, sh + k * N + sb, n, 4});
+      tasks.push_back({ev->q.data(), qq + sb, n, 1});
       sb += n;
       hb += nh;
     }
@@ -404,14 +402,14 @@ static void unpack_batch_t(ktf_ctx* c, Lane& ln) {
   for (ServeEvent* ev : ln.batch) {
     const int64_t n = ev->n_seeds;
     int32_t* r_hit = ev->r_hit.get((size_t)L * n);
-    float* r_state = ev->r_state.get(6 * n);
-    float* r_cov = ev->r_cov.get(21 * n);
-    for (int l = 0; l < L; ++l) tasks.push_back({hit + l * N + sb, r_hit + l * n, n, 3});
-    for (int k = 0; k < 6; ++k) tasks.push_back({st + k * N + sb, r_state + k * n, n, kind_out<TS>()});
-    for (int k = 0; k < 21; ++k) tasks.push_back({cv + k * N + sb, r_cov + k * n, n, kind_out<TS>()});
-    tasks.push_back({c2 + sb, ev->r_chi2.get(n), 8 * n, 4});
-    tasks.push_back({nu + sb, ev->r_nh.get(n), n, 3});
-    tasks.push_back({ss + sb, ev->r_st.get(n), n, 3});
+    TS* r_state = reinterpret_cast<TS*>(ev->r_state.get(sizeof(TS) * 6 * n));
+    TS* r_cov = reinterpret_cast<TS*>(ev->r_cov.get(sizeof(TS) * 21 * n));
+    for (int l = 0; l < L; ++l) tasks.push_back({hit + l * N + sb, r_hit + l * n, n, 4});
+    for (int k = 0; k < 6; ++k) tasks.push_back({st + k * N + sb, r_state + k * n, n, (int)sizeof(TS)});
+    for (int k = 0; k < 21; ++k) tasks.push_back({cv + k * N + sb, r_cov + k * n, n, (int)sizeof(TS)});
+    tasks.push_back({c2 + sb, ev->r_chi2.get(n), n, 8});
+    tasks.push_back({nu + sb, ev->r_nh.get(n), n, 4});
+    tasks.push_back({ss + sb, ev->r_st.get(n), n, 4});
     sb += n;
   }
   run_copies(tasks);
@@ -456,6 +454,7 @@ static void scheduler(ktf_ctx* c) {
       while (!S->queue.empty()) {
         ServeEvent* ev = S->queue.front();
         if (ev->prec != prec) break;
+        if (!ln.batch.empty() && (ev->solo || ln.batch.front()->solo)) break;
         if (S->n_inflight >= c->cfg.max_inflight) break;
         if (S->inflight_bytes + ev->footprint > c->cfg.hbm_budget_bytes) break;
         if (!ln.batch.empty() && seeds + ev->n_seeds > kMaxBatchSeeds) break;
@@ -471,7 +470,22 @@ static void scheduler(ktf_ctx* c) {
       lk.unlock();
       int rc = prec == KTF_FP64 ? launch_batch_t<double>(c, ln) : launch_batch_t<float>(c, ln);
       lk.lock();
-      if (rc) {  // fail these events, keep serving
+      // a failed launch may have enqueued part of the batch's copies: the
+      // lane's staging is reused only once they are done
+      if (rc) (void)hipStreamSynchronize(ln.stream);
+      if (rc && ln.batch.size() > 1) {
+        // one event must not fail the others: every event of the batch goes
+        // back to the front of the queue (in order) to run alone
+        for (auto it = ln.batch.rbegin(); it != ln.batch.rend(); ++it) {
+          ServeEvent* ev = *it;
+          ev->solo = true;
+          S->inflight_bytes -= ev->footprint;
+          --S->n_inflight;
+          S->queue.push_front(ev);
+        }
+        ln.batch.clear();
+        ln.busy = false;
+      } else if (rc) {  // fail this event, keep serving
         for (ServeEvent* ev : ln.batch) {
           ev->done = true;
           ev->error = rc;
@@ -500,7 +514,10 @@ static void scheduler(ktf_ctx* c) {
   }
 }
 
+// The serving state is created by the first ktf_submit on a context; the
+// context's serve_mu makes concurrent first submissions create it once.
 static int ensure_serving(ktf_ctx* c) {
+  std::lock_guard<std::mutex> g(c->serve_mu);
   if (c->serve) return KTF_OK;
   ServeState* S = new ServeState();
   for (Lane& ln : S->lanes) {
@@ -522,6 +539,7 @@ static int ensure_serving(ktf_ctx* c) {
 }
 
 void serve_shutdown(ktf_ctx* c) {
+  std::lock_guard<std::mutex> g(c->serve_mu);
   ServeState* S = c->serve;
   if (!S) return;
   {
@@ -569,6 +587,7 @@ int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
   if ((n > 0 && (!ev->seed_state || !ev->seed_cov || !ev->charge || !ev->seed_hit)) || (nh > 0 && !ev->hits))
     return fail(c, KTF_EINVAL, "ktf_submit: null buffer");
   const size_t fp = footprint_of(cfg, n, nh, ev->prec);
+  const size_t ts = ev->prec == KTF_FP64 ? 8 : 4;
   if (fp > cfg.hbm_budget_bytes)
     return fail(c, KTF_ENOMEM, "ktf_submit: event needs %zu bytes, budget %llu", fp,
                 (unsigned long long)cfg.hbm_budget_bytes);
@@ -598,19 +617,23 @@ int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
   e->done = false;
   e->error = 0;
   e->t_admit = e->t_done = 0;
+  e->solo = false;
   e->n_seeds = n;
   e->n_hits = nh;
   e->prec = ev->prec;
+  e->ts = ts;
   e->hit_off.assign(ev->hit_off, ev->hit_off + L + 1);
-  run_copies({{ev->hits, e->hits.get(3 * nh), 3 * nh, 0},
-              {ev->seed_state, e->state.get(6 * n), 6 * n, 0},
-              {ev->seed_cov, e->cov.get(21 * n), 21 * n, 0},
-              {ev->charge, e->q.get(n), n, 4},
-              {ev->seed_hit, e->seed_hit.get((size_t)NSL * n), (int64_t)NSL * n, 3}});
+  run_copies({{ev->hits, e->hits.get(ts * 3 * nh), 3 * nh, (int)ts},
+              {ev->seed_state, e->state.get(ts * 6 * n), 6 * n, (int)ts},
+              {ev->seed_cov, e->cov.get(ts * 21 * n), 21 * n, (int)ts},
+              {ev->charge, e->q.get(n), n, 1},
+              {ev->seed_hit, e->seed_hit.get((size_t)NSL * n), (int64_t)NSL * n, 4}});
   e->footprint = fp;
   e->t_submit = t_entry;
   {
     std::lock_guard<std::mutex> g(S->mu);
+    e->fail_injected = S->fail_next;
+    S->fail_next = false;
     e->ticket = S->next_ticket++;
     S->tickets[e->ticket] = e;
     S->queue.push_back(e);
@@ -639,8 +662,8 @@ int ktf_poll(ktf_ctx* c, uint64_t ticket, ktf_result_host* out) {
     const int L = c->cfg.n_layers;
     const int64_t n = e->n_seeds;
     if (out->hit_idx) memcpy(out->hit_idx, e->r_hit.data(), sizeof(int32_t) * L * n);
-    if (out->state) memcpy(out->state, e->r_state.data(), sizeof(float) * 6 * n);
-    if (out->cov) memcpy(out->cov, e->r_cov.data(), sizeof(float) * 21 * n);
+    if (out->state) memcpy(out->state, e->r_state.data(), e->ts * 6 * n);
+    if (out->cov) memcpy(out->cov, e->r_cov.data(), e->ts * 21 * n);
     if (out->chi2) memcpy(out->chi2, e->r_chi2.data(), sizeof(double) * n);
     if (out->n_hits) memcpy(out->n_hits, e->r_nh.data(), sizeof(int32_t) * n);
     if (out->status) memcpy(out->status, e->r_st.data(), sizeof(uint32_t) * n);
@@ -657,6 +680,15 @@ int ktf_poll(ktf_ctx* c, uint64_t ticket, ktf_result_host* out) {
   }
   delete e;
   return rc ? fail(c, rc, "ktf_poll: event failed on the device") : KTF_OK;
+}
+
+int ktf_debug_fail_next_event(ktf_ctx* c) {
+  if (!c) return KTF_EINVAL;
+  int rc = ensure_serving(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(c->serve->mu);
+  c->serve->fail_next = true;
+  return KTF_OK;
 }
 
 int ktf_serving_stats(ktf_ctx* c, int64_t* queued, int64_t* inflight, int64_t* done) {

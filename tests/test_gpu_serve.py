@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import trackgen as tg
-from helpers import build_inputs, fp64_close, host
+from helpers import build_inputs, fp64_close, host, oracle_with_spread
 
 pytestmark = pytest.mark.gpu
 
@@ -59,11 +59,14 @@ def test_alone_equals_mix(k, prec):
 
 
 def test_fp64_results_match_oracle(k, orc):
+    """An FP64 event comes back in double: its hits exactly the oracle's
+    building, its final fit over those hits within the FP64 tolerance."""
     det, evs = events(2, 3, sizes=(300,))
     ctx = k.Context.for_detector(det)
     tickets = [ctx.submit(host_event(ev, "fp64")) for ev in evs]
     for t, ev in zip(tickets, evs):
         r = wait(ctx, t, ev.n_seeds)
+        assert r["state"].dtype == np.float64 and r["cov"].dtype == np.float64
         o = orc.build_event(ev, 0)
         assert np.array_equal(r["hit_idx"], o["hit_idx"])
         # the final fit over the built hits
@@ -74,11 +77,55 @@ def test_fp64_results_match_oracle(k, orc):
             lh = ev.layer_hits(0, l)
             idx = np.maximum(o["hit_idx"][l], 0)
             hits[l] = lh[:, idx] * valid[l]
-        of = orc.fit_arrays(det, ev.state, ev.cov, ev.q, hits, valid)
-        g = dict(state=r["state"].astype(np.float64), cov=r["cov"].astype(np.float64),
-                 chi2=r["chi2"], nupd=r["nhits"], status=r["status"])
-        # results come back as float32 on the host: compare at float precision
-        fp64_close(g, of, tol=3e-7)
+        fs = tg.FitSet(det, ev.state, ev.cov, ev.q, hits, valid, ev.truth_pos, ev.truth_mom)
+        of, spread = oracle_with_spread(orc, fs)
+        g = dict(state=r["state"], cov=r["cov"], chi2=r["chi2"], nupd=r["nhits"], status=r["status"])
+        fp64_close(g, of, spread)
+    ctx.close()
+
+
+def test_failed_event_is_isolated(k):
+    """A failure forced from the host on one event (ktf_debug_fail_next_event:
+    its group fails to launch, before any device work) fails that event
+    alone: the events queued with it are retried one by one and their
+    results are bit for bit those of running each alone.  Heavy events
+    first keep every lane busy, so that the small events queue up and are
+    admitted together."""
+    det, evs = events(7, 4, sizes=(300, 600, 200, 400))
+    rng = np.random.default_rng(17)
+    heavy = [tg.make_build_event(rng, 20000, det) for _ in range(4)]
+    probe = k.Context.for_detector(det)
+    ref = [wait(probe, probe.submit(host_event(ev)), ev.n_seeds) for ev in evs]
+    probe.close()
+    ctx = k.Context.for_detector(det)
+    th = [ctx.submit(host_event(ev)) for ev in heavy]
+    tickets = []
+    for i, ev in enumerate(evs):
+        if i == 1:
+            ctx.debug_fail_next_event()
+        tickets.append(ctx.submit(host_event(ev)))
+    for i, (t, ev) in enumerate(zip(tickets, evs)):
+        if i == 1:
+            t0 = time.time()
+            while True:
+                try:
+                    r = ctx.poll(t, ev.n_seeds)
+                except k.KtfError as e:
+                    assert e.code == k.EDEVICE
+                    break
+                assert r is None, "the injected failure completed"
+                assert time.time() - t0 < 60
+                time.sleep(0.001)
+            continue
+        r = wait(ctx, t, ev.n_seeds)
+        for key in ("hit_idx", "state", "cov", "chi2", "nhits", "status"):
+            assert np.array_equal(r[key], ref[i][key]), (i, key)
+    for t, ev in zip(th, heavy):
+        wait(ctx, t, ev.n_seeds)
+    # the hook fires once: the next event runs normally
+    r = wait(ctx, ctx.submit(host_event(evs[1])), evs[1].n_seeds)
+    assert np.array_equal(r["hit_idx"], ref[1]["hit_idx"])
+    assert ctx.serving_stats() == dict(queued=0, inflight=0, done=0)
     ctx.close()
 
 
