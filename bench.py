@@ -5,8 +5,11 @@ Workload: 1,000,000 synthetic tracks on 10 cylindrical barrel layers
 GeV, |eta| < 1, hits smeared by 0.01 cm in r-phi and 0.1 cm in z, seeds
 drawn around the truth.  One step = one fit of every track (propagate to
 each layer along the helix, Kalman update with its hit) on inputs already
-resident in HBM.  The headline is the FP32-bulk path; the plain FP64 path,
-the per-layer graph sweep and the FP64 CPU oracle are measured beside it.
+resident in HBM.  The headline is the float path that holds the 1e-4
+parameter bound on every track (float storage and state propagation, the
+covariance in double); FP32 bulk (the covariance in float too), the plain
+FP64 path, the per-layer graph sweeps, building, serving, uneven events
+and the FP64 CPU oracle are measured beside it.
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -24,12 +27,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of the fit per track and layer, counted from the
-# implementation's formulas (propagation in the storage precision, update in
-# FP64; an FMA counts 2).  See the measurement section of the design notes.
-FLOP_PROP_PER_LAYER = 860      # path solve (3 Newton steps), transport, Jacobian, F P F^T
-FLOP_UPD_PER_LAYER = 585       # V, S, S^-1, chi2, gain, state, Joseph covariance
-FLOP_FPF_PER_LAYER = 378       # the F P F^T part of the propagation (189 FMA)
+# Algorithmic work of the fit per track and layer.  The reference model
+# (the scope's measurement table): propagation 680 flops, of which F P F^T
+# about 200 FMA, and the update 790 FP64 flops.  FP32 bulk runs the
+# propagation in FP32; the headline path moves F P F^T to FP64.  Our own
+# count of the implemented formulas (FMA = 2) is reported beside it.
+REF_PROP, REF_FPF, REF_UPD = 680, 400, 790
+OWN_PROP, OWN_FPF, OWN_UPD = 860, 378, 585  # 3 Newton steps + series helix, 189-FMA F P F^T, 585 update
+SWEEP_REF_BYTES = 237          # per track-layer, FP32 sweep: state+cov r/w 216, hit 12, chi2 8, flag 1
 PEAK_FP32 = 157.3e12           # MI355X vector FP32 (datasheet, packed issue)
 PEAK_FP64 = 78.6e12            # MI355X vector FP64
 HBM_PEAK = 8.0e12              # bytes/s
@@ -82,6 +87,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work of the oracle sample (core-seconds)")
+    ap.add_argument("--prec", choices=["fp32p", "fp32b", "fp64"], default="fp32p",
+                    help="precision of the --profile fit loop (fp32p: the headline path)")
     ap.add_argument("--profile", choices=["fit", "sweep", "build", "copy"], default=None,
                     help="only one timed loop, for rocprofv3 runs (copy: a plain copy of "
                          "known size to calibrate the HBM byte counters)")
@@ -94,11 +101,14 @@ def parse():
     ap.add_argument("--no-build", action="store_true", help="skip the building measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-events", type=int, default=500)
-    ap.add_argument("--rates", type=str, default="500,2000")
+    ap.add_argument("--rates", type=str, default="200,500,1000,2000")
+    ap.add_argument("--budgets-mb", type=str, default="16384,1024,512",
+                    help="HBM budgets of the serving sweep (MB); a small one makes admission bind")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-events measurement")
     return ap.parse_args()
 
 
-def serving_measurement(ktf, tg, n_events, rates):
+def serving_measurement(ktf, tg, n_events, rates, budgets):
     """Poisson arrivals of building events (5,000 tracks, 10% heavy events of
     20,000-50,000 tracks, 17 layers, 20% noise) into the continuous-batching
     loop (build + final fit per event), against the plain FP64 path serving
@@ -108,10 +118,14 @@ def serving_measurement(ktf, tg, n_events, rates):
     arrivals, ntr, rng = tg.config5_stream(n_events=n_events, rate=1.0)
     det = tg.barrel(17)
     evs = [tg.make_build_event(rng, int(n), det) for n in ntr]
-    # the client hands over float32 arrays, as the C-ABI takes them
+    # the client hands over float32 arrays (float64 for the FP64 events,
+    # converted by the binding), as the C-ABI takes them
     f32 = lambda x: np.ascontiguousarray(x, np.float32)
+    f64 = lambda x: np.ascontiguousarray(x, np.float64)
     host = [dict(hit_off=e.hit_off, hits=f32(e.hits), state=f32(e.state), cov=f32(e.cov), q=e.q,
                  seed_hit=e.seed_hit) for e in evs]
+    host64 = [dict(hit_off=e.hit_off, hits=f64(e.hits), state=f64(e.state), cov=f64(e.cov), q=e.q,
+                   seed_hit=e.seed_hit) for e in evs]
 
     def run(ctx, rate, prec, sequential=False):
         lat, tracks = [], 0
@@ -119,8 +133,10 @@ def serving_measurement(ktf, tg, n_events, rates):
         lock = threading.Lock()
         start = ctx.now() + 0.05
 
+        src = host64 if prec == "fp64" else host
+
         def submitter():
-            for i, ev in enumerate(host):
+            for i, ev in enumerate(src):
                 if not sequential:
                     t_arr = start + arrivals[i] / rate
                     dt = t_arr - ctx.now()
@@ -160,17 +176,23 @@ def serving_measurement(ktf, tg, n_events, rates):
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
                 "events_per_s": round(len(host) / span, 1), "tracks_per_s": round(tracks / span)}
 
-    out = {"events": n_events, "mean_tracks_per_event": round(float(np.mean(ntr)))}
-    ctx = ktf.Context.for_detector(det, hbm_budget_bytes=16 << 30, max_inflight=64)
-    run(ctx, 1e9, "fp32b")  # warm-up: workspaces grow to their working size
-    # each rate is run once untimed first: its arrivals batch differently
-    # from the warm-up's, and a lane's first batch of a new shape may grow
-    # its workspace (a regrowth waits for the device)
+    out = {"events": n_events, "mean_tracks_per_event": round(float(np.mean(ntr))),
+           "heavy_events": int(np.sum(ntr >= 20000))}
+    # the continuous-batching loop at each HBM budget: a large one that never
+    # binds, and small ones under which admission waits for memory to free up
     out["fp32b_continuous"] = {}
-    for r in rates:
-        run(ctx, r, "fp32b")
-        out["fp32b_continuous"][str(r)] = run(ctx, r, "fp32b")
-    ctx.close()
+    for budget in budgets:
+        ctx = ktf.Context.for_detector(det, hbm_budget_bytes=budget, max_inflight=64)
+        run(ctx, 1e9, "fp32b")  # warm-up: workspaces grow to their working size
+        # each rate is run once untimed first: its arrivals batch differently
+        # from the warm-up's, and a lane's first batch of a new shape may grow
+        # its workspace (a regrowth waits for the device)
+        per = {}
+        for r in rates:
+            run(ctx, r, "fp32b")
+            per[str(r)] = run(ctx, r, "fp32b")
+        out["fp32b_continuous"][f"budget_{budget >> 20}MB"] = per
+        ctx.close()
     ctx1 = ktf.Context.for_detector(det, hbm_budget_bytes=16 << 30, max_inflight=1)
     run(ctx1, 1e9, "fp64", sequential=True)
     # closed loop: each event submitted when the previous one is done (the
@@ -452,14 +474,16 @@ def profile_run(args):
     if args.profile in ("fit", "sweep"):
         fs = tg.config2(n=args.n)
         ctx = ktf.Context.for_detector(fs.det)
-        d = fit_inputs(fs, "fp32b")
-        out = ctx.alloc_fit_out(fs.n, d["state"].shape[1], torch.float32)
+        prec = "fp32b" if args.profile == "sweep" and args.prec == "fp32p" else args.prec
+        d = fit_inputs(fs, "fp64" if prec == "fp64" else "fp32b")
+        pp = None if prec == "fp32b" else prec
+        out = ctx.alloc_fit_out(fs.n, d["state"].shape[1], d["state"].dtype)
         # the same launch the headline times: the tuned shape of the fused
         # kernel (tuning launches appear in the trace under their own names)
         if args.profile == "fit":
-            ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out)
+            ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out, prec=pp)
         mode = "auto" if args.profile == "fit" else "sweep_graph"
-        run = lambda: ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode, out=out)
+        run = lambda: ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode=mode, out=out, prec=pp)
         ms, _ = timed_loop(run, args.steps, args.warmup, torch)
         print(json.dumps({"ms_per_step": ms, "n": fs.n}))
         return
@@ -472,10 +496,13 @@ def profile_run(args):
     print(json.dumps({"ms_per_step": ms, "seeds": bs.n_seeds}))
 
 
-def mixed_frac(f32_per_layer, f64_per_layer, L, n, ms):
-    """Achieved over peak for a launch doing the given FP32 and FP64 flops."""
-    f32, f64 = f32_per_layer * L * n, f64_per_layer * L * n
-    return (f32 / PEAK_FP32 + f64 / PEAK_FP64) / (ms * 1e-3)
+def roofline_of(f32, f64, ms):
+    """Mixed-precision ALU roofline of a launch doing f32 FP32 and f64 FP64
+    flops in ms: the time at the published peaks, and the fraction of it
+    achieved (t_bound / t_measured)."""
+    t_bound = f32 / PEAK_FP32 + f64 / PEAK_FP64
+    return {"achieved": (f32 + f64) / (ms * 1e-3), "peak": (f32 + f64) / t_bound,
+            "frac": t_bound / (ms * 1e-3), "t_bound_us": t_bound * 1e6}
 
 
 def timed_loop(fn, steps, warmup, torch):
@@ -507,6 +534,60 @@ def per_launch_ms(fn, reps, torch):
         b.record(s)
     torch.cuda.synchronize()
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def uneven_summary(ktf, tg, torch, steps):
+    """Events of uneven size (2,000 events, log-normal track counts, 6-17
+    hits, 0-3 missing layers; FP32 bulk) in one launch of the tuned fused
+    kernel, against one launch per event: issued from the host, and the
+    same 2,000 launches captured once in a graph and replayed (device time
+    without host launch overhead)."""
+    from tests.helpers import fit_inputs
+    print("[bench] uneven events: generating", file=sys.stderr, flush=True)
+    fs, offs = tg.config4()
+    n = fs.n
+    ctx = ktf.Context.for_detector(fs.det)
+    d = fit_inputs(fs, "fp32b")
+    out = ctx.alloc_fit_out(n, d["state"].shape[1], torch.float32)
+    ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out)
+    res = {"events": len(offs) - 1, "tracks": n,
+           "hits_per_track": round(float(fs.valid.sum(axis=0).mean()), 3)}
+    for mode in ("auto", "persistent", "sweep_graph"):
+        ms, _ = timed_loop(lambda: ctx.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"],
+                                           mode=mode, out=out), steps, 2, torch)
+        res[mode] = {"ms": round(ms, 4), "tracks_per_s": round(n / (ms * 1e-3))}
+    res["tuned_launch"] = json.loads(ctx.tuned_shape("fp32b", n))
+    del d, out
+    print("[bench] uneven events: per-event launches", file=sys.stderr, flush=True)
+    per = []
+    for e in range(len(offs) - 1):
+        a, b = int(offs[e]), int(offs[e + 1])
+        ev = tg.FitSet(fs.det, fs.state[:, a:b], fs.cov[:, a:b], fs.q[a:b], fs.hits[:, :, a:b],
+                       fs.valid[:, a:b], fs.truth_pos[:, :, a:b], fs.truth_mom[:, :, a:b])
+        per.append((fit_inputs(ev, "fp32b"), b - a))
+    outs = [ctx.alloc_fit_out(m, dd["state"].shape[1], torch.float32) for dd, m in per]
+
+    def all_events():
+        for (dd, m), oo in zip(per, outs):
+            ctx.fit(dd["state"], dd["cov"], dd["q"], dd["hits"], dd["valid"], mode="fused", out=oo)
+
+    ms_host, wall = timed_loop(all_events, 3, 1, torch)
+    # the same launches captured once and replayed: a fused launch allocates
+    # nothing and records no memset, so it can be captured
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        all_events()
+    ms_graph, _ = timed_loop(g.replay, 5, 2, torch)
+    res["per_event_launches"] = {"launches": len(per), "host_issued_ms": round(ms_host, 4),
+                                 "host_issued_wall_ms": round(wall, 3),
+                                 "graph_replay_ms": round(ms_graph, 4),
+                                 "graph_replay_tracks_per_s": round(n / (ms_graph * 1e-3))}
+    res["one_launch_speedup_vs_graph"] = round(ms_graph / res["auto"]["ms"], 3)
+    res["one_launch_speedup_vs_host_issued"] = round(ms_host / res["auto"]["ms"], 2)
+    del g, per, outs
+    ctx.close()
+    return res
 
 
 def main():
@@ -542,14 +623,18 @@ def main():
     ctx = ktf.Context.for_detector(fs.det)
     d32 = fit_inputs(fs, "fp32b")
     d64 = fit_inputs(fs, "fp64")
+    outp = ctx.alloc_fit_out(n, d32["state"].shape[1], torch.float32)
     out32 = ctx.alloc_fit_out(n, d32["state"].shape[1], torch.float32)
     out64 = ctx.alloc_fit_out(n, d64["state"].shape[1], torch.float64)
     print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
+    ctx.autotune_fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], out=outp, prec="fp32p")
     ctx.autotune_fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], out=out32)
     ctx.autotune_fit(d64["state"], d64["cov"], d64["q"], d64["hits"], d64["valid"], out=out64)
-    out32p = ctx.alloc_fit_out(n, d32["state"].shape[1], torch.float32)
-    ctx.autotune_fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], out=out32p, prec="fp32p")
     torch.cuda.synchronize()
+
+    def runp(mode="auto"):
+        ctx.fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], mode=mode, out=outp,
+                prec="fp32p")
 
     def run32(mode="auto"):
         ctx.fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], mode=mode, out=out32)
@@ -557,51 +642,59 @@ def main():
     def run64(mode="auto"):
         ctx.fit(d64["state"], d64["cov"], d64["q"], d64["hits"], d64["valid"], mode=mode, out=out64)
 
-    def run32p(mode="auto"):
-        ctx.fit(d32["state"], d32["cov"], d32["q"], d32["hits"], d32["valid"], mode=mode, out=out32p,
-                prec="fp32p")
+    print("[bench] timing the headline fused fit", file=sys.stderr, flush=True)
+    ms, wall_ms = timed_loop(runp, args.steps, args.warmup, torch)
+    k_ms = per_launch_ms(runp, 10, torch)
 
-    print("[bench] timing FP32-bulk fused fit", file=sys.stderr, flush=True)
-    ms, wall_ms = timed_loop(run32, args.steps, args.warmup, torch)
-    k_ms = per_launch_ms(run32, 10, torch)
-
-    print("[bench] timing FP64 fused, graph sweeps", file=sys.stderr, flush=True)
+    print("[bench] timing FP32 bulk, FP64, graph sweeps", file=sys.stderr, flush=True)
+    ms32, _ = timed_loop(run32, max(3, args.steps // 2), 2, torch)
+    k32_ms = per_launch_ms(run32, 10, torch)
     ms64, _ = timed_loop(run64, max(3, args.steps // 2), 2, torch)
-    ms32p, _ = timed_loop(run32p, max(3, args.steps // 2), 2, torch)
     ms32_sw, _ = timed_loop(lambda: run32("sweep_graph"), max(3, args.steps // 2), 2, torch)
     ms64_sw, _ = timed_loop(lambda: run64("sweep_graph"), max(3, args.steps // 2), 2, torch)
 
     # results of the timed configurations, for the error report
+    runp()
     run32()
     run64()
-    run32p()
     torch.cuda.synchronize()
+    gp = {k: v.cpu().numpy()[..., :n] for k, v in outp.items()}
     g32 = {k: v.cpu().numpy()[..., :n] for k, v in out32.items()}
-    g32p = {k: v.cpu().numpy()[..., :n] for k, v in out32p.items()}
     g64 = {k: v.cpu().numpy()[..., :n] for k, v in out64.items()}
 
-    # roofline of the dominant kernel (the fused FP32-bulk fit)
-    f32 = FLOP_PROP_PER_LAYER * L * n
-    f64 = FLOP_UPD_PER_LAYER * L * n
-    t_bound = f32 / PEAK_FP32 + f64 / PEAK_FP64
-    mixed_peak = (f32 + f64) / t_bound
-    achieved = (f32 + f64) / (k_ms * 1e-3)
-    traffic = measured_traffic("fit_fused_kernel<float,float,float>")
-    roof = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(mixed_peak / 1e12, 1),
-            "unit": "TFLOP/s", "frac": round(achieved / mixed_peak, 4),
+    # roofline of the headline kernel: ALU bound, the reference flop model
+    # with F P F^T in FP64; our own count beside it
+    hp = "fit_fused_kernel<float,float,double>"
+    ref = roofline_of((REF_PROP - REF_FPF) * L * n, (REF_UPD + REF_FPF) * L * n, k_ms)
+    own = roofline_of((OWN_PROP - OWN_FPF) * L * n, (OWN_UPD + OWN_FPF) * L * n, k_ms)
+    traffic = measured_traffic(hp)
+    roof = {"bound": "alu", "achieved": round(ref["achieved"] / 1e12, 2), "peak": round(ref["peak"] / 1e12, 1),
+            "unit": "TFLOP/s", "frac": round(ref["frac"], 4),
             "traffic": None if traffic is None else round(traffic / 1e6, 1),
             "traffic_unit": "MB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "fit_fused_kernel<float,float,float>", "kernel_ms": round(k_ms, 4),
-            "flop_per_track": (FLOP_PROP_PER_LAYER + FLOP_UPD_PER_LAYER) * L,
+            "kernel": hp, "kernel_ms": round(k_ms, 4), "t_bound_us": round(ref["t_bound_us"], 1),
+            "flop_model": f"per track-layer {REF_PROP - REF_FPF} FP32 + {REF_UPD + REF_FPF} FP64 "
+                          "(propagation 680 with F P F^T 400 moved to FP64, update 790)",
+            "frac_own_count": round(own["frac"], 4),
+            "own_count": f"per track-layer {OWN_PROP - OWN_FPF} FP32 + {OWN_UPD + OWN_FPF} FP64",
             "hbm_GBps": round(fused_bytes_per_track(4, L) * n / (k_ms * 1e-3) / 1e9, 1)}
+    r32 = roofline_of(REF_PROP * L * n, REF_UPD * L * n, k32_ms)
+    o32 = roofline_of(OWN_PROP * L * n, OWN_UPD * L * n, k32_ms)
+    t32 = measured_traffic("fit_fused_kernel<float,float,float>")
     sweep = {}
-    for name, msv, pb in [("fp32b", ms32_sw, 4), ("fp64", ms64_sw, 8)]:
-        by = sweep_bytes_per_track_layer(pb) * L * n
+    for name, msv, kern in [("fp32b", ms32_sw, "fit_layer_kernel<float,float>"),
+                            ("fp64", ms64_sw, "fit_layer_kernel<double,double>")]:
+        pb = 4 if name == "fp32b" else 8
+        by_ref = (SWEEP_REF_BYTES if pb == 4 else 465) * L * n
+        by_model = sweep_bytes_per_track_layer(pb) * L * n
+        tsw = measured_traffic(kern)
         sweep[name] = {"tracks_per_s": round(n / (msv * 1e-3)), "ms": round(msv, 4),
-                       "hbm_GBps": round(by / (msv * 1e-3) / 1e9, 1),
-                       "hbm_frac": round(by / (msv * 1e-3) / HBM_PEAK, 4)}
-    tsw = measured_traffic("fit_layer_kernel<float,float>")
-    sweep["fp32b"]["traffic_MB_per_layer_launch"] = None if tsw is None else round(tsw / 1e6, 1)
+                       "hbm_frac": round(by_ref / (msv * 1e-3) / HBM_PEAK, 4),
+                       "bytes_per_track_layer": SWEEP_REF_BYTES if pb == 4 else 465,
+                       "hbm_frac_kernel_bytes": round(by_model / (msv * 1e-3) / HBM_PEAK, 4),
+                       "kernel_bytes_per_track_layer": sweep_bytes_per_track_layer(pb),
+                       "traffic_MB_per_layer_launch": None if tsw is None else round(tsw / 1e6, 1),
+                       "hbm_frac_counters": None if tsw is None else round(tsw * L / (msv * 1e-3) / HBM_PEAK, 4)}
 
     result = {
         "metric": "fitted tracks/s FP32-bulk vs FP64 plain at pull-RMS match; p50/p99 event ms",
@@ -618,17 +711,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": "FP32-bulk vs FP64 fit at scale: 1,000,000 tracks, 10 barrel layers "
                                "r=4..40 cm, Bz=3.8 T, pT log-uniform 0.5-100 GeV",
-                   "tracks": n, "layers": L, "precision": "fp32-bulk (fp64 S-inverse and Joseph update)",
-                   "launch": ctx.tuned_shape("fp32b", n)},
+                   "tracks": n, "layers": L,
+                   "precision": "float storage and float state propagation (path solve, helix, transport, "
+                                "Jacobian); covariance in double (F P F^T, S^-1, gain, Joseph update)",
+                   "launch": json.loads(ctx.tuned_shape("fp32p", n))},
         "roofline": roof,
+        "fp32_bulk": {"tracks_per_s": round(n / (ms32 * 1e-3)), "ms": round(ms32, 4),
+                      "precision": "float propagation including F P F^T, covariance float between layers; "
+                                   "S^-1, gain and Joseph update in double",
+                      "roofline_frac": round(r32["frac"], 4), "roofline_frac_own_count": round(o32["frac"], 4),
+                      "t_bound_us": round(r32["t_bound_us"], 1), "kernel_ms": round(k32_ms, 4),
+                      "traffic_MB": None if t32 is None else round(t32 / 1e6, 1),
+                      "launch": json.loads(ctx.tuned_shape("fp32b", n))},
         "fp64_plain": {"tracks_per_s": round(n / (ms64 * 1e-3)), "ms": round(ms64, 4),
-                       "launch": ctx.tuned_shape("fp64", n)},
-        "speedup_fp32b_over_fp64": round(ms64 / ms, 3),
-        "fp32_prop": {"tracks_per_s": round(n / (ms32p * 1e-3)), "ms": round(ms32p, 4),
-                      "roofline_frac": round(mixed_frac(FLOP_PROP_PER_LAYER - FLOP_FPF_PER_LAYER,
-                                                        FLOP_UPD_PER_LAYER + FLOP_FPF_PER_LAYER, L, n, ms32p), 4),
-                      "launch": ctx.tuned_shape("fp32p", n),
-                      "precision": "float state propagation, double covariance (F P F^T and update)"},
+                       "launch": json.loads(ctx.tuned_shape("fp64", n))},
+        "speedup_over_fp64": round(ms64 / ms, 3),
+        "speedup_fp32b_over_fp64": round(ms64 / ms32, 3),
         "sweep_graph": sweep,
         "wall_ms_per_step": round(wall_ms, 4),
     }
@@ -651,19 +749,24 @@ def main():
                                   "kind": "oracle",
                                   "sample": f"first {m} of the {n} tracks, FP64 scalar C, "
                                             f"{cores} threads, wall {t_cpu:.2f} s"}
-        # accuracy of both GPU paths on the oracle's sample
+        # accuracy of every GPU path on the oracle's sample
         from tests.helpers import fp32_errors, param_rel_errors, pulls
         acc = {}
         ptv = np.hypot(o["state"][3], o["state"][4])
-        for name, g in (("fp32b", g32), ("fp32p", g32p), ("fp64", g64)):
+        po = pulls(o["state"], o["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
+        for name, g in (("headline_fp32p", gp), ("fp32b", g32), ("fp64", g64)):
             gs = {k: v[..., :m] for k, v in g.items()}
             e_pos, e_mom = fp32_errors(gs, o, 40.0)
+            e_rel = param_rel_errors(gs, o)
+            c2rel = np.abs(gs["chi2"] - o["chi2"]) / np.maximum(1.0, np.abs(o["chi2"]))
             pg = pulls(gs["state"], gs["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
-            po = pulls(o["state"], o["cov"], sub.truth_pos[-1], sub.truth_mom[-1])
             acc[name] = {"e_pos_max": float(e_pos.max()), "e_mom_max": float(e_mom.max()),
                          "e_mom_p999": float(np.quantile(e_mom, 0.999)),
-                         "e_rel_max": float(param_rel_errors(gs, o).max()),
+                         "e_rel_max": float(e_rel.max()),
                          "tracks_e_mom_above_1e-4": int(np.sum(e_mom > 1e-4)),
+                         "tracks_e_rel_above_1e-4": int(np.sum(e_rel > 1e-4)),
+                         "chi2_rel_err_p9999": float(np.quantile(c2rel, 0.9999)),
+                         "chi2_rel_err_max": float(c2rel.max()),
                          "e_mom_max_by_pt": {f"{lo:g}-{hi:g}": float(e_mom[(ptv >= lo) & (ptv < hi)].max(initial=0.0))
                                              for lo, hi in ((0.5, 2), (2, 10), (10, 30), (30, 100))},
                          "pull_rms_ratio": {kk: round(float(np.sqrt(np.mean(pg[kk] ** 2)) /
@@ -672,17 +775,25 @@ def main():
                          "status_mismatch": int(np.sum(gs["status"].astype(np.uint32) != o["status"]))}
         acc["oracle_pull_rms"] = {kk: round(float(np.sqrt(np.mean(v ** 2))), 4) for kk, v in po.items()}
         result["accuracy_vs_oracle"] = acc
+    del d32, d64, outp, out32, out64, gp, g32, g64
+    ctx.close()
+    torch.cuda.empty_cache()
     if not args.no_build:
         print("[bench] building", file=sys.stderr, flush=True)
         orc = None
         if not args.no_cpu:
             import oracle as orc
         result["building"] = build_measurement(ktf.Context, tg, torch, orc=orc)
+        torch.cuda.empty_cache()
+    if not args.no_uneven:
+        result["uneven_events"] = uneven_summary(ktf, tg, torch, max(3, args.steps // 2))
+        torch.cuda.empty_cache()
     if not args.no_serving:
         print("[bench] serving loop", file=sys.stderr, flush=True)
         rates = [float(r) for r in args.rates.split(",")]
-        result["serving"] = serving_measurement(ktf, tg, args.serve_events, rates)
-    print(json.dumps(result))
+        budgets = [int(b) << 20 for b in args.budgets_mb.split(",")]
+        result["serving"] = serving_measurement(ktf, tg, args.serve_events, rates, budgets)
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":
