@@ -74,7 +74,7 @@ struct BuildArgs {
   int32_t* cinfo[2];       // [S]: event << 1 | (charge > 0) of each dense candidate row
   int32_t* cstart[2];      // [sp]: first dense row of each seed's candidates
   int32_t* sel_parent;     // [S]: per child row, its parent's row
-  int32_t* sel_hit;        // [S]: per child row, the hit it takes as an index into hits (-1: missed layer)
+  int32_t* sel_hit;        // [S]: per child row, the hit it takes as its position among the binned records (-1: missed layer)
   double* sel_chi2;        // [S]: per child row, its chi2 total
   unsigned* ccount;        // [n_layers][kRegions][kCtrStride]: rows used per region after each layer
   void* hb;                // [n_hits] BinHit<TS>: binned coordinates and local index
@@ -88,9 +88,10 @@ struct BuildArgs {
   void* pmom[2];
   void* pcov[2];
   double* rchi;            // [max_cands][S]
-  int32_t* rhit;           // [max_cands][S]: hit index within its (event, layer)
+  int32_t* rhit;           // [max_cands][S]: the hit's index within its (event, layer)
+  int32_t* rpos;           // [max_cands][S]: the hit's position among the binned records
   int32_t* rcount;         // [S]: records, -1 ended (no reach), -2 ended (missed too often)
-  int32_t* hist;           // [L][max_cands][2][sp]
+  int32_t* hist;           // [L][max_cands][2][sp]: (parent rank, hit index)
   int32_t* count;          // [L][sp]
   // best ended candidate per seed
   double* bpos;
@@ -699,10 +700,6 @@ void build_seed_kernel(BuildArgs a) {
 }
 
 // ---------------------------------------------------------------- scoring
-// record key within one parent: (chi2 total, hit index) ascending
-__device__ __forceinline__ bool rec_less(double c1, int32_t h1, double c2, int32_t h2) {
-  return c1 < c2 || (c1 == c2 && (uint32_t)h1 < (uint32_t)h2);
-}
 
 // A child of layer l (row c of the buffer `to`): its parent's propagated
 // state on layer l with the Kalman update of the hit it took (a missed layer
@@ -716,8 +713,9 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
   load_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], a.S, p, x, P);
   int cnh = meta_nh(pm), cnm = meta_nm(pm);
   if (h >= 0) {
-    const TS* hits = static_cast<const TS*>(a.hits);
-    const double m[3] = {(double)hits[h], (double)hits[a.hp + h], (double)hits[2 * a.hp + h]};
+    // the hit's binned record: its coordinates in one load
+    const BinHit<TS> r = static_cast<const BinHit<TS>*>(a.hb)[h];
+    const double m[3] = {(double)r.x, (double)r.y, (double)r.z};
     Residual R;
     residual(x, P, m, hit_res(a), R);  // scored positive definite already
     apply_update(x, P, R, x, P);       // in place
@@ -820,25 +818,33 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   const HitRes hr = hit_res(a);
   // the candidate's sorted record list lives in LDS while the window is
   // scanned (rows [k][blockDim] of the dynamic shared memory: chi2 totals,
-  // then hit indices) and goes to its record rows once complete
+  // hit indices, binned positions) and goes to its record rows once
+  // complete; records rank by (chi2 total, hit index)
   extern __shared__ double rec_lds[];
   const int t = threadIdx.x, B = blockDim.x;
   double* lc = rec_lds;
   int32_t* lh = reinterpret_cast<int32_t*>(rec_lds + NC * B);
+  int32_t* lp = lh + NC * B;
   int nrec = 0;
-  auto insert = [&](double c2, int32_t hid) {
+  auto rec_less = [](double c1, int32_t h1, double c2, int32_t h2) {
+    return c1 < c2 || (c1 == c2 && (uint32_t)h1 < (uint32_t)h2);
+  };
+  auto insert = [&](double c2, int32_t hid, int32_t hpos) {
     if (nrec == NC && !rec_less(c2, hid, lc[(NC - 1) * B + t], lh[(NC - 1) * B + t])) return;
     int pos = nrec < NC ? nrec : NC - 1;
     while (pos > 0 && rec_less(c2, hid, lc[(pos - 1) * B + t], lh[(pos - 1) * B + t])) {
       lc[pos * B + t] = lc[(pos - 1) * B + t];
       lh[pos * B + t] = lh[(pos - 1) * B + t];
+      lp[pos * B + t] = lp[(pos - 1) * B + t];
       --pos;
     }
     lc[pos * B + t] = c2;
     lh[pos * B + t] = hid;
+    lp[pos * B + t] = hpos;
     if (nrec < NC) ++nrec;
   };
-  // each hit's loads are issued before it is scored; score(m0, m1, m2, id)
+  // each hit's loads are issued before it is scored; score(m0, m1, m2,
+  // hit index, binned position)
   auto scan_range = [&](int32_t j0, int32_t j1, auto&& score) {
     if constexpr (sizeof(TS) == 4) {
       // two hits per step, their loads issued together (in double the
@@ -846,13 +852,13 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
       for (int32_t j = j0; j < j1; j += 2) {
         const int64_t h0 = base + j, h1 = base + (j + 1 < j1 ? j + 1 : j);
         const BinHit<TS> r0 = hb[h0], r1 = hb[h1];
-        score((double)r0.x, (double)r0.y, (double)r0.z, r0.id);
-        if (j + 1 < j1) score((double)r1.x, (double)r1.y, (double)r1.z, r1.id);
+        score((double)r0.x, (double)r0.y, (double)r0.z, r0.id, (int32_t)h0);
+        if (j + 1 < j1) score((double)r1.x, (double)r1.y, (double)r1.z, r1.id, (int32_t)h1);
       }
     } else {
       for (int32_t j = j0; j < j1; ++j) {
         const BinHit<TS> r = hb[base + j];
-        score(r.x, r.y, r.z, r.id);
+        score(r.x, r.y, r.z, r.id, (int32_t)(base + j));
       }
     }
   };
@@ -894,23 +900,24 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     double Si[6];
     const double p0 = xp.pos[0], p1 = xp.pos[1], p2 = xp.pos[2];
     if (sym3_inverse(Sc, Si)) {
-      scan_window([&](double m0, double m1, double m2, int32_t hid) {
+      scan_window([&](double m0, double m1, double m2, int32_t hid, int32_t hpos) {
         const double r[3] = {m0 - p0, m1 - p1, m2 - p2};
         const double c2 = quad3(Si, r);
-        if (c2 < cut) insert(pchi2 + c2, hid);
+        if (c2 < cut) insert(pchi2 + c2, hid, hpos);
       });
     }
   } else {
-    scan_window([&](double m0, double m1, double m2, int32_t hid) {
+    scan_window([&](double m0, double m1, double m2, int32_t hid, int32_t hpos) {
       const double m[3] = {m0, m1, m2};
       Residual R;
-      if (residual(xp, Pp, m, hr, R) && R.chi2 < cut) insert(pchi2 + R.chi2, hid);
+      if (residual(xp, Pp, m, hr, R) && R.chi2 < cut) insert(pchi2 + R.chi2, hid, hpos);
     });
   }
   if (nrec == 0) {
     if (meta_nm(meta) < a.g.max_missed) {
       lc[t] = pchi2;
       lh[t] = -1;
+      lp[t] = -1;
       nrec = 1;
     } else {
       a.rcount[c] = -2;
@@ -921,6 +928,7 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   for (int k = 0; k < nrec; ++k) {
     st_nt(a.rchi + (int64_t)k * S + c, lc[k * B + t]);
     st_nt(a.rhit + (int64_t)k * S + c, lh[k * B + t]);
+    st_nt(a.rpos + (int64_t)k * S + c, lp[k * B + t]);
   }
   st_nt(a.rcount + c, (int32_t)nrec);
 }
@@ -961,12 +969,19 @@ constexpr int merge_lanes(int max_cands) { return max_cands <= 4 ? 1 : (max_cand
 constexpr int merge_seeds(int lps) { return kMergeThreads / lps; }
 
 // a record-list head as ranked by the merge: key = 0 for none, else the hit
-// count it gives plus one; pj = parent << 8 | record
+// count it gives plus one; pj = parent << 16 | records in its list << 8 |
+// this record's place in the list
+__device__ __forceinline__ int mpj(int parent, int count, int rec) { return (parent << 16) | (count << 8) | rec; }
+__device__ __forceinline__ int mpj_parent(int pj) { return pj >> 16; }
+__device__ __forceinline__ int mpj_count(int pj) { return (pj >> 8) & 0xff; }
+__device__ __forceinline__ int mpj_rec(int pj) { return pj & 0xff; }
+
 struct MHead {
   int key;
   double c;
   int pj;
-  int hit;
+  int hit;  // index within the (event, layer), -1: missed layer
+  int pos;  // binned position, -1: missed layer
 };
 
 // all terms evaluated (no short circuit), so that the choice compiles to
@@ -974,7 +989,7 @@ struct MHead {
 __device__ __forceinline__ bool mhead_better(const MHead& x, const MHead& y) {
   const bool gt = x.key > y.key, eq = x.key == y.key;
   const bool cl = x.c < y.c, ce = x.c == y.c;
-  const bool pl = (x.pj >> 8) < (y.pj >> 8);
+  const bool pl = x.pj < y.pj;  // the parent decides: parents differ, and they are the top bits
   return gt | (eq & (cl | (ce & pl)));
 }
 
@@ -985,6 +1000,7 @@ __device__ __forceinline__ void mhead_take(MHead& w, const MHead& h) {
   w.c = b ? h.c : w.c;
   w.pj = b ? h.pj : w.pj;
   w.hit = b ? h.hit : w.hit;
+  w.pos = b ? h.pos : w.pos;
 }
 
 // w = the better of w and h where h's parent is known to come after w's
@@ -995,6 +1011,7 @@ __device__ __forceinline__ void mhead_take_later(MHead& w, const MHead& h) {
   w.c = b ? h.c : w.c;
   w.pj = b ? h.pj : w.pj;
   w.hit = b ? h.hit : w.hit;
+  w.pos = b ? h.pos : w.pos;
 }
 
 template <int CTRL>
@@ -1008,7 +1025,7 @@ __device__ __forceinline__ void dpp_take(MHead& h) {
   const MHead o{dpp_i<CTRL>(h.key),
                 __longlong_as_double(((int64_t)dpp_i<CTRL>((int)(cb >> 32)) << 32) |
                                      (uint32_t)dpp_i<CTRL>((int)cb)),
-                dpp_i<CTRL>(h.pj), dpp_i<CTRL>(h.hit)};
+                dpp_i<CTRL>(h.pj), dpp_i<CTRL>(h.hit), dpp_i<CTRL>(h.pos)};
   mhead_take(h, o);
 }
 
@@ -1018,6 +1035,14 @@ template <int LPS>
 __device__ __forceinline__ void group_best(MHead& h) {
   if constexpr (LPS >= 2) dpp_take<0xB1>(h);  // lanes q ^ 1
   if constexpr (LPS == 4) dpp_take<0x4E>(h);  // lanes q ^ 2
+}
+
+// the sum over the group's lanes, in every one of them
+template <int LPS>
+__device__ __forceinline__ int group_sum(int v) {
+  if constexpr (LPS >= 2) v += dpp_i<0xB1>(v);  // lanes q ^ 1
+  if constexpr (LPS == 4) v += dpp_i<0x4E>(v);  // lanes q ^ 2
+  return v;
 }
 
 // the value of the group's first lane
@@ -1032,9 +1057,6 @@ template <typename TS, int LPS, int PPL>
 __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a, int l, int cur) {
   constexpr int SB = merge_seeds(LPS);
   __shared__ int wtot[kMergeThreads / 64 + 1];
-  __shared__ int pick_s[SB][LPS * PPL];  // parent << 8 | record
-  __shared__ int phit_s[SB][LPS * PPL];
-  __shared__ double pchi_s[SB][LPS * PPL];
   const int NC = a.g.max_cands;
   const int tid = threadIdx.x;
   const int q = tid % LPS, ls = tid / LPS;
@@ -1044,17 +1066,23 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   int nlive = 0;
   int64_t pbase = 0;
   int32_t info = 0;
-  int64_t hbase = 0;  // the seed's event's first hit on layer l
   if (real) {  // cstart is only meaningful for a seed with candidates
     nlive = a.count[(int64_t)(l - 1) * sp + s];
     pbase = a.cstart[cur][s];
     const int e = a.sev[s];
     info = pack_info(e, a.q[s]);
-    hbase = a.hit_off[(int64_t)e * a.g.n_layers + l];
   }
-  constexpr int PF = 3;  // records prefetched behind each head
-  int rc[PPL], nh[PPL], hd[PPL], hh[PPL], pre_h[PPL][PF];
-  double pchi[PPL], hc[PPL], pre_c[PPL][PF];
+  // Each parent's head record sits in registers; the records behind it, up
+  // to PF of them, wait in LDS rows [PF][PPL][threads] (one column per
+  // thread: conflict-free however the lanes index them), so that taking a
+  // head replaces only that head's registers instead of shifting a queue
+  // through every slot.  Records beyond PF are read from their rows, rarely.
+  constexpr int PF = 1;
+  __shared__ double qc_s[PF * PPL][kMergeThreads];
+  __shared__ int qh_s[PF * PPL][kMergeThreads];
+  __shared__ int qp_s[PF * PPL][kMergeThreads];
+  int rc[PPL], nh[PPL], hd[PPL], hh[PPL], hp[PPL];
+  double pchi[PPL], hc[PPL];
 #pragma unroll
   for (int u = 0; u < PPL; ++u) {
     const int j = q + LPS * u;
@@ -1065,38 +1093,35 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     pchi[u] = 0.0;
     hc[u] = 0.0;
     hh[u] = -1;
+    hp[u] = -1;
     if (j < nlive) {  // record 0 is read with the count and used only if rc > 0
       rc[u] = a.rcount[p];
       nh[u] = meta_nh(a.cmeta[cur][p]);
       pchi[u] = a.cchi2[cur][p];
       hc[u] = a.rchi[p];
       hh[u] = a.rhit[p];
+      hp[u] = a.rpos[p];
     }
   }
 #pragma unroll
   for (int u = 0; u < PPL; ++u) {
     const int64_t p = pbase + q + LPS * u;
-    if (rc[u] > 1) {
 #pragma unroll
-      for (int v = 0; v < PF; ++v) {
-        const int64_t ri = (int64_t)min(v + 1, rc[u] - 1) * S + p;
-        pre_c[u][v] = a.rchi[ri];
-        pre_h[u][v] = a.rhit[ri];
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < PF; ++v) {
-        pre_c[u][v] = 0.0;
-        pre_h[u][v] = -1;
+    for (int v = 0; v < PF; ++v) {
+      if (v + 1 < rc[u]) {
+        const int64_t ri = (int64_t)(v + 1) * S + p;
+        qc_s[v * PPL + u][tid] = a.rchi[ri];
+        qh_s[v * PPL + u][tid] = a.rhit[ri];
+        qp_s[v * PPL + u][tid] = a.rpos[ri];
       }
     }
   }
   // best ended parent (the same in all the seed's lanes)
-  MHead eb{0, 0.0, 0, 0};
+  MHead eb{0, 0.0, 0, 0, 0};
 #pragma unroll
   for (int u = 0; u < PPL; ++u) {
     const int j = q + LPS * u;
-    const MHead h{(j < nlive && rc[u] <= 0) ? nh[u] + 1 : 0, pchi[u], j << 8, 0};
+    const MHead h{(j < nlive && rc[u] <= 0) ? nh[u] + 1 : 0, pchi[u], mpj(j, 0, 0), 0, 0};
     if (u == 0)
       eb = h;
     else
@@ -1104,7 +1129,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   }
   group_best<LPS>(eb);
   if (eb.key > 0) {
-    const int e_nh = eb.key - 1, ej = eb.pj >> 8;
+    const int e_nh = eb.key - 1, ej = mpj_parent(eb.pj);
     const int be = a.bend[s];
     if (be < 0 || final_less(e_nh, eb.c, l, ej, meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s])) {
       // the seed's lanes copy the ended candidate element by element
@@ -1136,55 +1161,13 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   int hk[PPL];
 #pragma unroll
   for (int u = 0; u < PPL; ++u) hk[u] = rc[u] > 0 ? nh[u] + (hh[u] >= 0 ? 1 : 0) + 1 : 0;
-  int nsel = 0;
-  for (int k = 0; k < NC; ++k) {
-    MHead w{hk[0], hc[0], (q << 8) | hd[0], hh[0]};
+  // the seed keeps min(max_cands, records of all its parents) children: its
+  // rows of the next buffer are reserved before the picks, which then go
+  // straight to them
+  int nrec_lane = 0;
 #pragma unroll
-    for (int u = 1; u < PPL; ++u) {
-      mhead_take_later(w, MHead{hk[u], hc[u], ((q + LPS * u) << 8) | hd[u], hh[u]});
-    }
-    group_best<LPS>(w);
-    if (w.key == 0) break;  // uniform over the seed's lanes
-    if (q == 0) {
-      pick_s[ls][k] = w.pj;
-      phit_s[ls][k] = w.hit;
-      pchi_s[ls][k] = w.c;
-    }
-    // the owner lane advances that parent's head (selects, not branches;
-    // records beyond the prefetched ones are loaded, rarely)
-    const int wj = w.pj >> 8;
-    int nxw = 0;  // the owner lane's next record, where its list has one
-#pragma unroll
-    for (int u = 0; u < PPL; ++u) {
-      const bool adv = wj == q + LPS * u;
-      const int nx = hd[u] + 1;
-      const bool more = nx < rc[u];
-      nxw = adv && more ? nx : nxw;
-      // the prefetched records move up one place
-      hd[u] = adv ? nx : hd[u];
-      hc[u] = adv ? pre_c[u][0] : hc[u];
-      hh[u] = adv ? pre_h[u][0] : hh[u];
-#pragma unroll
-      for (int v = 0; v + 1 < PF; ++v) {
-        pre_c[u][v] = adv ? pre_c[u][v + 1] : pre_c[u][v];
-        pre_h[u][v] = adv ? pre_h[u][v + 1] : pre_h[u][v];
-      }
-      hk[u] = adv && !more ? 0 : hk[u];
-    }
-    if (nxw > PF) {  // a record beyond the prefetched ones
-      const int64_t far = (int64_t)nxw * S + pbase + wj;
-      const double fc = a.rchi[far];
-      const int fh = a.rhit[far];
-#pragma unroll
-      for (int u = 0; u < PPL; ++u) {
-        if (wj == q + LPS * u) {
-          hc[u] = fc;
-          hh[u] = fh;
-        }
-      }
-    }
-    ++nsel;
-  }
+  for (int u = 0; u < PPL; ++u) nrec_lane += rc[u] > 0 ? rc[u] : 0;
+  const int nsel = min(NC, group_sum<LPS>(nrec_lane));
   const int reg = block_region();
   const int local = (int)block_reserve(region_ctr(a, l, reg), q == 0 ? nsel : 0, wtot);
   const int64_t first = reg * a.RS + group_first<LPS>(local);
@@ -1192,18 +1175,48 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     a.count[(int64_t)l * sp + s] = nsel;
     if (nsel > 0) a.cstart[cur ^ 1][s] = (int32_t)first;
   }
-  for (int k = q; k < nsel; k += LPS) {
-    const int pk = pick_s[ls][k];
-    a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = pk >> 8;
-    a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = phit_s[ls][k];
-    const int32_t h = phit_s[ls][k];
-    a.sel_parent[first + k] = (int32_t)(pbase + (pk >> 8));
-    a.sel_hit[first + k] = h >= 0 ? (int32_t)(hbase + h) : -1;
-    a.sel_chi2[first + k] = pchi_s[ls][k];
-    a.cinfo[cur ^ 1][first + k] = info;
+  for (int k = 0; k < nsel; ++k) {
+    MHead w{hk[0], hc[0], mpj(q, rc[0], hd[0]), hh[0], hp[0]};
+#pragma unroll
+    for (int u = 1; u < PPL; ++u) {
+      mhead_take_later(w, MHead{hk[u], hc[u], mpj(q + LPS * u, rc[u], hd[u]), hh[u], hp[u]});
+    }
+    group_best<LPS>(w);
+    if (q == 0) {  // the seed's k-th child: its parent, hit and chi2 total
+      a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = mpj_parent(w.pj);
+      a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = w.hit;
+      a.sel_parent[first + k] = (int32_t)(pbase + mpj_parent(w.pj));
+      a.sel_hit[first + k] = w.pos;
+      a.sel_chi2[first + k] = w.c;
+      a.cinfo[cur ^ 1][first + k] = info;
+    }
+    // the owner lane replaces the taken head by the next record of its list
+    // (selects, not branches; a record beyond the LDS ones is loaded, rarely)
+    const int wj = mpj_parent(w.pj);
+    const int us = wj / LPS;               // the winner's slot in its owner lane
+    const int nx = mpj_rec(w.pj) + 1;      // the next record of its list
+    const bool more = nx < mpj_count(w.pj);
+    const int vq = nx - 1 < PF ? nx - 1 : PF - 1;
+    double ncv = qc_s[vq * PPL + us][tid];
+    int nhv = qh_s[vq * PPL + us][tid];
+    int npv = qp_s[vq * PPL + us][tid];
+    if (more && nx > PF && wj % LPS == q) {
+      const int64_t far = (int64_t)nx * S + pbase + wj;
+      ncv = a.rchi[far];
+      nhv = a.rhit[far];
+      npv = a.rpos[far];
+    }
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+      const bool adv = wj == q + LPS * u;
+      hd[u] = adv ? nx : hd[u];
+      hc[u] = adv ? ncv : hc[u];
+      hh[u] = adv ? nhv : hh[u];
+      hp[u] = adv ? npv : hp[u];
+      hk[u] = adv && !more ? 0 : hk[u];
+    }
   }
 }
-
 // ------------------------------------------------------------------ final
 // The seed's final choice: the best survivor or the best ended candidate.
 // LAZY: the survivors are the last layer's children, not yet made, ranked
@@ -1249,7 +1262,7 @@ __device__ __forceinline__ FinalChoice final_choice(const BuildArgs& a, int cur,
 // records back from its end layer.  A kernel of its own: the walk is a
 // chain of dependent loads, which wants many waves in flight, while making
 // the chosen child needs the registers of a Kalman update.
-template <bool LAZY>
+template <typename TS, bool LAZY>
 __global__ __launch_bounds__(256) void build_backtrack_kernel(BuildArgs a, int cur) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n_seeds) return;
@@ -1377,7 +1390,7 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   int cur = 0;
   // the score kernel's record lists in LDS: max_cands chi2 totals and hit
   // indices per thread
-  const size_t rec_lds = (size_t)a.g.max_cands * bs * (sizeof(double) + sizeof(int32_t));
+  const size_t rec_lds = (size_t)a.g.max_cands * bs * (sizeof(double) + 2 * sizeof(int32_t));
   const dim3 rows((unsigned)(kRegions * ((a.RS / bs + kRowChunks - 1) / kRowChunks)));
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     const bool child = l > a.g.n_seed_layers;  // candidates kept on layer l - 1, not yet made
@@ -1393,10 +1406,10 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
     cur ^= 1;
   }
   if (a.g.n_layers > a.g.n_seed_layers) {  // the last layer's children are made for the chosen one only
-    hipLaunchKernelGGL((build_backtrack_kernel<true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
+    hipLaunchKernelGGL((build_backtrack_kernel<TS, true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
     hipLaunchKernelGGL((build_final_kernel<TS, TP, true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
   } else {
-    hipLaunchKernelGGL((build_backtrack_kernel<false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
+    hipLaunchKernelGGL((build_backtrack_kernel<TS, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
     hipLaunchKernelGGL((build_final_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
   }
   return hipGetLastError();
@@ -1540,12 +1553,14 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.sel_chi2 = reinterpret_cast<double*>(p);
   }
   const int NC = cfg.max_cands;
-  if ((e = c->b_rec.ensure((size_t)S * (NC * 12 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
+  if ((e = c->b_rec.ensure((size_t)S * (NC * 16 + 4))) != hipSuccess) return hip_fail(c, e, "record workspace");
   {
     char* p = static_cast<char*>(c->b_rec.p);
     a.rchi = reinterpret_cast<double*>(p);
     p += (size_t)S * NC * 8;
     a.rhit = reinterpret_cast<int32_t*>(p);
+    p += (size_t)S * NC * 4;
+    a.rpos = reinterpret_cast<int32_t*>(p);
     p += (size_t)S * NC * 4;
     a.rcount = reinterpret_cast<int32_t*>(p);
   }

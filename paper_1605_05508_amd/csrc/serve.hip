@@ -123,7 +123,7 @@ static size_t footprint_of(const ktf_config& cfg, int64_t n, int64_t nh, ktf_pre
   // candidate rows: max_cands per seed plus the slack of the 64 row regions
   // per row: two candidate buffers, two propagated-state buffers, records,
   // the row lists (seed x2, parent, hit) and the child chi2
-  const size_t per_row = 2 * (24 + 24 * ts + 12) + 2 * (24 + 24 * ts) + 12 * NC + 4 + 16 + 8;
+  const size_t per_row = 2 * (24 + 24 * ts + 12) + 2 * (24 + 24 * ts) + 16 * NC + 4 + 16 + 8;
   const size_t rows = (size_t)n * NC + 64 * 257;
   const size_t per_seed_ws = L * NC * 8 + L * 4 + (24 + 24 * ts + 20) + 8;
   const size_t per_seed_fit = L * (3 * ts + 1) + 27 * ts + 16 + L * 4;
