@@ -99,6 +99,7 @@ def parse():
                          "fit at scale through layer material; shapes: the fit's time per "
                          "launch shape and its throughput from 1e3 to 1e7 tracks")
     ap.add_argument("--no-build", action="store_true", help="skip the building measurement")
+    ap.add_argument("--seed-order", type=int, default=0, help="--profile build: the library's seed order (1) or not (0)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-events", type=int, default=500)
     ap.add_argument("--rates", type=str, default="200,500,1000,2000")
@@ -271,6 +272,16 @@ def build_measurement(ctx_cls, tg, torch, reps=5, orc=None, bs=None, precs=("fp3
             out["fp32b_eta_order"] = {"ms": round(mse, 3), "seeds_per_s": round(bs.n_seeds / (mse * 1e-3)),
                                       "eta_bins": 21, "same_hits_as_generation_order": bool(np.array_equal(hite, hit))}
             del de, oe
+            # the library's seed order: seeds sorted by their predicted cell on
+            # the first building layer, each wave's window box staged in LDS
+            ctx2 = ctx_cls.for_detector(bs.det, seed_order=1)
+            o2 = ctx2.build(d)
+            ms2 = time_build(ctx2, d, o2, reps, torch)
+            hit2 = o2["hit_idx"].cpu().numpy()[:, :bs.n_seeds]
+            out["fp32b_seed_order"] = {"ms": round(ms2, 3), "seeds_per_s": round(bs.n_seeds / (ms2 * 1e-3)),
+                                       "same_hits": bool(np.array_equal(hit2, hit))}
+            del o2
+            ctx2.close()
         del d, o
     if "fp32b" in hits_by_prec and "fp64" in hits_by_prec:
         # the FP64 build equals the oracle's bit for bit (tests); FP32 bulk
@@ -488,7 +499,7 @@ def profile_run(args):
         print(json.dumps({"ms_per_step": ms, "n": fs.n}))
         return
     bs = tg.config3()
-    ctx = ktf.Context.for_detector(bs.det)
+    ctx = ktf.Context.for_detector(bs.det, seed_order=args.seed_order)
     d = build_inputs(bs, "fp32b")
     o = ctx.build(d)
     run = lambda: ctx.build(d, out=o)

@@ -113,6 +113,15 @@ typedef struct {
                               normal incidence, >= 0; NULL = no material       */
   double eloss_per_x0;     /* mean energy loss per radiation length (GeV), >= 0 */
   double mass;             /* particle mass hypothesis (GeV), > 0 when material */
+  /* Building: 1 = work on each event's seeds sorted by where their helix
+   * meets the first building layer (a Z-order curve over 256 x 32 phi-z
+   * cells), so that a wave's candidates search neighbouring hit bins, and
+   * stage each wave's box of bins in LDS (the paper's spatial partition of
+   * the hits, Sec. 3, with data loaded into local caches, Sec. 3.1); the
+   * outputs are returned in the caller's order.  0 = the caller's order,
+   * every window read from the binned hits in memory.  Results are the same
+   * either way. */
+  int32_t seed_order;
 } ktf_config;
 
 /* Create a context on the current HIP device.  Returns KTF_EINVAL for an

@@ -209,7 +209,7 @@ int ktf_destroy(ktf_ctx* c) {
   c->fit_pos.release();
   c->counters.release();
   for (DevBuf* b : {&c->b_off, &c->b_perm, &c->b_binned, &c->b_cand[0], &c->b_cand[1], &c->b_prop,
-                    &c->b_rec, &c->b_hist, &c->b_best, &c->b_misc, &c->b_stage, &c->b_list})
+                    &c->b_rec, &c->b_hist, &c->b_best, &c->b_misc, &c->b_stage, &c->b_list, &c->b_sort})
     b->release();
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->build_done) (void)hipEventDestroy(c->build_done);

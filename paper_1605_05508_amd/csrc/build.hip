@@ -64,6 +64,27 @@ struct BuildArgs {
   const void* seed_cov;    // [21][sp]
   const int8_t* q;         // [sp]
   const int32_t* seed_hit; // [nsl][sp]
+  // seed order: building works on the seeds of each event sorted by their
+  // predicted phi bin at the first building layer (neighbouring rows then
+  // search neighbouring hit bins); the seed arrays above are copies in that
+  // order, the caller's are src_*, and the outputs go back through order
+  const void* src_state;   // [6][sp] as the caller gave them
+  const void* src_cov;     // [21][sp]
+  const int8_t* src_q;     // [sp]
+  const int32_t* src_seed_hit; // [nsl][sp]
+  int32_t* skey;           // [sp]: sort key of each (caller's) seed
+  int32_t* order;          // [sp]: the caller's index of the seed at each sorted place
+  int32_t* rank;           // [sp]: the sorted place of each caller's seed
+  int32_t n_keys;          // values of the sort key
+  int32_t seed_order;      // 1: seeds sorted and window boxes staged in LDS, 0: the caller's order
+  int32_t* u_hit;          // caller's outputs: [L][sp]
+  void* u_state;           // [6][sp]
+  void* u_cov;             // [21][sp]
+  double* u_chi2;
+  int32_t* u_nhits;
+  uint32_t* u_status;
+  int32_t* u_hist;         // optional [L][max_cands][2][sp]
+  int32_t* u_count;        // optional [L][sp]
   // binning
   int32_t* bin_off;        // [n_groups][n_bins+1]
   int32_t* bin_cur;        // [n_groups][n_bins]
@@ -448,6 +469,144 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
   }
 }
 
+// ------------------------------------------------------------ seed order
+// Workgroups are dealt to the chip's eight XCDs in turn, each XCD with its
+// own L2.  A kernel whose neighbouring blocks share data (one event's seed
+// rows) maps block b to a logical block so that every XCD takes one
+// contiguous eighth of the logical blocks; the grid is rounded up to a
+// multiple of eight and the logical blocks beyond nb do nothing.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t nb) {
+  const int64_t per = (nb + kXcds - 1) / kXcds;
+  return (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+static inline unsigned xcd_grid(int64_t nb) { return (unsigned)((nb + kXcds - 1) / kXcds * kXcds); }
+
+// Sort key of every seed (the caller's order): where the seed's helix
+// meets the first building layer (or the seed itself, if it does not reach
+// it), as a cell of 256 (phi) x 32 (z) over the layer, the cells numbered
+// along a Z-order (Morton) curve so that seeds close in the order are close
+// in both phi and z.
+template <typename TS, typename TP>
+__global__ void seed_key_kernel(BuildArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  const TS* st = static_cast<const TS*>(a.src_state);
+  TrackState<TP> x, xo;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.pos[c] = (double)st[c * a.sp + s];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x.mom[c] = (TP)st[(c + 3) * a.sp + s];
+  const TP k = (TP)(kCLight * (a.src_q[s] > 0 ? 1.0 : -1.0) * a.g.bz);
+  Jac<TP> F;
+  const int lb = a.g.n_seed_layers < a.g.n_layers ? a.g.n_seed_layers : a.g.n_layers - 1;
+  double px = x.pos[0], py = x.pos[1], pz = x.pos[2];
+  if (propagate<TP, BuildNewton<TP>::n>(x, k, a.g.radii[lb], false, xo, F)) {
+    px = xo.pos[0];
+    py = xo.pos[1];
+    pz = xo.pos[2];
+  }
+  int cp = (int)((atan2f((float)py, (float)px) + (float)kPi) * (float)(256.0 / (2.0 * kPi)));
+  int cz = (int)floor((pz + a.g.z_half) * (32.0 / (2.0 * a.g.z_half)));
+  cp = cp < 0 ? 0 : (cp > 255 ? 255 : cp);
+  cz = cz < 0 ? 0 : (cz > 31 ? 31 : cz);
+  int key = 0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) key |= (((cz >> b) & 1) << (2 * b)) | (((cp >> b) & 1) << (2 * b + 1));
+  key |= (cp >> 5) << 10;
+  a.skey[s] = key;
+}
+
+// One block per event: its seeds' sorted places by a counting sort on the
+// key (the order within a key is whatever the atomics give: rows may land
+// anywhere, a seed's result does not depend on its row).
+constexpr int kOrderThreads = 1024;
+constexpr int kMaxKeys = 8192;
+__global__ __launch_bounds__(kOrderThreads) void seed_order_kernel(BuildArgs a) {
+  __shared__ int32_t cnt[kMaxKeys];
+  __shared__ int32_t wsum[kOrderThreads / 64];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int64_t lo = a.seed_off[e], hi = a.seed_off[e + 1];
+  const int nk = a.n_keys;
+  for (int b = tid; b < nk; b += kOrderThreads) cnt[b] = 0;
+  __syncthreads();
+  for (int64_t i = lo + tid; i < hi; i += kOrderThreads) atomicAdd(&cnt[a.skey[i]], 1);
+  __syncthreads();
+  // exclusive scan: each thread a contiguous run of keys, then the block
+  const int per = (nk + kOrderThreads - 1) / kOrderThreads;
+  const int b0 = min(nk, tid * per), b1 = min(nk, b0 + per);
+  int32_t sum = 0;
+  for (int b = b0; b < b1; ++b) sum += cnt[b];
+  const int lane = tid & 63, wave = tid >> 6;
+  int32_t x = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int32_t run = x - sum;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+  for (int b = b0; b < b1; ++b) {
+    const int32_t v = cnt[b];
+    cnt[b] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (int64_t i = lo + tid; i < hi; i += kOrderThreads) {
+    const int32_t pos = atomicAdd(&cnt[a.skey[i]], 1);
+    a.order[lo + pos] = (int32_t)i;
+    a.rank[i] = (int32_t)(lo + pos);
+  }
+}
+
+// the seed inputs in sorted order (reads within each event's rows, which
+// stay in one XCD's L2)
+template <typename TS>
+__global__ void seed_gather_kernel(BuildArgs a) {
+  const int64_t i = xcd_block((a.n_seeds + blockDim.x - 1) / blockDim.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n_seeds) return;
+  const int64_t s = a.order[i];
+  const TS* st = static_cast<const TS*>(a.src_state);
+  const TS* cv = static_cast<const TS*>(a.src_cov);
+  TS* dst = static_cast<TS*>(const_cast<void*>(a.seed_state));
+  TS* dcv = static_cast<TS*>(const_cast<void*>(a.seed_cov));
+#pragma unroll
+  for (int c = 0; c < 6; ++c) dst[c * a.sp + i] = st[c * a.sp + s];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) dcv[c * a.sp + i] = cv[c * a.sp + s];
+  const_cast<int8_t*>(a.q)[i] = a.src_q[s];
+  for (int l = 0; l < a.g.n_seed_layers; ++l)
+    const_cast<int32_t*>(a.seed_hit)[l * a.sp + i] = a.src_seed_hit[l * a.sp + s];
+}
+
+// the outputs back to the caller's order: one lane per caller seed, so the
+// writes are coalesced and the reads stay within the event's sorted rows
+template <typename TS>
+__global__ void seed_scatter_kernel(BuildArgs a) {
+  const int64_t s = xcd_block((a.n_seeds + blockDim.x - 1) / blockDim.x) * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  const int64_t i = a.rank[s], sp = a.sp;
+  const int L = a.g.n_layers, NC = a.g.max_cands;
+  for (int l = 0; l < L; ++l) a.u_hit[l * sp + s] = a.o_hit[l * sp + i];
+  const TS* st = static_cast<const TS*>(a.o_state);
+  const TS* cv = static_cast<const TS*>(a.o_cov);
+  TS* ust = static_cast<TS*>(a.u_state);
+  TS* ucv = static_cast<TS*>(a.u_cov);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) ust[c * sp + s] = st[c * sp + i];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) ucv[c * sp + s] = cv[c * sp + i];
+  a.u_chi2[s] = a.o_chi2[i];
+  a.u_nhits[s] = a.o_nhits[i];
+  a.u_status[s] = a.o_status[i];
+  if (a.u_count)
+    for (int l = 0; l < L; ++l) a.u_count[l * sp + s] = a.count[l * sp + i];
+  if (a.u_hist)
+    for (int64_t r = 0; r < (int64_t)L * NC * 2; ++r) a.u_hist[r * sp + s] = a.hist[r * sp + i];
+}
+
 // event of every seed, once per build
 __global__ void seed_event_kernel(BuildArgs a) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -700,6 +859,24 @@ void build_seed_kernel(BuildArgs a) {
 }
 
 // ---------------------------------------------------------------- scoring
+// A wave's LDS area for staging its window box: 8 reduction words, the
+// box's offsets (rows x (bins + 1)), the start of each row's hits and
+// their total, then the hits (about 5.4 KB per wave in float, 6.9 KB in
+// double).
+template <typename TS> struct StageArea {
+  static constexpr int offs = 512, rows = 64;
+  static constexpr int hits = sizeof(TS) == 4 ? 192 : 96;
+  static constexpr size_t bytes = (size_t)(8 + offs + rows + 8) * 4 + (size_t)hits * sizeof(BinHit<TS>);
+};
+
+// LDS written by some lanes of a wave and read by others: the wave's LDS
+// operations are processed in order, so the compiler must only keep them
+// in program order
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 
 // A child of layer l (row c of the buffer `to`): its parent's propagated
 // state on layer l with the Kalman update of the hit it took (a missed layer
@@ -734,7 +911,7 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
 // (The child variants are held to three waves per SIMD: left alone they
 // take a few registers over that budget and run at two, which costs more
 // than the few registers the cap spills in double.)
-template <typename TS, typename TP, bool MAT, bool CHILD>
+template <typename TS, typename TP, bool MAT, bool CHILD, bool STAGE>
 __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, int64_t c) {
   const int32_t info = ld_nt(a.cinfo[cur] + c);
   const int L = a.g.n_layers, NC = a.g.max_cands;
@@ -875,7 +1052,91 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
       hi1 = a1 - nphi;
     }
   }
+  // Staging (seed order on): the wave's candidates come from neighbouring
+  // seeds, so the union of their windows is a small box of bins; the wave
+  // copies the box's offsets and binned hits into its own LDS area once,
+  // and every lane scans its window there.  The wave works alone (its LDS
+  // operations are in order; no barrier), with the lanes that reached this
+  // point (the others ended).  A box that wraps in phi, spans two events
+  // or exceeds the area falls back to the global scan below.
+  bool staged = false;
+  int32_t* s_off = nullptr;
+  int32_t* s_row = nullptr;
+  BinHit<TS>* s_hit = nullptr;
+  int s_z0 = 0, s_p0 = 0, s_per = 0;
+  if constexpr (STAGE) {
+    char* wa = reinterpret_cast<char*>(rec_lds + NC * B) + (size_t)NC * B * 2 * sizeof(int32_t) +
+               (size_t)(threadIdx.x >> 6) * StageArea<TS>::bytes;
+    int32_t* red = reinterpret_cast<int32_t*>(wa);
+    s_off = red + 8;
+    s_row = s_off + StageArea<TS>::offs;
+    s_hit = reinterpret_cast<BinHit<TS>*>(s_row + StageArea<TS>::rows + 8);
+    const uint64_t act = __ballot(1);
+    const int nact = __popcll(act);
+    const int rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    if (rk == 0) {
+      red[0] = INT32_MAX;
+      red[1] = INT32_MIN;
+      red[2] = INT32_MAX;
+      red[3] = INT32_MIN;
+      red[4] = INT32_MAX;
+      red[5] = INT32_MIN;
+    }
+    wave_sync();
+    atomicMin(&red[0], zlo);
+    atomicMax(&red[1], zhi);
+    atomicMin(&red[2], full_phi ? -1 : plo);
+    atomicMax(&red[3], full_phi ? nphi : phi_hi);
+    atomicMin(&red[4], g);
+    atomicMax(&red[5], g);
+    wave_sync();
+    const int z0 = red[0], z1 = red[1], p0 = red[2], p1 = red[3];
+    const int nrows = z1 - z0 + 1, per = p1 - p0 + 2;  // a row: the box's bins and the end of the last
+    staged = red[4] == red[5] && p0 >= 0 && p1 < nphi && nrows <= StageArea<TS>::rows &&
+             nrows * per <= StageArea<TS>::offs;
+    if (staged) {
+      for (int i = rk; i < nrows * per; i += nact) {
+        const int r = i / per;
+        s_off[i] = off[(z0 + r) * nphi + p0 + (i - r * per)];
+      }
+      wave_sync();
+      if (rk == 0) {  // where each row's hits start in the area, and their total
+        int tot = 0;
+        for (int r = 0; r < nrows; ++r) {
+          s_row[r] = tot;
+          tot += s_off[r * per + per - 1] - s_off[r * per];
+        }
+        s_row[nrows] = tot;
+      }
+      wave_sync();
+      staged = s_row[nrows] <= StageArea<TS>::hits;
+      if (staged) {
+        for (int r = 0; r < nrows; ++r) {
+          const int32_t g0 = s_off[r * per], n = s_off[r * per + per - 1] - g0, b = s_row[r];
+          for (int j = rk; j < n; j += nact) s_hit[b + j] = hb[base + g0 + j];
+        }
+        wave_sync();
+      }
+    }
+    s_z0 = z0;
+    s_p0 = p0;
+    s_per = per;
+  }
   auto scan_window = [&](auto&& score) {
+    if constexpr (STAGE) {
+      if (staged) {  // the lane's window lies in the box: one run per row
+        for (int zb = zlo; zb <= zhi; ++zb) {
+          const int32_t* ro = s_off + (zb - s_z0) * s_per;
+          const int32_t j0 = ro[lo0 - s_p0], j1 = ro[hi0 + 1 - s_p0];
+          const int32_t sh = s_row[zb - s_z0] - ro[0];  // area place of the row's hit j: sh + j
+          for (int32_t j = j0; j < j1; ++j) {
+            const BinHit<TS> r = s_hit[sh + j];
+            score((double)r.x, (double)r.y, (double)r.z, r.id, (int32_t)(base + j));
+          }
+        }
+        return;
+      }
+    }
     // the next row's first run is looked up while this row's hits are scored
     int32_t nj0 = off[zlo * nphi + lo0], nj1 = off[zlo * nphi + hi0 + 1];
     for (int zb = zlo; zb <= zhi; ++zb) {
@@ -933,10 +1194,10 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   st_nt(a.rcount + c, (int32_t)nrec);
 }
 
-template <typename TS, typename TP, bool MAT, bool CHILD>
+template <typename TS, typename TP, bool MAT, bool CHILD, bool STAGE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHILD ? 3 : 1)))
 void build_score_kernel(BuildArgs a, int l, int cur) {
-  ROW_CHUNKS(a, l - 1, (score_row<TS, TP, MAT, CHILD>(a, l, cur, c)));
+  ROW_CHUNKS(a, l - 1, (score_row<TS, TP, MAT, CHILD, STAGE>(a, l, cur, c)));
 }
 
 // ----------------------------------------------------------------- select
@@ -1336,6 +1597,19 @@ static int64_t region_rows(int64_t n_seeds, int nc) {
   return (r + 255) / 256 * 256;
 }
 
+template <typename TS, typename TP, bool STAGE>
+static void launch_score(const BuildArgs& a, int l, int cur, bool child, dim3 rows, size_t lds, hipStream_t st) {
+  const dim3 blk(256);
+  if (a.g.mat.on && child)
+    hipLaunchKernelGGL((build_score_kernel<TS, TP, true, true, STAGE>), rows, blk, lds, st, a, l, cur);
+  else if (a.g.mat.on)
+    hipLaunchKernelGGL((build_score_kernel<TS, TP, true, false, STAGE>), rows, blk, lds, st, a, l, cur);
+  else if (child)
+    hipLaunchKernelGGL((build_score_kernel<TS, TP, false, true, STAGE>), rows, blk, lds, st, a, l, cur);
+  else
+    hipLaunchKernelGGL((build_score_kernel<TS, TP, false, false, STAGE>), rows, blk, lds, st, a, l, cur);
+}
+
 template <typename TS, int LPS, int PPL>
 static void launch_merge_as(const BuildArgs& a, int l, int cur, hipStream_t st) {
   const dim3 grid(nblk(a.n_seeds, merge_seeds(LPS))), block(kMergeThreads);
@@ -1382,6 +1656,11 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   const int64_t nctr = (int64_t)a.g.n_layers * kRegions * kCtrStride;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nctr, bs)), dim3(bs), 0, st, reinterpret_cast<int32_t*>(a.ccount),
                      nctr, 0);
+  if (a.seed_order) {  // the seeds of each event in order of their predicted cell
+    hipLaunchKernelGGL((seed_key_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
+    hipLaunchKernelGGL(seed_order_kernel, dim3(a.n_events), dim3(kOrderThreads), 0, st, a);
+    hipLaunchKernelGGL((seed_gather_kernel<TS>), dim3(xcd_grid(nblk(a.n_seeds, bs))), dim3(bs), 0, st, a);
+  }
   hipLaunchKernelGGL(seed_event_kernel, dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
   if (a.g.mat.on)
     hipLaunchKernelGGL((build_seed_kernel<TS, TP, true>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
@@ -1390,18 +1669,15 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   int cur = 0;
   // the score kernel's record lists in LDS: max_cands chi2 totals and hit
   // indices per thread
-  const size_t rec_lds = (size_t)a.g.max_cands * bs * (sizeof(double) + 2 * sizeof(int32_t));
+  const size_t rec_lds = (size_t)a.g.max_cands * bs * (sizeof(double) + 2 * sizeof(int32_t)) +
+                         (a.seed_order ? (size_t)(bs / 64) * StageArea<TS>::bytes : 0);
   const dim3 rows((unsigned)(kRegions * ((a.RS / bs + kRowChunks - 1) / kRowChunks)));
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     const bool child = l > a.g.n_seed_layers;  // candidates kept on layer l - 1, not yet made
-    if (a.g.mat.on && child)
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, true>), rows, dim3(bs), rec_lds, st, a, l, cur);
-    else if (a.g.mat.on)
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, true, false>), rows, dim3(bs), rec_lds, st, a, l, cur);
-    else if (child)
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, true>), rows, dim3(bs), rec_lds, st, a, l, cur);
+    if (a.seed_order)
+      launch_score<TS, TP, true>(a, l, cur, child, rows, rec_lds, st);
     else
-      hipLaunchKernelGGL((build_score_kernel<TS, TP, false, false>), rows, dim3(bs), rec_lds, st, a, l, cur);
+      launch_score<TS, TP, false>(a, l, cur, child, rows, rec_lds, st);
     launch_merge<TS>(a, l, cur, st);
     cur ^= 1;
   }
@@ -1412,6 +1688,8 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
     hipLaunchKernelGGL((build_backtrack_kernel<TS, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
     hipLaunchKernelGGL((build_final_kernel<TS, TP, false>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a, cur);
   }
+  if (a.seed_order)
+    hipLaunchKernelGGL((seed_scatter_kernel<TS>), dim3(xcd_grid(nblk(a.n_seeds, bs))), dim3(bs), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1585,6 +1863,37 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     p += (size_t)sp * 4;
     a.sev = reinterpret_cast<int32_t*>(p);
   }
+  a.seed_order = cfg.seed_order != 0 ? 1 : 0;
+  if (a.seed_order) {
+    // the seeds in sorted order (inputs and outputs), the key and the order
+    const size_t NSL = (size_t)cfg.n_seed_layers;
+    const size_t sort_bytes = (size_t)sp * (27 * ts + 1 + 4 * NSL + 4 + 4) + (size_t)sp * (4 * L + 27 * ts + 8 + 4 + 4 + 4) + 16 * 256;  // 15 pieces, each rounded up to 256 bytes
+    if ((e = c->b_sort.ensure(sort_bytes)) != hipSuccess) return hip_fail(c, e, "seed order workspace");
+    char* p = static_cast<char*>(c->b_sort.p);
+    auto take = [&](size_t bytes) {
+      char* r = p;
+      p += (bytes + 255) / 256 * 256;
+      return r;
+    };
+    a.src_state = a.seed_state;
+    a.src_cov = a.seed_cov;
+    a.src_q = a.q;
+    a.src_seed_hit = a.seed_hit;
+    a.seed_state = take((size_t)sp * 6 * ts);
+    a.seed_cov = take((size_t)sp * 21 * ts);
+    a.seed_hit = reinterpret_cast<int32_t*>(take((size_t)sp * 4 * NSL));
+    a.skey = reinterpret_cast<int32_t*>(take((size_t)sp * 4));
+    a.order = reinterpret_cast<int32_t*>(take((size_t)sp * 4));
+    a.rank = reinterpret_cast<int32_t*>(take((size_t)sp * 4));
+    a.o_hit = reinterpret_cast<int32_t*>(take((size_t)sp * 4 * L));
+    a.o_state = take((size_t)sp * 6 * ts);
+    a.o_cov = take((size_t)sp * 21 * ts);
+    a.o_chi2 = reinterpret_cast<double*>(take((size_t)sp * 8));
+    a.o_nhits = reinterpret_cast<int32_t*>(take((size_t)sp * 4));
+    a.o_status = reinterpret_cast<uint32_t*>(take((size_t)sp * 4));
+    a.q = reinterpret_cast<int8_t*>(take((size_t)sp));
+    a.n_keys = kMaxKeys;
+  }
   const size_t ctr_at = ((size_t)S * 4 + (size_t)sp * 2 + kCtrStride - 1) / kCtrStride * kCtrStride;
   if ((e = c->b_list.ensure((ctr_at + (size_t)L * kRegions * kCtrStride) * 4)) != hipSuccess)
     return hip_fail(c, e, "list workspace");
@@ -1619,34 +1928,47 @@ int build_impl(ktf_ctx* c, const ktf_event_batch* ev, ktf_build_out* out, hipStr
   const int L = c->cfg.n_layers, NC = c->cfg.max_cands;
   const int64_t sp = std::max<int64_t>(a.sp, 1);
   hipError_t e;
-  if (out->cand_hist) {
+  // with the seed order on, the (parent, hit) records and the counts per
+  // layer are kept in sorted order and copied to the caller's arrays at the
+  // end if asked for; otherwise the caller's arrays are used directly
+  if (out->cand_hist && !a.seed_order) {
     a.hist = out->cand_hist;
   } else {
     if ((e = c->b_hist.ensure(sizeof(int32_t) * (size_t)L * NC * 2 * sp)) != hipSuccess)
       return hip_fail(c, e, "history workspace");
     a.hist = static_cast<int32_t*>(c->b_hist.p);
   }
-  if (out->cand_count) {
+  if (out->cand_count && !a.seed_order) {
     a.count = out->cand_count;
   } else {
     if ((e = c->b_misc.ensure(sizeof(int32_t) * (size_t)L * sp)) != hipSuccess)
       return hip_fail(c, e, "count workspace");
     a.count = static_cast<int32_t*>(c->b_misc.p);
   }
+  a.u_hist = a.seed_order ? out->cand_hist : nullptr;
+  a.u_count = a.seed_order ? out->cand_count : nullptr;
   // the caller's copy of the (parent, hit) records reads -1 for unused
-  // ranks; the internal one is only ever read along written paths
+  // ranks; otherwise they are only ever read along written paths
   if (out->cand_hist) {
     const int64_t nh = (int64_t)L * NC * 2 * sp;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nh, 256)), dim3(256), 0, st, a.hist, nh, -1);
   }
   hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk((int64_t)L * sp, 256)), dim3(256), 0, st, a.count,
                      (int64_t)L * sp, 0);
-  a.o_hit = out->hit_idx;
-  a.o_state = out->state;
-  a.o_cov = out->cov;
-  a.o_chi2 = out->chi2;
-  a.o_nhits = out->n_hits;
-  a.o_status = out->status;
+  a.u_hit = out->hit_idx;
+  a.u_state = out->state;
+  a.u_cov = out->cov;
+  a.u_chi2 = out->chi2;
+  a.u_nhits = out->n_hits;
+  a.u_status = out->status;
+  if (!a.seed_order) {  // the kernels write the caller's outputs directly
+    a.o_hit = out->hit_idx;
+    a.o_state = out->state;
+    a.o_cov = out->cov;
+    a.o_chi2 = out->chi2;
+    a.o_nhits = out->n_hits;
+    a.o_status = out->status;
+  }
   e = ev->prec == KTF_FP64 ? run_build<double, double>(a, false, st) : run_build<float, float>(a, false, st);
   if (e == hipSuccess) e = record_done(c, st);
   return e == hipSuccess ? KTF_OK : hip_fail(c, e, "build launch");

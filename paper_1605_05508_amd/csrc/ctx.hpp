@@ -98,7 +98,7 @@ struct ktf_ctx {
   hipStream_t capture_stream = nullptr;
 
   // build workspace
-  ktf::DevBuf b_off, b_perm, b_binned, b_cand[2], b_prop, b_rec, b_hist, b_best, b_misc, b_stage, b_list;
+  ktf::DevBuf b_off, b_perm, b_binned, b_cand[2], b_prop, b_rec, b_hist, b_best, b_misc, b_stage, b_list, b_sort;
   hipEvent_t build_done = nullptr;  // last ktf_build / ktf_bin_hits work on the workspace
   void* h_pinned = nullptr;
   size_t h_pinned_bytes = 0;

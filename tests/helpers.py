@@ -180,7 +180,13 @@ def build_inputs(bs, prec, seed_pad=0, hit_pad=0):
                 q=to_dev(bs.q, np.int8, sp), seed_hit=to_dev(bs.seed_hit, np.int32, sp))
 
 
-def certified(o_dbg_n, o_dbg, o_margin, g_count, g_hist, tau):
+# Adjudication threshold of FP32-bulk building mismatches: ten times the
+# 99.99th percentile of the FP32-bulk fit's relative chi2 error against the
+# FP64 oracle on the 1e6-track fit workload (measured 2.06e-4).
+TAU_FP32B = 2.1e-3
+
+
+def certified(o_dbg_n, o_dbg, o_margin, g_count, g_hist, tau=TAU_FP32B):
     """Adjudication of a building mismatch of one seed: find the first layer
     whose kept (parent, hit) list differs; the mismatch is certified when
     the oracle's smallest decision gap at that layer is within tau.  When

@@ -114,9 +114,10 @@ def test_bins_at_phi_edges(k, orc):
 
 
 @pytest.mark.parametrize("ghosts", [False, True])
-def test_fp64_build_matches_oracle(k, orc, ghosts):
+@pytest.mark.parametrize("seed_order", [0, 1])
+def test_fp64_build_matches_oracle(k, orc, ghosts, seed_order):
     bs = small_batch(2, 3, 300, ghosts=ghosts)
-    ctx = ctx_for(k, bs.det)
+    ctx = ctx_for(k, bs.det, seed_order=seed_order)
     d = build_inputs(bs, "fp64", seed_pad=64)
     g = host(ctx.build(d, hist=True), bs.n_seeds)
     o = oracle_batch(orc, bs)
@@ -180,7 +181,8 @@ def test_edge_cases(k, orc):
 def test_config3_full_size_sampled(k, orc):
     """The full combinatorial-building workload (100 events x 5,000 tracks,
     17 layers, 20% noise) in one batch; sampled seeds checked against the
-    brute-force oracle, FP64 exactly and FP32-bulk up to certified ties."""
+    brute-force oracle, FP64 exactly and FP32-bulk up to certified ties; the
+    library's seed order gives every seed the same hits."""
     bs = tg.config3()
     ctx = ctx_for(k, bs.det)
     rng = np.random.default_rng(5)
@@ -189,6 +191,12 @@ def test_config3_full_size_sampled(k, orc):
         d = build_inputs(bs, prec)
         res[prec] = host(ctx.build(d, hist=True), bs.n_seeds)
         del d
+    ctx1 = ctx_for(k, bs.det, seed_order=1)
+    for prec in ("fp64", "fp32b"):
+        g1 = host(ctx1.build(build_inputs(bs, prec)), bs.n_seeds)
+        assert np.array_equal(g1["hit_idx"], res[prec]["hit_idx"]), prec
+        assert np.array_equal(g1["chi2"], res[prec]["chi2"]), prec
+    ctx1.close()
     # overall physics sanity: most seeds find their own particle's hits
     match = (res["fp64"]["hit_idx"] == bs.true_idx).all(axis=0)
     assert match.mean() > 0.95
@@ -205,7 +213,7 @@ def test_config3_full_size_sampled(k, orc):
             if np.array_equal(g["hit_idx"][:, s], o["hit_idx"][:, j]):
                 continue
             ok, layer = certified(o["dbg_n"][:, j], o["dbg"][:, :, :, j], o["margin"][:, j],
-                                  g["count"][:, s], g["hist"][:, :, :, s], 1e-3)
+                                  g["count"][:, s], g["hist"][:, :, :, s])
             assert ok, (e, s, layer)
 
 
@@ -237,7 +245,7 @@ def test_fp32_build_agrees_up_to_ties(k, orc):
     assert same.mean() > 0.98
     for s in np.nonzero(~same)[0]:
         ok, layer = certified(o["dbg_n"][:, s], o["dbg"][:, :, :, s], o["margin"][:, s],
-                              g["count"][:, s], g["hist"][:, :, :, s], 1e-3)
+                              g["count"][:, s], g["hist"][:, :, :, s])
         assert ok, (s, layer)
     np.testing.assert_allclose(g["chi2"][same], o["chi2"][same], rtol=1e-3, atol=1e-3)
 
@@ -260,3 +268,9 @@ def test_seed_order_invariance(k, prec):
         inv[perm] = np.arange(bs.n_seeds)
         for key in ("hit_idx", "nhits", "chi2", "state", "cov", "status", "count", "hist"):
             assert np.array_equal(g[key][..., inv], base[key], equal_nan=g[key].dtype.kind == "f"), key
+    # the library's own seed order (sorted by predicted cell, window boxes
+    # staged in LDS): the same results in the caller's order
+    ctx1 = ctx_for(k, bs.det, seed_order=1)
+    g = host(ctx1.build(build_inputs(bs, prec), hist=True), bs.n_seeds)
+    for key in ("hit_idx", "nhits", "chi2", "state", "cov", "status", "count", "hist"):
+        assert np.array_equal(g[key], base[key], equal_nan=g[key].dtype.kind == "f"), key

@@ -40,15 +40,16 @@ def k():
     return k
 
 
+@pytest.mark.parametrize("seed_order", [0, 1])
 @pytest.mark.parametrize("case", CASES, ids=[f"seed{c[0]}" for c in CASES])
-def test_build_configurations(k, orc, case):
+def test_build_configurations(k, orc, case, seed_order):
     seed, L, nc, missed, cut, x0, sizes = case[:7]
     res = case[7] if len(case) > 7 else {}
     rng = np.random.default_rng(seed)
     det = tg.barrel(L, x0=x0, eloss=0.036 if x0 > 0 else 0.0, **res)
     evs = [with_ghosts(tg.make_build_event(rng, n, det), seed * 10 + i) for i, n in enumerate(sizes)]
     bs = tg.concat_events(evs)
-    ctx = k.Context.for_detector(det, max_cands=nc, max_missed=missed, chi2_cut=cut)
+    ctx = k.Context.for_detector(det, max_cands=nc, max_missed=missed, chi2_cut=cut, seed_order=seed_order)
     g = host(ctx.build(build_inputs(bs, "fp64")), bs.n_seeds)
     outs = [orc.build_event(bs, e, max_cands=nc, max_missed=missed, chi2_cut=cut)
             for e in range(bs.n_events)]

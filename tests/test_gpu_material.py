@@ -109,5 +109,5 @@ def test_build_through_material(k, orc):
         if np.array_equal(g["hit_idx"][:, s], o["hit_idx"][:, s]):
             continue
         ok, layer = certified(o["dbg_n"][:, s], o["dbg"][:, :, :, s], o["margin"][:, s],
-                              g["count"][:, s], g["hist"][:, :, :, s], 1e-3)
+                              g["count"][:, s], g["hist"][:, :, :, s])
         assert ok, (s, layer)
