@@ -337,8 +337,8 @@ def shapes_workload(args):
     out = ctx.alloc_fit_out(n, n, torch.float32)
     ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out)
     tuned = json.loads(ctx.tuned_shape("fp32b", n, trials=True))
-    trials = [{"block": b, "waves_per_simd": w, "persistent": bool(p), "ms": ms}
-              for b, w, p, ms in tuned.pop("trials")]
+    trials = [{"block": b, "waves_per_simd": w, "persistent": bool(p), "tracks_per_lane": tp, "ms": ms}
+              for b, w, p, tp, ms in tuned.pop("trials")]
     del out
     scan = []
     for m in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):

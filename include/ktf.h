@@ -184,15 +184,21 @@ int ktf_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, ktf_fit_mode m
             void *hip_stream);
 
 /* Time each launch shape of the fused fit (block size 64..512 x plain or
- * persistent x a register budget of 1, 2 or 3 waves per SIMD) on the given
- * inputs, in two rounds keeping each shape's faster one, and keep the
- * fastest shape for this precision and size class; KTF_FIT_AUTO then uses
- * it.  Runs synchronously on hip_stream and overwrites out. */
+ * persistent x a register budget of 1, 2 or 3 waves per SIMD x 1 or 2
+ * tracks per lane, the two tracks' layers fitted side by side; two per lane
+ * only for one pass without material) on the given inputs, in two rounds
+ * keeping each shape's faster one, and keep the fastest shape for this
+ * precision and size class; KTF_FIT_AUTO then uses it.  The shapes with one
+ * track per lane give bit-identical results; two tracks per lane compile the
+ * same arithmetic in another context, where the compiler may fuse other
+ * multiply-adds, and agree with them to rounding.  Runs synchronously on
+ * hip_stream and overwrites out (with the last shape's results). */
 int ktf_autotune_fit(ktf_ctx *ctx, const ktf_fit_in *in, ktf_fit_out *out, void *hip_stream);
 /* Describe the chosen launch shape for (prec, n) as JSON into buf (block,
- * waves_per_simd, persistent, blocks_per_cu, ms, tuned, and "trials": one
- * [block, waves_per_simd, persistent, ms] per shape tried).  The text is cut
- * at len - 1 characters; 4096 bytes hold every shape. */
+ * waves_per_simd, tracks_per_lane, persistent, blocks_per_cu, ms, tuned,
+ * and "trials": one [block, waves_per_simd, persistent, tracks_per_lane,
+ * ms] per shape tried).  The text is cut at len - 1 characters; 4096 bytes
+ * hold every shape. */
 int ktf_tuned_shape(ktf_ctx *ctx, ktf_precision prec, int64_t n, char *buf, size_t len);
 
 /* Bytes of the device scratch array behind ktf_fit_noalloc (one copy per

@@ -72,15 +72,16 @@ int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* out) {
 }
 
 // blocks per CU for the persistent kernel, from the occupancy calculator
-int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves);
+int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves, int tpl);
 
 // the launch shape the tuner chose for (prec, size class of n); false (and
 // the arguments unchanged) when none was tuned
-bool tuned_launch(ktf_ctx* c, ktf_precision prec, int64_t n, int& bs, int& waves, bool& persistent) {
+bool tuned_launch(ktf_ctx* c, ktf_precision prec, int64_t n, int& bs, int& waves, int& tpl, bool& persistent) {
   auto it = c->tuned.find({(int)prec, size_class(n)});
   if (it == c->tuned.end()) return false;
   bs = it->second.block;
   waves = it->second.waves;
+  tpl = it->second.tpl;
   persistent = it->second.persistent;
   return true;
 }
@@ -88,7 +89,7 @@ bool tuned_launch(ktf_ctx* c, ktf_precision prec, int64_t n, int& bs, int& waves
 // device address of the allocation-free entry point's scratch (noalloc.hip)
 hipError_t noalloc_init(int device);
 
-static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode, int bs, int waves,
+static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode, int bs, int waves, int tpl,
                    bool persistent, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (mode == KTF_FIT_SWEEP || mode == KTF_FIT_SWEEP_GRAPH) {
@@ -139,12 +140,13 @@ static int run_fit(ktf_ctx* c, FitArgs a, ktf_precision prec, ktf_fit_mode mode,
     if ((e = c->counters.ensure(64 * sizeof(unsigned long long))) != hipSuccess)
       return hip_fail(c, e, "counters");
     a.counters = static_cast<unsigned long long*>(c->counters.p);
-    a.tile_count = (a.n + bs - 1) / bs;
-    pblocks = persistent_blocks(c, prec, bs, waves) * c->n_cu;
+    const int tile = a.mat.on ? bs : bs * tpl;
+    a.tile_count = (a.n + tile - 1) / tile;
+    pblocks = persistent_blocks(c, prec, bs, waves, tpl) * c->n_cu;
     if (pblocks <= 0) pblocks = c->n_cu;
     if ((e = launch_fill_u64(a.counters, 1, 0ull, st)) != hipSuccess) return hip_fail(c, e, "fill");
   }
-  e = launch_fit_fused(a, prec, bs, waves, persistent, pblocks, st);
+  e = launch_fit_fused(a, prec, bs, waves, tpl, persistent, pblocks, st);
   return e == hipSuccess ? KTF_OK : hip_fail(c, e, "fit launch");
 }
 
@@ -230,10 +232,10 @@ int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mod
   if (in->n == 0) return KTF_OK;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   FitArgs a = make_fit_args(c, in, out);
-  int bs = 256, waves = 1;
+  int bs = 256, waves = 1, tpl = 1;
   bool persistent = false;
   switch (mode) {
-    case KTF_FIT_AUTO: (void)tuned_launch(c, in->prec, in->n, bs, waves, persistent); break;
+    case KTF_FIT_AUTO: (void)tuned_launch(c, in->prec, in->n, bs, waves, tpl, persistent); break;
     case KTF_FIT_FUSED: break;
     case KTF_FIT_PERSISTENT: persistent = true; break;
     case KTF_FIT_SWEEP:
@@ -245,7 +247,7 @@ int ktf_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mod
       break;
     default: return fail(c, KTF_EINVAL, "ktf_fit: unknown mode %d", (int)mode);
   }
-  return run_fit(c, a, in->prec, mode, bs, waves, persistent, st);
+  return run_fit(c, a, in->prec, mode, bs, waves, tpl, persistent, st);
 }
 
 int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* hip_stream) {
@@ -261,18 +263,20 @@ int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* h
   // clocks ramp up) and keeps its faster round
   TunedShape best;
   best.ms = 1e30f;
+  // two tracks per lane only for one pass without material
+  const int ntpl = (a.mat.on || a.n_passes > 1) ? 1 : kTplChoices;
   for (int round = 0; round < 2 && rc == 0; ++round) {
     int t = 0;
     for (int bs : kBlockSizes) {
-      for (int w = 0; w < 2 * kWaveChoices && rc == 0; ++w, ++t) {
-        const int pers = w & 1, waves = 1 + w / 2;
-        rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, waves, pers != 0, st);  // warm-up
+      for (int w = 0; w < 2 * kWaveChoices * ntpl && rc == 0; ++w, ++t) {
+        const int pers = w & 1, waves = 1 + (w / 2) % kWaveChoices, tpl = 1 + w / (2 * kWaveChoices);
+        rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, waves, tpl, pers != 0, st);  // warm-up
         if (rc) break;
         float tot = 0.f;
         const int reps = 3;
         (void)hipEventRecord(e0, st);
         for (int r = 0; r < reps && rc == 0; ++r)
-          rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, waves, pers != 0, st);
+          rc = run_fit(c, a, in->prec, KTF_FIT_FUSED, bs, waves, tpl, pers != 0, st);
         (void)hipEventRecord(e1, st);
         if (rc) break;
         if (hipEventSynchronize(e1) != hipSuccess) {
@@ -282,7 +286,7 @@ int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* h
         (void)hipEventElapsedTime(&tot, e0, e1);
         const float ms = tot / reps;
         if (round == 0)
-          best.trials.push_back(LaunchTrial{bs, waves, pers != 0, ms});
+          best.trials.push_back(LaunchTrial{bs, waves, pers != 0, tpl, ms});
         else
           best.trials[t].ms = std::min(best.trials[t].ms, ms);
       }
@@ -294,8 +298,9 @@ int ktf_autotune_fit(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, void* h
       best.ms = tr.ms;
       best.block = tr.block;
       best.waves = tr.waves;
+      best.tpl = tr.tpl;
       best.persistent = tr.persistent;
-      best.persistent_blocks = tr.persistent ? persistent_blocks(c, in->prec, tr.block, tr.waves) : 0;
+      best.persistent_blocks = tr.persistent ? persistent_blocks(c, in->prec, tr.block, tr.waves, tr.tpl) : 0;
     }
   }
   (void)hipEventDestroy(e0);
@@ -309,11 +314,12 @@ int ktf_tuned_shape(ktf_ctx* c, ktf_precision prec, int64_t n, char* buf, size_t
   if (!c || !buf || len == 0) return KTF_EINVAL;
   auto it = c->tuned.find({(int)prec, size_class(n)});
   if (it == c->tuned.end()) {
-    snprintf(buf, len, "{\"block\": 256, \"waves_per_simd\": 1, \"persistent\": false, \"tuned\": false}");
+    snprintf(buf, len, "{\"block\": 256, \"waves_per_simd\": 1, \"tracks_per_lane\": 1, \"persistent\": false, \"tuned\": false}");
   } else {
     const TunedShape& t = it->second;
     std::string s = "{\"block\": " + std::to_string(t.block) + ", \"waves_per_simd\": " +
-                    std::to_string(t.waves) + ", \"persistent\": " + (t.persistent ? "true" : "false") +
+                    std::to_string(t.waves) + ", \"tracks_per_lane\": " + std::to_string(t.tpl) +
+                    ", \"persistent\": " + (t.persistent ? "true" : "false") +
                     ", \"blocks_per_cu\": " + std::to_string(t.persistent_blocks);
     char num[32];
     snprintf(num, sizeof num, "%.6f", t.ms);
@@ -321,7 +327,8 @@ int ktf_tuned_shape(ktf_ctx* c, ktf_precision prec, int64_t n, char* buf, size_t
     for (size_t i = 0; i < t.trials.size(); ++i) {
       snprintf(num, sizeof num, "%.6f", t.trials[i].ms);
       s += std::string(i ? ", " : "") + "[" + std::to_string(t.trials[i].block) + ", " +
-           std::to_string(t.trials[i].waves) + ", " + (t.trials[i].persistent ? "1" : "0") + ", " + num + "]";
+           std::to_string(t.trials[i].waves) + ", " + (t.trials[i].persistent ? "1" : "0") + ", " +
+           std::to_string(t.trials[i].tpl) + ", " + num + "]";
     }
     s += "]}";
     snprintf(buf, len, "%s", s.c_str());

@@ -56,12 +56,14 @@ struct LaunchTrial {
   int block;
   int waves;
   bool persistent;
+  int tpl;
   float ms;
 };
 
 struct TunedShape {
   int block = 256;
   int waves = 1;  // waves per SIMD the registers must allow (1: compiler's choice)
+  int tpl = 1;    // tracks per lane
   bool persistent = false;
   int persistent_blocks = 0;
   float ms = 0.f;

@@ -180,17 +180,125 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
   }
 }
 
-// W: the waves per SIMD the register allocation must allow (1 leaves it to
-// the compiler; more trades registers, and maybe spills, for latency hiding)
-template <typename TS, typename TP, typename TC, int BS, int W, bool MAT, bool REFIT = false>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_fused_kernel(FitArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < a.n) fit_one_track<TS, TP, TC, MAT, REFIT>(a, i);
+// Two tracks per lane (register tiling): the lane fits tracks i and i + BS
+// (so that each row access of the wave stays one coalesced transaction),
+// layer by layer, the two tracks' work on a layer side by side, so that one
+// track's arithmetic can cover the other's latencies.  One pass, no
+// material: the same arithmetic per track as fit_pass, whose results it
+// reproduces bit for bit.
+template <typename TS, typename TP, typename TC, int TPL>
+__device__ __forceinline__ void fit_tile(const FitArgs& a, int64_t i0, int64_t stride) {
+  const int64_t p = a.pitch;
+  const HitRes hr{a.hr.sr2, a.hr.srphi2, a.hr.sz2};
+  const TS* st = static_cast<const TS*>(a.state);
+  const TS* cv = static_cast<const TS*>(a.cov);
+  const TS* hits = static_cast<const TS*>(a.hits);
+  TrackState<TP> x[TPL];
+  TC P[TPL][21];
+  TP k[TPL];
+  uint32_t vmask[TPL], status[TPL];
+  int lend[TPL];
+  double chi2[TPL];
+  int32_t nupd[TPL];
+  bool live[TPL];
+  int lmax = 0;
+#pragma unroll
+  for (int j = 0; j < TPL; ++j) {
+    const int64_t i = i0 + j * stride;
+    live[j] = i < a.n;
+    const int64_t ic = live[j] ? i : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[j].pos[c] = (double)st[c * p + ic];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[j].mom[c] = (TP)st[(c + 3) * p + ic];
+#pragma unroll
+    for (int c = 0; c < 21; ++c) P[j][c] = (TC)cv[c * p + ic];
+    k[j] = (TP)(kCLight * (double)a.q[ic] * a.bz);
+    vmask[j] = 0;
+    for (int l = 0; l < a.n_layers; ++l)
+      if (a.valid == nullptr || a.valid[l * p + ic]) vmask[j] |= 1u << l;
+    lend[j] = live[j] ? (vmask[j] ? 32 - __builtin_clz(vmask[j]) : 1) : 0;
+    lmax = lend[j] > lmax ? lend[j] : lmax;
+    chi2[j] = 0.0;
+    nupd[j] = 0;
+    status[j] = 0;
+  }
+  for (int l = 0; l < lmax; ++l) {
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+      if (!live[j] || l >= lend[j]) continue;
+      const int64_t i = i0 + j * stride;
+      double m[3] = {0.0, 0.0, 0.0};
+      const bool has = (vmask[j] >> l) & 1u;
+      if (has) {
+        const TS* h = hits + (int64_t)l * 3 * p;
+        m[0] = (double)h[i];
+        m[1] = (double)h[p + i];
+        m[2] = (double)h[2 * p + i];
+      }
+      TrackState<TP> xp;
+      Jac<TP> F;
+      if (!propagate<TP, NewtonIters<TP>::n>(x[j], k[j], a.radii[l], l == 0, xp, F)) {
+        status[j] |= kNoReach;
+        live[j] = false;
+        continue;
+      }
+      TC Pp[21];
+      cov_propagate(P[j], F, Pp);
+      if (has) {
+        Residual R;
+        if (residual(xp, Pp, m, hr, R)) {
+          apply_update(xp, Pp, R, xp, Pp);
+          chi2[j] += R.chi2;
+          ++nupd[j];
+        } else {
+          status[j] |= kSNotPD;
+        }
+      }
+      x[j] = xp;
+#pragma unroll
+      for (int c = 0; c < 21; ++c) P[j][c] = Pp[c];
+      if (!finite_state(x[j], P[j])) {
+        status[j] |= kNonFinite;
+        live[j] = false;
+      }
+    }
+  }
+  TS* so = static_cast<TS*>(a.state_o);
+  TS* co = static_cast<TS*>(a.cov_o);
+#pragma unroll
+  for (int j = 0; j < TPL; ++j) {
+    const int64_t i = i0 + j * stride;
+    if (i >= a.n) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x[j].pos[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x[j].mom[c];
+#pragma unroll
+    for (int c = 0; c < 21; ++c) co[c * p + i] = (TS)P[j][c];
+    a.chi2[i] = chi2[j];
+    a.nupd[i] = nupd[j];
+    a.status[i] = status[j];
+  }
 }
 
-// Persistent blocks: every block loops taking the next tile of BS tracks
-// from counters[0]; all waves leave once the tile index passes tile_count.
-template <typename TS, typename TP, typename TC, int BS, int W, bool MAT>
+// W: the waves per SIMD the register allocation must allow (1 leaves it to
+// the compiler; more trades registers, and maybe spills, for latency
+// hiding); TPL: tracks per lane (2: fit_tile, one pass without material)
+template <typename TS, typename TP, typename TC, int BS, int W, bool MAT, bool REFIT = false, int TPL = 1>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_fused_kernel(FitArgs a) {
+  if constexpr (TPL == 1) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i < a.n) fit_one_track<TS, TP, TC, MAT, REFIT>(a, i);
+  } else {
+    fit_tile<TS, TP, TC, TPL>(a, (int64_t)blockIdx.x * BS * TPL + threadIdx.x, BS);
+  }
+}
+
+// Persistent blocks: every block loops taking the next tile of BS * TPL
+// tracks from counters[0]; all waves leave once the tile index passes
+// tile_count.
+template <typename TS, typename TP, typename TC, int BS, int W, bool MAT, int TPL = 1>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fit_persistent_kernel(FitArgs a) {
   __shared__ long long tile;
   for (;;) {
@@ -199,8 +307,12 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W))) void fi
     const long long t = tile;
     __syncthreads();
     if (t >= a.tile_count) break;
-    const int64_t i = t * BS + threadIdx.x;
-    if (i < a.n) fit_one_track<TS, TP, TC, MAT, false>(a, i);
+    if constexpr (TPL == 1) {
+      const int64_t i = t * BS + threadIdx.x;
+      if (i < a.n) fit_one_track<TS, TP, TC, MAT, false>(a, i);
+    } else {
+      fit_tile<TS, TP, TC, TPL>(a, t * BS * TPL + threadIdx.x, BS);
+    }
   }
 }
 
@@ -318,21 +430,24 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
   return hipGetLastError();
 }
 
-template <typename TS, typename TP, typename TC, int BS, int W, bool MAT>
+template <typename TS, typename TP, typename TC, int BS, int W, bool MAT, int TPL>
 static hipError_t launch_fused_m(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
   if (persistent) {
-    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, TC, BS, W, MAT>), dim3(pblocks), dim3(BS), 0, st, a);
+    hipLaunchKernelGGL((fit_persistent_kernel<TS, TP, TC, BS, W, MAT, TPL>), dim3(pblocks), dim3(BS), 0, st, a);
   } else {
-    const int64_t nb = (a.n + BS - 1) / BS;
-    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS, W, MAT>), dim3((unsigned)nb), dim3(BS), 0, st, a);
+    const int64_t nb = (a.n + BS * TPL - 1) / (BS * TPL);
+    hipLaunchKernelGGL((fit_fused_kernel<TS, TP, TC, BS, W, MAT, false, TPL>), dim3((unsigned)nb), dim3(BS), 0, st, a);
   }
   return hipGetLastError();
 }
 
+// two tracks per lane only without material (the material fit keeps its
+// own single-track kernels)
 template <typename TS, typename TP, typename TC, int BS, int W>
-static hipError_t launch_fused_bs(const FitArgs& a, bool persistent, int pblocks, hipStream_t st) {
-  return a.mat.on ? launch_fused_m<TS, TP, TC, BS, W, true>(a, persistent, pblocks, st)
-                  : launch_fused_m<TS, TP, TC, BS, W, false>(a, persistent, pblocks, st);
+static hipError_t launch_fused_bs(const FitArgs& a, int tpl, bool persistent, int pblocks, hipStream_t st) {
+  if (a.mat.on) return launch_fused_m<TS, TP, TC, BS, W, true, 1>(a, persistent, pblocks, st);
+  return tpl == 2 ? launch_fused_m<TS, TP, TC, BS, W, false, 2>(a, persistent, pblocks, st)
+                  : launch_fused_m<TS, TP, TC, BS, W, false, 1>(a, persistent, pblocks, st);
 }
 
 // the iterated refit: one launch shape (256 threads, the compiler's
@@ -349,28 +464,28 @@ static hipError_t launch_refit(const FitArgs& a, hipStream_t st) {
 }
 
 template <typename TS, typename TP, typename TC, int W>
-static hipError_t launch_fused_w(const FitArgs& a, int bs, bool persistent, int pblocks, hipStream_t st) {
+static hipError_t launch_fused_w(const FitArgs& a, int bs, int tpl, bool persistent, int pblocks, hipStream_t st) {
   switch (bs) {
-    case 64: return launch_fused_bs<TS, TP, TC, 64, W>(a, persistent, pblocks, st);
-    case 128: return launch_fused_bs<TS, TP, TC, 128, W>(a, persistent, pblocks, st);
-    case 256: return launch_fused_bs<TS, TP, TC, 256, W>(a, persistent, pblocks, st);
-    case 512: return launch_fused_bs<TS, TP, TC, 512, W>(a, persistent, pblocks, st);
+    case 64: return launch_fused_bs<TS, TP, TC, 64, W>(a, tpl, persistent, pblocks, st);
+    case 128: return launch_fused_bs<TS, TP, TC, 128, W>(a, tpl, persistent, pblocks, st);
+    case 256: return launch_fused_bs<TS, TP, TC, 256, W>(a, tpl, persistent, pblocks, st);
+    case 512: return launch_fused_bs<TS, TP, TC, 512, W>(a, tpl, persistent, pblocks, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename TS, typename TP, typename TC>
-static hipError_t launch_fused_t(const FitArgs& a, int bs, int waves, bool persistent, int pblocks,
+static hipError_t launch_fused_t(const FitArgs& a, int bs, int waves, int tpl, bool persistent, int pblocks,
                                  hipStream_t st) {
   switch (waves) {
-    case 1: return launch_fused_w<TS, TP, TC, 1>(a, bs, persistent, pblocks, st);
-    case 2: return launch_fused_w<TS, TP, TC, 2>(a, bs, persistent, pblocks, st);
-    case 3: return launch_fused_w<TS, TP, TC, 3>(a, bs, persistent, pblocks, st);
+    case 1: return launch_fused_w<TS, TP, TC, 1>(a, bs, tpl, persistent, pblocks, st);
+    case 2: return launch_fused_w<TS, TP, TC, 2>(a, bs, tpl, persistent, pblocks, st);
+    case 3: return launch_fused_w<TS, TP, TC, 3>(a, bs, tpl, persistent, pblocks, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, int waves, bool persistent,
+hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, int waves, int tpl, bool persistent,
                             int persistent_blocks, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   if (a.n_passes > 1) {  // a double covariance (checked at the boundary)
@@ -378,10 +493,10 @@ hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, int wa
     return launch_refit<float, float, double>(a, st);
   }
   if (prec == KTF_FP64)
-    return launch_fused_t<double, double, double>(a, bs, waves, persistent, persistent_blocks, st);
+    return launch_fused_t<double, double, double>(a, bs, waves, tpl, persistent, persistent_blocks, st);
   if (prec == KTF_FP32_PROP)
-    return launch_fused_t<float, float, double>(a, bs, waves, persistent, persistent_blocks, st);
-  return launch_fused_t<float, float, float>(a, bs, waves, persistent, persistent_blocks, st);
+    return launch_fused_t<float, float, double>(a, bs, waves, tpl, persistent, persistent_blocks, st);
+  return launch_fused_t<float, float, float>(a, bs, waves, tpl, persistent, persistent_blocks, st);
 }
 
 hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hipStream_t st) {
@@ -403,39 +518,40 @@ hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hip
 
 namespace ktf {
 
-template <typename TS, typename TP, typename TC, int W, bool MAT>
+template <typename TS, typename TP, typename TC, int W, bool MAT, int TPL>
 static int occ_blocks_w(int bs) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (bs) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 64, W, MAT>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 128, W, MAT>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 256, W, MAT>, 256, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 512, W, MAT>, 512, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 64, W, MAT, TPL>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 128, W, MAT, TPL>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 256, W, MAT, TPL>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TS, TP, TC, 512, W, MAT, TPL>, 512, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;
 }
 
-template <typename TS, typename TP, typename TC, bool MAT>
+template <typename TS, typename TP, typename TC, bool MAT, int TPL>
 static int occ_blocks(int bs, int waves) {
   switch (waves) {
-    case 1: return occ_blocks_w<TS, TP, TC, 1, MAT>(bs);
-    case 2: return occ_blocks_w<TS, TP, TC, 2, MAT>(bs);
-    case 3: return occ_blocks_w<TS, TP, TC, 3, MAT>(bs);
+    case 1: return occ_blocks_w<TS, TP, TC, 1, MAT, TPL>(bs);
+    case 2: return occ_blocks_w<TS, TP, TC, 2, MAT, TPL>(bs);
+    case 3: return occ_blocks_w<TS, TP, TC, 3, MAT, TPL>(bs);
     default: return 0;
   }
 }
 
-template <bool MAT>
+template <bool MAT, int TPL>
 static int persistent_blocks_m(ktf_precision prec, int bs, int waves) {
-  if (prec == KTF_FP64) return occ_blocks<double, double, double, MAT>(bs, waves);
-  if (prec == KTF_FP32_PROP) return occ_blocks<float, float, double, MAT>(bs, waves);
-  return occ_blocks<float, float, float, MAT>(bs, waves);
+  if (prec == KTF_FP64) return occ_blocks<double, double, double, MAT, TPL>(bs, waves);
+  if (prec == KTF_FP32_PROP) return occ_blocks<float, float, double, MAT, TPL>(bs, waves);
+  return occ_blocks<float, float, float, MAT, TPL>(bs, waves);
 }
 
-int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves) {
-  return c->x0.empty() ? persistent_blocks_m<false>(prec, bs, waves) : persistent_blocks_m<true>(prec, bs, waves);
+int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves, int tpl) {
+  if (!c->x0.empty()) return persistent_blocks_m<true, 1>(prec, bs, waves);
+  return tpl == 2 ? persistent_blocks_m<false, 2>(prec, bs, waves) : persistent_blocks_m<false, 1>(prec, bs, waves);
 }
 
 }  // namespace ktf

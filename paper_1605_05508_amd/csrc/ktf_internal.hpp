@@ -48,9 +48,11 @@ struct FitArgs {
 // launch shapes of the fused fit
 constexpr int kBlockSizes[4] = {64, 128, 256, 512};
 constexpr int kWaveChoices = 3;  // register budgets tried: 1 (compiler's), 2 and 3 waves per SIMD
+constexpr int kTplChoices = 2;   // tracks per lane tried: 1 and 2
 
-// waves: 1, 2 or 3, the waves per SIMD the fused kernel's registers must allow
-hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, int waves, bool persistent,
+// waves: 1, 2 or 3, the waves per SIMD the fused kernel's registers must
+// allow; tpl: tracks per lane, 1 or 2 (2 only for one pass without material)
+hipError_t launch_fit_fused(const FitArgs& a, ktf_precision prec, int bs, int waves, int tpl, bool persistent,
                             int persistent_blocks, hipStream_t st);
 hipError_t launch_fit_layer(const FitArgs& a, ktf_precision prec, int layer, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);

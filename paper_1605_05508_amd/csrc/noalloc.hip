@@ -55,9 +55,9 @@ static size_t sweep_bytes(int64_t pitch, ktf_precision prec) {
   return b;
 }
 
-int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves);
+int persistent_blocks(ktf_ctx* c, ktf_precision prec, int bs, int waves, int tpl);
 int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* out);
-bool tuned_launch(ktf_ctx* c, ktf_precision prec, int64_t n, int& bs, int& waves, bool& persistent);
+bool tuned_launch(ktf_ctx* c, ktf_precision prec, int64_t n, int& bs, int& waves, int& tpl, bool& persistent);
 
 static int fit_noalloc(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_fit_mode mode,
                        hipStream_t st) {
@@ -73,10 +73,10 @@ static int fit_noalloc(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_f
   if (!base) return fail(c, KTF_EDEVICE, "ktf_fit_noalloc: no scratch address for device %d", dev);
   if (in->n == 0) return KTF_OK;
   FitArgs a = make_fit_args(c, in, out);
-  int bs = 256, waves = 1;
+  int bs = 256, waves = 1, tpl = 1;
   bool persistent = false;
   switch (mode) {
-    case KTF_FIT_AUTO: (void)tuned_launch(c, in->prec, in->n, bs, waves, persistent); break;
+    case KTF_FIT_AUTO: (void)tuned_launch(c, in->prec, in->n, bs, waves, tpl, persistent); break;
     case KTF_FIT_FUSED: break;
     case KTF_FIT_PERSISTENT: persistent = true; break;
     case KTF_FIT_SWEEP: {
@@ -101,14 +101,15 @@ static int fit_noalloc(ktf_ctx* c, const ktf_fit_in* in, ktf_fit_out* out, ktf_f
   int pblocks = 0;
   if (persistent && in->n_passes <= 1) {
     a.counters = reinterpret_cast<unsigned long long*>(base);
-    a.tile_count = (a.n + bs - 1) / bs;
-    pblocks = persistent_blocks(c, in->prec, bs, waves) * c->n_cu;
+    const int tile = a.mat.on ? bs : bs * tpl;
+    a.tile_count = (a.n + tile - 1) / tile;
+    pblocks = persistent_blocks(c, in->prec, bs, waves, tpl) * c->n_cu;
     if (pblocks <= 0) pblocks = c->n_cu;
     // a fill kernel, not a memset: a caller may capture this call in a graph
     if ((e = launch_fill_u64(a.counters, 1, 0ull, st)) != hipSuccess)
       return hip_fail(c, e, "ktf_fit_noalloc: counter reset");
   }
-  e = launch_fit_fused(a, in->prec, bs, waves, persistent && in->n_passes <= 1, pblocks, st);
+  e = launch_fit_fused(a, in->prec, bs, waves, tpl, persistent && in->n_passes <= 1, pblocks, st);
   return e == hipSuccess ? KTF_OK : hip_fail(c, e, "ktf_fit_noalloc: launch");
 }
 

@@ -232,25 +232,38 @@ def test_empty_and_single(ctx10, orc):
 
 def test_autotune_keeps_results(ctx10):
     """Whatever block size, persistence and register budget the autotuner
-    picks, the results are bitwise those of the default fused launch."""
+    picks with one track per lane, the results are bitwise those of the
+    default fused launch; with two tracks per lane they agree to rounding."""
     rng = np.random.default_rng(34)
     fs = tg.make_fit_set(rng, 20000, tg.barrel(10))
     for prec in ("fp32b", "fp64", "fp32p"):
         d = fit_inputs(fs, "fp64" if prec == "fp64" else "fp32b")
         pp = None if prec == "fp32b" else prec
         ref = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="fused", prec=pp), fs.n)
-        ctx10.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], prec=pp)
+        # the tuner leaves the outputs of the last shape it timed: 512 per
+        # block, persistent, three waves per SIMD, two tracks per lane.  The
+        # two tracks' arithmetic is the same but compiled in another context,
+        # where the compiler fuses other multiply-adds: agreement to rounding
+        last = host(ctx10.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], prec=pp), fs.n)
+        assert np.array_equal(ref["nupd"], last["nupd"]) and np.array_equal(ref["status"], last["status"])
+        tol = 1e-12 if prec == "fp64" else 2e-4
+        np.testing.assert_allclose(last["state"], ref["state"], rtol=tol, atol=tol)
+        np.testing.assert_allclose(last["chi2"], ref["chi2"], rtol=50 * tol, atol=tol)
         assert '"tuned": true' in ctx10.tuned_shape(prec, fs.n)
         shape = json.loads(ctx10.tuned_shape(prec, fs.n, trials=True))
-        trials = shape["trials"]   # [block, waves per SIMD, persistent, ms] per shape
-        assert len(trials) == 24 and len({tuple(t[:3]) for t in trials}) == 24
-        chosen = [t for t in trials if [t[0], t[1], bool(t[2])] ==
-                  [shape["block"], shape["waves_per_simd"], shape["persistent"]]]
-        assert len(chosen) == 1 and chosen[0][3] <= min(t[3] for t in trials) + 1e-6   # the fastest
-        assert abs(chosen[0][3] - shape["ms"]) < 1e-6
+        trials = shape["trials"]   # [block, waves per SIMD, persistent, tracks per lane, ms] per shape
+        assert len(trials) == 48 and len({tuple(t[:4]) for t in trials}) == 48
+        chosen = [t for t in trials if [t[0], t[1], bool(t[2]), t[3]] ==
+                  [shape["block"], shape["waves_per_simd"], shape["persistent"], shape["tracks_per_lane"]]]
+        assert len(chosen) == 1 and chosen[0][4] <= min(t[4] for t in trials) + 1e-6   # the fastest
+        assert abs(chosen[0][4] - shape["ms"]) < 1e-6
         g = host(ctx10.fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], mode="auto", prec=pp), fs.n)
-        for key in ref:
-            assert np.array_equal(ref[key], g[key]), (prec, key, ctx10.tuned_shape(prec, fs.n))
+        if shape["tracks_per_lane"] == 1:
+            for key in ref:
+                assert np.array_equal(ref[key], g[key]), (prec, key, ctx10.tuned_shape(prec, fs.n))
+        else:
+            assert np.array_equal(ref["nupd"], g["nupd"]) and np.array_equal(ref["status"], g["status"])
+            np.testing.assert_allclose(g["state"], ref["state"], rtol=tol, atol=tol)
 
 
 def test_bad_arguments_raise(ctx10):
