@@ -282,6 +282,16 @@ def build_measurement(ctx_cls, tg, torch, reps=5, orc=None, bs=None, precs=("fp3
                                        "same_hits": bool(np.array_equal(hit2, hit))}
             del o2
             ctx2.close()
+            # the paper's eta partition: 21 eta bins by 512 phi bins
+            ctx3 = ctx_cls.for_detector(bs.det, n_etabins=21, eta_max=1.2)
+            o3 = ctx3.build(d)
+            ms3 = time_build(ctx3, d, o3, reps, torch)
+            hit3 = o3["hit_idx"].cpu().numpy()[:, :bs.n_seeds]
+            out["fp32b_eta_bins"] = {"ms": round(ms3, 3), "seeds_per_s": round(bs.n_seeds / (ms3 * 1e-3)),
+                                     "bins": "21 eta x 512 phi over |eta| < 1.2",
+                                     "same_hits": bool(np.array_equal(hit3, hit))}
+            del o3
+            ctx3.close()
         del d, o
     if "fp32b" in hits_by_prec and "fp64" in hits_by_prec:
         # the FP64 build equals the oracle's bit for bit (tests); FP32 bulk

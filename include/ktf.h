@@ -122,6 +122,16 @@ typedef struct {
    * every window read from the binned hits in memory.  Results are the same
    * either way. */
   int32_t seed_order;
+  /* Building: > 0 = bin each layer's hits in n_etabins pseudorapidity bins
+   * over |eta| < eta_max (eta = asinh(z / rho) of the hit, seen from the
+   * origin; beyond, the edge bins) by n_phibins phi bins, the paper's
+   * directionally projective partition (Sec. 3: tracks do not bend in eta),
+   * in place of n_zbins z bins.  A candidate searches the eta bins that its
+   * window (the same conservative bound on every compatible hit) overlaps:
+   * the compatible set, and so the result, does not depend on the binning.
+   * 0 = z bins. */
+  int32_t n_etabins;
+  double eta_max;
 } ktf_config;
 
 /* Create a context on the current HIP device.  Returns KTF_EINVAL for an

@@ -261,6 +261,24 @@ def bin_layer(hits, z_half, nz, nphi):
     return offs, perm[:n]
 
 
+def eta(h):
+    """Pseudorapidity of the point h = (x, y, z) seen from the origin."""
+    f = lib().orc_eta
+    f.restype = C.c_double
+    return f(_p(_d(h), C.c_double))
+
+
+def bin_layer_eta(hits, eta_max, neta, nphi):
+    """hits[3, n] -> (offsets[neta*nphi+1], perm[n]) with rows of pseudorapidity."""
+    n = hits.shape[1]
+    hh = _d(np.asarray(hits).T)
+    offs = np.zeros(neta * nphi + 1, dtype=np.int32)
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    lib().orc_bin_layer_eta(C.c_int64(n), _p(hh, C.c_double), C.c_double(eta_max), C.c_int32(neta),
+                            C.c_int32(nphi), _p(offs, C.c_int32), _p(perm, C.c_int32))
+    return offs, perm[:n]
+
+
 # --------------------------------------------------------------- building
 
 def build_event(bs, e, seeds=None, *, max_cands=10, max_missed=1, chi2_cut=30.0,

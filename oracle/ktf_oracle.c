@@ -530,28 +530,55 @@ static int cmp_bin_key(const void *a, const void *b) {
   return (x->idx > y->idx) - (x->idx < y->idx);
 }
 
+static int32_t phi_bin(const double *h, int32_t nphi) {
+  double phi = atan2(h[1], h[0]);
+  int32_t pb = (int32_t)floor((phi + ORC_PI) * nphi / (2.0 * ORC_PI));
+  return ((pb % nphi) + nphi) % nphi;
+}
+
+static void bin_sort(int64_t n, bin_key *keys, int32_t nb, int32_t *offsets, int32_t *perm);
+
 void orc_bin_layer(int64_t n, const double *hits, double z_half, int32_t nz, int32_t nphi,
                    int32_t *offsets, int32_t *perm) {
   bin_key *keys = (bin_key *)malloc(sizeof(bin_key) * (size_t)(n > 0 ? n : 1));
-  const int32_t nb = nz * nphi;
-  for (int32_t b = 0; b <= nb; ++b) offsets[b] = 0;
   for (int64_t i = 0; i < n; ++i) {
     const double *h = hits + 3 * i;
     double zf = floor((h[2] + z_half) * nz / (2.0 * z_half));
     int32_t zb = zf < 0.0 ? 0 : (zf > nz - 1 ? nz - 1 : (int32_t)zf);
-    double phi = atan2(h[1], h[0]);
-    int32_t pb = (int32_t)floor((phi + ORC_PI) * nphi / (2.0 * ORC_PI));
-    pb = ((pb % nphi) + nphi) % nphi;
-    keys[i].bin = zb * nphi + pb;
+    keys[i].bin = zb * nphi + phi_bin(h, nphi);
     keys[i].idx = (int32_t)i;
   }
+  bin_sort(n, keys, nz * nphi, offsets, perm);
+  free(keys);
+}
+
+/* pseudorapidity of a hit seen from the origin: eta = -ln tan(theta / 2)
+ * with theta the polar angle, i.e. sinh(eta) = cot(theta) = z / rho */
+double orc_eta(const double h[3]) { return asinh(h[2] / sqrt(h[0] * h[0] + h[1] * h[1])); }
+
+void orc_bin_layer_eta(int64_t n, const double *hits, double eta_max, int32_t neta, int32_t nphi,
+                       int32_t *offsets, int32_t *perm) {
+  bin_key *keys = (bin_key *)malloc(sizeof(bin_key) * (size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) {
+    const double *h = hits + 3 * i;
+    double ef = floor((orc_eta(h) + eta_max) * neta / (2.0 * eta_max));
+    int32_t eb = ef < 0.0 ? 0 : (ef > neta - 1 ? neta - 1 : (int32_t)ef);
+    keys[i].bin = eb * nphi + phi_bin(h, nphi);
+    keys[i].idx = (int32_t)i;
+  }
+  bin_sort(n, keys, neta * nphi, offsets, perm);
+  free(keys);
+}
+
+/* hits sorted by (bin, original index) and the CSR offsets of the bins */
+static void bin_sort(int64_t n, bin_key *keys, int32_t nb, int32_t *offsets, int32_t *perm) {
+  for (int32_t b = 0; b <= nb; ++b) offsets[b] = 0;
   qsort(keys, (size_t)n, sizeof(bin_key), cmp_bin_key);
   for (int64_t i = 0; i < n; ++i) {
     perm[i] = keys[i].idx;
     offsets[keys[i].bin + 1] += 1;
   }
   for (int32_t b = 0; b < nb; ++b) offsets[b + 1] += offsets[b];
-  free(keys);
 }
 
 /* ---------------------------------------------------------------- building */

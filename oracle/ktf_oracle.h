@@ -130,6 +130,13 @@ void orc_fit_batch(const orc_geom *g, int64_t n, const double *state, const doub
 void orc_bin_layer(int64_t n, const double *hits /* [n][3] */, double z_half,
                    int32_t nz, int32_t nphi, int32_t *offsets, int32_t *perm);
 
+/* pseudorapidity of a point seen from the origin, -ln tan(theta / 2) */
+double orc_eta(const double h[3]);
+/* the same binning with rows of pseudorapidity: etabin = floor((eta +
+ * eta_max) * neta / (2 eta_max)) clamped to 0 .. neta - 1 */
+void orc_bin_layer_eta(int64_t n, const double *hits /* [n][3] */, double eta_max,
+                       int32_t neta, int32_t nphi, int32_t *offsets, int32_t *perm);
+
 /* building of one seed by brute force over every hit of each layer.
  * hits: AoS [total][3] of one event; layer_off[L+1].  seed_hit[nsl] are
  * indices within each seed layer's hit list.  Outputs hit_idx[L] (-1 =

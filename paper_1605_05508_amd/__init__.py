@@ -44,7 +44,8 @@ class _Config(C.Structure):
                 ("max_cands", C.c_int32), ("max_missed", C.c_int32), ("n_seed_layers", C.c_int32),
                 ("chi2_cut", C.c_double), ("hbm_budget_bytes", C.c_uint64),
                 ("max_inflight", C.c_int32), ("layer_x0", C.POINTER(C.c_double)),
-                ("eloss_per_x0", C.c_double), ("mass", C.c_double), ("seed_order", C.c_int32)]
+                ("eloss_per_x0", C.c_double), ("mass", C.c_double), ("seed_order", C.c_int32),
+                ("n_etabins", C.c_int32), ("eta_max", C.c_double)]
 
 
 class _FitIn(C.Structure):
@@ -144,11 +145,14 @@ class Context:
     def __init__(self, radii: Sequence[float], *, bz=3.8, sigma_r=0.01, sigma_rphi=0.01,
                  sigma_z=0.1, z_half=100.0, n_zbins=64, n_phibins=512, max_cands=10,
                  max_missed=1, n_seed_layers=3, chi2_cut=30.0, hbm_budget_bytes=8 << 30,
-                 max_inflight=64, layer_x0=None, eloss_per_x0=0.0, mass=0.13957, seed_order=0):
+                 max_inflight=64, layer_x0=None, eloss_per_x0=0.0, mass=0.13957, seed_order=0,
+                 n_etabins=0, eta_max=1.2):
         """layer_x0: per-layer material thickness in radiation lengths (a number
         for all layers, a sequence, or None for no material).  seed_order: 1
         to build on seeds sorted by their predicted cell with each wave's
-        window box staged in LDS (results unchanged)."""
+        window box staged in LDS (results unchanged).  n_etabins > 0: bin hits
+        in that many eta bins over |eta| < eta_max instead of n_zbins z bins
+        (results unchanged)."""
         _torch()
         lib = load_library()
         self._lib = lib
@@ -164,7 +168,8 @@ class Context:
             self._x0 = (C.c_double * self.n_layers)(*x0)
         cfg = _Config(self.n_layers, self._r, z_half, bz, sigma_r, sigma_rphi, sigma_z, n_zbins,
                       n_phibins, max_cands, max_missed, n_seed_layers, chi2_cut,
-                      int(hbm_budget_bytes), max_inflight, self._x0, eloss_per_x0, mass, int(seed_order))
+                      int(hbm_budget_bytes), max_inflight, self._x0, eloss_per_x0, mass, int(seed_order),
+                      int(n_etabins), float(eta_max))
         self.cfg = cfg
         self._ticket_dtype = {}
         h = C.c_void_p()
@@ -338,7 +343,7 @@ class Context:
         dt = ev["hits"].dtype
         prec = FP64 if dt == torch.float64 else FP32_BULK
         E = len(ev["seed_off"]) - 1
-        nb = self.cfg.n_zbins * self.cfg.n_phibins
+        nb = (self.cfg.n_etabins if self.cfg.n_etabins > 0 else self.cfg.n_zbins) * self.cfg.n_phibins
         dev = torch.device("cuda")
         offs = torch.empty((E * self.n_layers, nb + 1), dtype=torch.int32, device=dev)
         perm = torch.empty(ev["hits"].shape[1], dtype=torch.int32, device=dev)

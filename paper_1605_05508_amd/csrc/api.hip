@@ -166,7 +166,9 @@ int ktf_create(const ktf_config* cfg, ktf_ctx** out) {
   if (!(cfg->sigma_r > 0.0) || !(cfg->sigma_rphi > 0.0) || !(cfg->sigma_z > 0.0)) return KTF_EINVAL;
   if (cfg->max_cands < 1 || cfg->max_cands > KTF_MAX_CANDS || cfg->max_missed < 0 ||
       cfg->n_seed_layers < 1 || cfg->n_seed_layers > cfg->n_layers || cfg->n_zbins < 1 ||
-      cfg->n_phibins < 1 || !(cfg->z_half > 0.0))
+      cfg->n_phibins < 1 || !(cfg->z_half > 0.0) || cfg->n_etabins < 0 ||
+      (cfg->n_etabins > 0 && !(cfg->eta_max > 0.0 && std::isfinite(cfg->eta_max))) ||
+      (int64_t)(cfg->n_etabins > 0 ? cfg->n_etabins : cfg->n_zbins) * cfg->n_phibins > INT32_MAX / 2)
     return KTF_EINVAL;
   bool material = false;
   if (cfg->layer_x0) {

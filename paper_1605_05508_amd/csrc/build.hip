@@ -169,9 +169,20 @@ template <> struct __align__(16) BinHit<double> {
   int32_t id, pad;
 };
 
-__device__ __forceinline__ int hit_bin_of(double x, double y, double z, double zh, int nz, int nphi) {
+// bin of a hit: its row is the z bin, zbin = floor((z + zh) nz / (2 zh))
+// clamped, or (eta rows) the eta bin, floor((asinh(z / rho) + eta_max) nz /
+// (2 eta_max)) clamped; the phi bin as below
+__device__ __forceinline__ int hit_bin_of(double x, double y, double z, const BuildGeom& g) {
 #pragma clang fp contract(off)
-  const double zf = floor((z + zh) * nz / (2.0 * zh));
+  const double zh = g.z_half;
+  const int nz = g.n_zbins, nphi = g.n_phibins;
+  double zf;
+  if (g.eta_rows) {
+    const double eta = asinh(z / sqrt(x * x + y * y));
+    zf = floor((eta + g.eta_max) * nz / (2.0 * g.eta_max));
+  } else {
+    zf = floor((z + zh) * nz / (2.0 * zh));
+  }
   const int zb = zf < 0.0 ? 0 : (zf > nz - 1 ? nz - 1 : (int)zf);
   // the phi bin from a float estimate of its position, unless that lies
   // within 1e-5 rad of a bin edge: the float angle's error (coordinates
@@ -204,8 +215,7 @@ __global__ void bin_count_kernel(BuildArgs a) {
   if (j >= a.n_hits) return;
   const int g = find_event(a.hit_off, a.n_groups, j);
   const TS* h = static_cast<const TS*>(a.hits);
-  const int b = hit_bin_of((double)h[j], (double)h[a.hp + j], (double)h[2 * a.hp + j], a.g.z_half,
-                           a.g.n_zbins, a.g.n_phibins);
+  const int b = hit_bin_of((double)h[j], (double)h[a.hp + j], (double)h[2 * a.hp + j], a.g);
   a.hit_bin[j] = b;
   atomicAdd(&a.bin_cur[(int64_t)g * a.n_bins + b], 1);
 }
@@ -341,8 +351,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
     for (int u = 0; u < kBinBatch; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
       if (j < n) {
-        const int b = hit_bin_of((double)x[u], (double)y[u], (double)z[u], a.g.z_half, a.g.n_zbins,
-                                 a.g.n_phibins);
+        const int b = hit_bin_of((double)x[u], (double)y[u], (double)z[u], a.g);
         a.hit_bin[base + j] = b;
         atomicAdd(&cnt[b >> 1], 1u << ((b & 1) * 16));
       }
@@ -972,8 +981,22 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   const int nz = a.g.n_zbins, nphi = a.g.n_phibins;
   const double zh = a.g.z_half;
   const double zp = xp.pos[2];
-  int zlo = (int)floor((zp - bzw + zh) * nz / (2.0 * zh));
-  int zhi = (int)floor((zp + bzw + zh) * nz / (2.0 * zh));
+  int zlo, zhi;
+  if (a.g.eta_rows) {
+    // the window's z range at hit radii within 1% of the layer's: asinh(z /
+    // rho) grows with z and, for z of one sign, with 1 / rho, so its least
+    // and greatest values over that box are at its corners; 1e-9 covers the
+    // rounding of asinh between this bound and the binning
+    const double z0 = zp - bzw, z1 = zp + bzw, ra = 0.99 * rho, rb = 1.01 * rho;
+    const double e0 = asinh(z0 / (z0 >= 0.0 ? rb : ra)) - 1e-9;
+    const double e1 = asinh(z1 / (z1 >= 0.0 ? ra : rb)) + 1e-9;
+    const double em = a.g.eta_max;
+    zlo = (int)fmax(-1.0, floor((e0 + em) * nz / (2.0 * em)));
+    zhi = (int)fmin((double)nz, floor((e1 + em) * nz / (2.0 * em)));
+  } else {
+    zlo = (int)floor((zp - bzw + zh) * nz / (2.0 * zh));
+    zhi = (int)floor((zp + bzw + zh) * nz / (2.0 * zh));
+  }
   zlo = max(0, min(nz - 1, zlo));
   zhi = max(0, min(nz - 1, zhi));
   const double sphi = bt / (0.99 * rho);
@@ -1728,7 +1751,9 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   const int L = cfg.n_layers;
   memset(&a, 0, sizeof a);
   a.g.n_layers = L;
-  a.g.n_zbins = cfg.n_zbins;
+  a.g.eta_rows = cfg.n_etabins > 0 ? 1 : 0;
+  a.g.eta_max = cfg.eta_max;
+  a.g.n_zbins = cfg.n_etabins > 0 ? cfg.n_etabins : cfg.n_zbins;
   a.g.n_phibins = cfg.n_phibins;
   a.g.max_cands = cfg.max_cands;
   a.g.max_missed = cfg.max_missed;
@@ -1743,7 +1768,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.g.mat = material_of(c);
   a.n_events = ev->n_events;
   a.n_groups = ev->n_events * L;
-  a.n_bins = cfg.n_zbins * cfg.n_phibins;
+  a.n_bins = a.g.n_zbins * cfg.n_phibins;
   a.n_seeds = ev->seed_off[ev->n_events];
   a.sp = ev->seed_pitch;
   a.RS = region_rows(a.n_seeds, cfg.max_cands);

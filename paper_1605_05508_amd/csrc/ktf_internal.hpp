@@ -59,8 +59,10 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
 
 // ------------------------------------------------------------------ build
 struct BuildGeom {
+  // n_zbins: rows of bins per layer, z bins, or eta bins when eta_rows
   int32_t n_layers, n_zbins, n_phibins, max_cands, max_missed, n_seed_layers;
-  double bz, z_half, chi2_cut;
+  int32_t eta_rows;  // 1: rows are eta bins over |eta| < eta_max
+  double bz, z_half, chi2_cut, eta_max;
   HitResD hr;
   double radii[KTF_MAX_LAYERS];
   MaterialD mat;

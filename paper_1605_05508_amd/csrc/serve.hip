@@ -127,7 +127,8 @@ static size_t footprint_of(const ktf_config& cfg, int64_t n, int64_t nh, ktf_pre
   const size_t rows = (size_t)n * NC + 64 * 257;
   const size_t per_seed_ws = L * NC * 8 + L * 4 + (24 + 24 * ts + 20) + 8;
   const size_t per_seed_fit = L * (3 * ts + 1) + 27 * ts + 16 + L * 4;
-  const size_t bins = L * ((size_t)cfg.n_zbins * cfg.n_phibins * 8 + 8);
+  const size_t bin_rows = cfg.n_etabins > 0 ? (size_t)cfg.n_etabins : (size_t)cfg.n_zbins;
+  const size_t bins = L * (bin_rows * cfg.n_phibins * 8 + 8);
   return rows * per_row + (size_t)n * (per_seed_in + per_seed_ws + per_seed_fit) +
          (size_t)nh * (3 * ts * 2 + 8) + bins;
 }

@@ -45,21 +45,27 @@ def oracle_batch(orc, bs, **kw):
     return cat
 
 
-@pytest.mark.parametrize("case", ["packed", "wide_group", "many_bins"])
+@pytest.mark.parametrize("case", ["packed", "wide_group", "many_bins", "eta", "eta_wide_group"])
 def test_bins_match_oracle(k, orc, case):
     """The binning paths: groups of at most 32,768 hits (one block per group,
     16-bit LDS tables), and the multi-kernel path over all hits for a group
-    above that and for a table of more than 32,768 bins."""
+    above that and for a table of more than 32,768 bins; and rows of 21
+    eta bins (the paper's projective partition) on both paths."""
     nz, nphi = 64, 512
-    if case == "packed":
+    eta = case.startswith("eta")
+    if case in ("packed", "eta"):
         bs = small_batch(1, 3, 400, n_layers=6)
-    elif case == "wide_group":
+    elif case in ("wide_group", "eta_wide_group"):
         bs = small_batch(2, 1, 30_000, n_layers=4)
         assert np.diff(bs.hit_off).max() > 32_768
     else:
         bs = small_batch(3, 2, 300, n_layers=4)
         nz = 128
-    ctx = ctx_for(k, bs.det, n_zbins=nz, n_phibins=nphi)
+    if eta:
+        nz = 21
+        ctx = ctx_for(k, bs.det, n_etabins=nz, eta_max=1.2, n_phibins=nphi)
+    else:
+        ctx = ctx_for(k, bs.det, n_zbins=nz, n_phibins=nphi)
     for prec in ("fp64", "fp32b"):
         d = build_inputs(bs, prec, hit_pad=64)
         offs, perm = ctx.bin_hits(d)
@@ -69,7 +75,7 @@ def test_bins_match_oracle(k, orc, case):
             for l in range(L):
                 g = e * L + l
                 h = bs.layer_hits(e, l)
-                oo, op = orc.bin_layer(h, 100.0, nz, nphi)
+                oo, op = orc.bin_layer_eta(h, 1.2, nz, nphi) if eta else orc.bin_layer(h, 100.0, nz, nphi)
                 a, b = bs.hit_off[g], bs.hit_off[g + 1]
                 assert np.array_equal(offs[g], oo), (prec, e, l)
                 assert np.array_equal(perm[a:b], op), (prec, e, l)
@@ -139,6 +145,27 @@ def test_fp64_build_matches_oracle(k, orc, ghosts, seed_order):
     assert (o["dbg_n"] > 1).any()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32b"])
+def test_eta_bins_build(k, orc, prec):
+    """Building over the eta partition (21 eta bins by 512 phi bins, the
+    window mapped to eta conservatively): FP64 hit indices, hit counts and
+    every layer's kept (parent, hit) lists exactly the oracle's brute force,
+    and in both precisions every output bit for bit that of the z bins."""
+    bs = small_batch(11, 3, 300, ghosts=True)
+    ctx_z = ctx_for(k, bs.det)
+    ctx_e = ctx_for(k, bs.det, n_etabins=21, eta_max=1.2)
+    d = build_inputs(bs, prec)
+    gz = host(ctx_z.build(d, hist=True), bs.n_seeds)
+    ge = host(ctx_e.build(d, hist=True), bs.n_seeds)
+    for key in ("hit_idx", "nhits", "chi2", "state", "cov", "status", "count", "hist"):
+        assert np.array_equal(ge[key], gz[key], equal_nan=ge[key].dtype.kind == "f"), key
+    if prec == "fp64":
+        o = oracle_batch(orc, bs)
+        assert np.array_equal(ge["hit_idx"], o["hit_idx"])
+        assert np.array_equal(ge["count"], o["dbg_n"])
+        assert (o["dbg_n"] > 1).any()
+
+
 @pytest.mark.parametrize("nc,missed", [(1, 1), (3, 0), (16, 2)])
 def test_beam_widths(k, orc, nc, missed):
     bs = small_batch(3, 2, 150, n_layers=9, ghosts=True)
@@ -182,7 +209,8 @@ def test_config3_full_size_sampled(k, orc):
     """The full combinatorial-building workload (100 events x 5,000 tracks,
     17 layers, 20% noise) in one batch; sampled seeds checked against the
     brute-force oracle, FP64 exactly and FP32-bulk up to certified ties; the
-    library's seed order gives every seed the same hits."""
+    library's seed order and the eta partition give every seed the same
+    hits."""
     bs = tg.config3()
     ctx = ctx_for(k, bs.det)
     rng = np.random.default_rng(5)
@@ -191,12 +219,13 @@ def test_config3_full_size_sampled(k, orc):
         d = build_inputs(bs, prec)
         res[prec] = host(ctx.build(d, hist=True), bs.n_seeds)
         del d
-    ctx1 = ctx_for(k, bs.det, seed_order=1)
-    for prec in ("fp64", "fp32b"):
-        g1 = host(ctx1.build(build_inputs(bs, prec)), bs.n_seeds)
-        assert np.array_equal(g1["hit_idx"], res[prec]["hit_idx"]), prec
-        assert np.array_equal(g1["chi2"], res[prec]["chi2"]), prec
-    ctx1.close()
+    for kw in (dict(seed_order=1), dict(n_etabins=21, eta_max=1.2)):
+        ctx1 = ctx_for(k, bs.det, **kw)
+        for prec in ("fp64", "fp32b"):
+            g1 = host(ctx1.build(build_inputs(bs, prec)), bs.n_seeds)
+            assert np.array_equal(g1["hit_idx"], res[prec]["hit_idx"]), (kw, prec)
+            assert np.array_equal(g1["chi2"], res[prec]["chi2"]), (kw, prec)
+        ctx1.close()
     # overall physics sanity: most seeds find their own particle's hits
     match = (res["fp64"]["hit_idx"] == bs.true_idx).all(axis=0)
     assert match.mean() > 0.95

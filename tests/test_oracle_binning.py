@@ -67,3 +67,40 @@ def test_csr_properties(orc):
 def test_empty_layer(orc):
     offs, perm = orc.bin_layer(np.zeros((3, 0)), 100.0, 64, 512)
     assert perm.size == 0 and np.all(offs == 0)
+
+
+def test_eta_is_minus_log_tan_half_theta(orc):
+    """The pseudorapidity of the eta partition (Sec. 3): -ln tan(theta / 2)
+    with theta the polar angle of the point seen from the origin."""
+    rng = np.random.default_rng(12)
+    for theta in np.concatenate([rng.uniform(0.05, math.pi - 0.05, 200), [math.pi / 2]]):
+        rho = rng.uniform(3.0, 70.0)
+        ph = rng.uniform(-math.pi, math.pi)
+        h = np.array([rho * math.cos(ph), rho * math.sin(ph), rho / math.tan(theta)])
+        assert abs(orc.eta(h) - (-math.log(math.tan(theta / 2)))) <= 1e-12 * max(1.0, abs(math.log(math.tan(theta / 2))))
+    assert orc.eta(np.array([4.0, 0.0, 0.0])) == 0.0
+
+
+def test_eta_bins_closed_form(orc):
+    """21 eta bins over |eta| < 1.2 by 8 phi bins: points placed at the
+    centre of eta bin k and phi bin j on cylinders of several radii land in
+    bin (k, j); points beyond |eta| = 1.2 land in the edge rows; within a
+    bin hits stay in index order."""
+    ne, nphi, em = 21, 8, 1.2
+    w = 2 * em / ne
+    pts, want = [], []
+    for k in range(ne):
+        for j in range(nphi):
+            for rho in (4.0, 37.0, 68.0):
+                eta = -em + (k + 0.5) * w
+                ph = -math.pi + (j + 0.5) * 2 * math.pi / nphi
+                pts.append((rho * math.cos(ph), rho * math.sin(ph), rho * math.sinh(eta)))
+                want.append(k * nphi + j)
+    for eta, row in ((1.5, ne - 1), (-2.0, 0), (3.0, ne - 1)):
+        pts.append((10.0, 0.0, 10.0 * math.sinh(eta)))
+        want.append(row * nphi + nphi // 2)
+    hits = np.array(pts).T
+    offs, perm = orc.bin_layer_eta(hits, em, ne, nphi)
+    want = np.array(want)
+    assert np.array_equal(perm, np.argsort(want, kind="stable"))
+    assert np.array_equal(offs, np.concatenate([[0], np.cumsum(np.bincount(want, minlength=ne * nphi))]))
