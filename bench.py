@@ -66,16 +66,26 @@ def kernel_sources_sha():
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (scaled by a plain copy of known size), or None when the
-    kernel sources changed since those counters were taken."""
+    """HBM bytes per launch of one kernel instance (its full template name)
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a
+    plain copy of known size, or None when the kernel sources changed since
+    those counters were taken or that instance was not measured."""
     try:
-        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        rd, wr = t["kernels"][kernel][:2]
     except (OSError, KeyError, ValueError):
         return None
     if t.get("source_sha") != kernel_sources_sha():
         return None
-    return t["fetch_bytes"] + t["write_bytes"]
+    return rd + wr
+
+
+def fit_kernel_name(ts, tp, tc, launch):
+    """Template name of the fused-fit instance a tuned launch runs."""
+    b, w, k = launch["block"], launch["waves_per_simd"], launch.get("tracks_per_lane", 1)
+    if launch.get("persistent"):
+        return f"fit_persistent_kernel<{ts}, {tp}, {tc}, {b}, {w}, false, {k}>"
+    return f"fit_fused_kernel<{ts}, {tp}, {tc}, {b}, {w}, false, false, {k}>"
 
 
 def parse():
@@ -685,7 +695,9 @@ def main():
 
     # roofline of the headline kernel: ALU bound, the reference flop model
     # with F P F^T in FP64; our own count beside it
-    hp = "fit_fused_kernel<float,float,double>"
+    launch_p = json.loads(ctx.tuned_shape("fp32p", n))
+    launch_b = json.loads(ctx.tuned_shape("fp32b", n))
+    hp = fit_kernel_name("float", "float", "double", launch_p)
     ref = roofline_of((REF_PROP - REF_FPF) * L * n, (REF_UPD + REF_FPF) * L * n, k_ms)
     own = roofline_of((OWN_PROP - OWN_FPF) * L * n, (OWN_UPD + OWN_FPF) * L * n, k_ms)
     traffic = measured_traffic(hp)
@@ -701,10 +713,10 @@ def main():
             "hbm_GBps": round(fused_bytes_per_track(4, L) * n / (k_ms * 1e-3) / 1e9, 1)}
     r32 = roofline_of(REF_PROP * L * n, REF_UPD * L * n, k32_ms)
     o32 = roofline_of(OWN_PROP * L * n, OWN_UPD * L * n, k32_ms)
-    t32 = measured_traffic("fit_fused_kernel<float,float,float>")
+    t32 = measured_traffic(fit_kernel_name("float", "float", "float", launch_b))
     sweep = {}
-    for name, msv, kern in [("fp32b", ms32_sw, "fit_layer_kernel<float,float>"),
-                            ("fp64", ms64_sw, "fit_layer_kernel<double,double>")]:
+    for name, msv, kern in [("fp32b", ms32_sw, "fit_layer_kernel<float, float, 256, false>"),
+                            ("fp64", ms64_sw, "fit_layer_kernel<double, double, 256, false>")]:
         pb = 4 if name == "fp32b" else 8
         by_ref = (SWEEP_REF_BYTES if pb == 4 else 465) * L * n
         by_model = sweep_bytes_per_track_layer(pb) * L * n
@@ -735,7 +747,7 @@ def main():
                    "tracks": n, "layers": L,
                    "precision": "float storage and float state propagation (path solve, helix, transport, "
                                 "Jacobian); covariance in double (F P F^T, S^-1, gain, Joseph update)",
-                   "launch": json.loads(ctx.tuned_shape("fp32p", n))},
+                   "launch": launch_p},
         "roofline": roof,
         "fp32_bulk": {"tracks_per_s": round(n / (ms32 * 1e-3)), "ms": round(ms32, 4),
                       "precision": "float propagation including F P F^T, covariance float between layers; "
@@ -743,7 +755,7 @@ def main():
                       "roofline_frac": round(r32["frac"], 4), "roofline_frac_own_count": round(o32["frac"], 4),
                       "t_bound_us": round(r32["t_bound_us"], 1), "kernel_ms": round(k32_ms, 4),
                       "traffic_MB": None if t32 is None else round(t32 / 1e6, 1),
-                      "launch": json.loads(ctx.tuned_shape("fp32b", n))},
+                      "launch": launch_b},
         "fp64_plain": {"tracks_per_s": round(n / (ms64 * 1e-3)), "ms": round(ms64, 4),
                        "launch": json.loads(ctx.tuned_shape("fp64", n))},
         "speedup_over_fp64": round(ms64 / ms, 3),
