@@ -1,8 +1,9 @@
 """Compile libktf.so (HIP for gfx950) in place, next to this file.
 
-Every translation unit under csrc/ is compiled with hipcc for gfx950 and
-linked into one shared library exporting the C-ABI of include/ktf.h.
-Packed FP32 instructions are disabled for all device code.
+Every HIP translation unit under csrc/ (*.hip) is compiled with hipcc for
+gfx950, the host-only ones (*.cpp, no HIP) with g++, and all are linked into
+one shared library exporting the C-ABI of include/ktf.h.  Packed FP32
+instructions are disabled for all device code.
 """
 import concurrent.futures as cf
 import glob
@@ -21,9 +22,15 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-command-line-argument"]
 
 
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
+
+
 def _compile(src):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = ["g++", *HOST_FLAGS, "-c", src, "-o", obj]
+    else:
+        cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -32,7 +39,7 @@ def _compile(src):
 
 def build(verbose=False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = min(len(srcs), max(1, (os.cpu_count() or 4) // 2), 8)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

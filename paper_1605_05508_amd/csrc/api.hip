@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "ctx.hpp"
+#include "host_logic.hpp"
 
 namespace ktf {
 
@@ -56,18 +57,7 @@ static int size_class(int64_t n) {
 }
 
 int check_fit_args(ktf_ctx* c, const ktf_fit_in* in, const ktf_fit_out* out) {
-  if (!c || !in || !out) return fail(c, KTF_EINVAL, "ktf_fit: null argument");
-  if (in->n < 0 || in->pitch < in->n)
-    return fail(c, KTF_EINVAL, "ktf_fit: n=%lld pitch=%lld", (long long)in->n, (long long)in->pitch);
-  if (in->prec != KTF_FP64 && in->prec != KTF_FP32_BULK && in->prec != KTF_FP32_PROP)
-    return fail(c, KTF_EINVAL, "ktf_fit: unknown precision %d", (int)in->prec);
-  if (in->n_passes < 0 || in->n_passes > KTF_MAX_PASSES)
-    return fail(c, KTF_EINVAL, "ktf_fit: n_passes %d outside 0..%d", (int)in->n_passes, KTF_MAX_PASSES);
-  if (in->n_passes > 1 && in->prec == KTF_FP32_BULK)
-    return fail(c, KTF_EINVAL, "ktf_fit: the iterated refit needs a double covariance (KTF_FP64 or KTF_FP32_PROP)");
-  if (in->n > 0 && (!in->seed_state || !in->seed_cov || !in->charge || !in->hits || !out->state ||
-                    !out->cov || !out->chi2 || !out->n_upd || !out->status))
-    return fail(c, KTF_EINVAL, "ktf_fit: null buffer");
+  if (const char* why = check_fit_in(in, out)) return fail(c, KTF_EINVAL, "ktf_fit: %s", why);
   return KTF_OK;
 }
 
@@ -159,27 +149,10 @@ extern "C" {
 int ktf_create(const ktf_config* cfg, ktf_ctx** out) {
   if (!cfg || !out) return KTF_EINVAL;
   *out = nullptr;
-  if (cfg->n_layers < 1 || cfg->n_layers > KTF_MAX_LAYERS || !cfg->layer_r) return KTF_EINVAL;
-  for (int l = 0; l < cfg->n_layers; ++l)
-    if (!(cfg->layer_r[l] > 0.0) || (l > 0 && !(cfg->layer_r[l] > cfg->layer_r[l - 1])))
-      return KTF_EINVAL;
-  if (!(cfg->sigma_r > 0.0) || !(cfg->sigma_rphi > 0.0) || !(cfg->sigma_z > 0.0)) return KTF_EINVAL;
-  if (cfg->max_cands < 1 || cfg->max_cands > KTF_MAX_CANDS || cfg->max_missed < 0 ||
-      cfg->n_seed_layers < 1 || cfg->n_seed_layers > cfg->n_layers || cfg->n_zbins < 1 ||
-      cfg->n_phibins < 1 || !(cfg->z_half > 0.0) || cfg->n_etabins < 0 ||
-      (cfg->n_etabins > 0 && !(cfg->eta_max > 0.0 && std::isfinite(cfg->eta_max))) ||
-      (int64_t)(cfg->n_etabins > 0 ? cfg->n_etabins : cfg->n_zbins) * cfg->n_phibins > INT32_MAX / 2)
-    return KTF_EINVAL;
+  if (check_config(cfg)) return KTF_EINVAL;
   bool material = false;
-  if (cfg->layer_x0) {
-    for (int l = 0; l < cfg->n_layers; ++l) {
-      if (!(cfg->layer_x0[l] >= 0.0) || !std::isfinite(cfg->layer_x0[l])) return KTF_EINVAL;
-      material = material || cfg->layer_x0[l] > 0.0;
-    }
-    if (material && (!(cfg->mass > 0.0) || !(cfg->eloss_per_x0 >= 0.0) || !std::isfinite(cfg->mass) ||
-                     !std::isfinite(cfg->eloss_per_x0)))
-      return KTF_EINVAL;
-  }
+  if (cfg->layer_x0)
+    for (int l = 0; l < cfg->n_layers; ++l) material = material || cfg->layer_x0[l] > 0.0;
   ktf_ctx* c = new ktf_ctx();
   c->cfg = *cfg;
   c->radii.assign(cfg->layer_r, cfg->layer_r + cfg->n_layers);

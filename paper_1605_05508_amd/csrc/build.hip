@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "ctx.hpp"
+#include "host_logic.hpp"
 #include "kf_math.hpp"
 
 namespace ktf {
@@ -1717,31 +1718,11 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
 }
 
 static int validate_batch(ktf_ctx* c, const ktf_event_batch* ev) {
-  const int L = c->cfg.n_layers;
-  if (ev->n_events < 0 || !ev->seed_off || !ev->hit_off)
-    return fail(c, KTF_EINVAL, "ktf_build: bad event batch");
-  if (ev->prec != KTF_FP64 && ev->prec != KTF_FP32_BULK)
-    return fail(c, KTF_EINVAL, "ktf_build: unknown precision");
-  if (ev->seed_off[0] != 0 || ev->hit_off[0] != 0)
-    return fail(c, KTF_EINVAL, "ktf_build: offsets must start at 0");
-  for (int e = 0; e < ev->n_events; ++e)
-    if (ev->seed_off[e + 1] < ev->seed_off[e]) return fail(c, KTF_EINVAL, "ktf_build: seed_off not monotone");
-  const int64_t G = (int64_t)ev->n_events * L;
-  for (int64_t g = 0; g < G; ++g) {
-    if (ev->hit_off[g + 1] < ev->hit_off[g]) return fail(c, KTF_EINVAL, "ktf_build: hit_off not monotone");
-    if (ev->hit_off[g + 1] - ev->hit_off[g] > INT32_MAX)
-      return fail(c, KTF_EINVAL, "ktf_build: too many hits in one layer");
-  }
-  const int64_t ns = ev->seed_off[ev->n_events];
-  const int64_t nh = ev->hit_off[G];
-  if (ev->seed_pitch < ns || ev->hit_pitch < nh) return fail(c, KTF_EINVAL, "ktf_build: pitch < size");
-  if (nh > INT32_MAX) return fail(c, KTF_EINVAL, "ktf_build: more than 2^31 hits in one batch");
-  if ((int64_t)c->cfg.max_cands * ev->seed_pitch > INT32_MAX ||
-      region_rows(ns, c->cfg.max_cands) * kRegions > INT32_MAX)
+  if (const char* why = check_event_batch(ev, c->cfg.n_layers, c->cfg.max_cands))
+    return fail(c, KTF_EINVAL, "ktf_build: %s", why);
+  // seed_pitch * max_cands < 2^31 here, so the row count cannot overflow
+  if (region_rows(ev->seed_off[ev->n_events], c->cfg.max_cands) * kRegions > INT32_MAX)
     return fail(c, KTF_EINVAL, "ktf_build: more than 2^31 candidate rows");
-  if (ns > 0 && (!ev->seed_state || !ev->seed_cov || !ev->charge || !ev->seed_hit))
-    return fail(c, KTF_EINVAL, "ktf_build: null seed buffer");
-  if (nh > 0 && !ev->hits) return fail(c, KTF_EINVAL, "ktf_build: null hits");
   return KTF_OK;
 }
 

@@ -15,6 +15,7 @@
 #include <memory>
 
 #include "ctx.hpp"
+#include "host_logic.hpp"
 #include "kf_math.hpp"
 
 namespace ktf {
@@ -114,25 +115,6 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// device bytes an event holds while in flight: inputs, outputs and its
-// share of the lane workspace (candidates, records, bins)
-static size_t footprint_of(const ktf_config& cfg, int64_t n, int64_t nh, ktf_precision prec) {
-  const size_t ts = prec == KTF_FP64 ? 8 : 4;
-  const size_t L = cfg.n_layers, NC = cfg.max_cands;
-  const size_t per_seed_in = 27 * ts + 1 + 4 * cfg.n_seed_layers;
-  // candidate rows: max_cands per seed plus the slack of the 64 row regions
-  // per row: two candidate buffers, two propagated-state buffers, records,
-  // the row lists (seed x2, parent, hit) and the child chi2
-  const size_t per_row = 2 * (24 + 24 * ts + 12) + 2 * (24 + 24 * ts) + 16 * NC + 4 + 16 + 8;
-  const size_t rows = (size_t)n * NC + 64 * 257;
-  const size_t per_seed_ws = L * NC * 8 + L * 4 + (24 + 24 * ts + 20) + 8;
-  const size_t per_seed_fit = L * (3 * ts + 1) + 27 * ts + 16 + L * 4;
-  const size_t bin_rows = cfg.n_etabins > 0 ? (size_t)cfg.n_etabins : (size_t)cfg.n_zbins;
-  const size_t bins = L * (bin_rows * cfg.n_phibins * 8 + 8);
-  return rows * per_row + (size_t)n * (per_seed_in + per_seed_ws + per_seed_fit) +
-         (size_t)nh * (3 * ts * 2 + 8) + bins;
-}
-
 // --------------------------------------------------------------- kernels
 // fit inputs from the built tracks: the hit coordinates each seed took on
 // each layer, and a valid flag
@@ -170,8 +152,6 @@ __global__ void or_status(int64_t N, uint32_t* a, const uint32_t* b) {
 }
 
 // ------------------------------------------------------------- batching
-static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
 // pinned staging of a lane, grown geometrically like the device buffers
 // (pinning host memory takes milliseconds)
 static hipError_t ensure_pinned(void** p, size_t* have, size_t want) {
@@ -190,70 +170,6 @@ static hipError_t ensure_pinned(void** p, size_t* have, size_t want) {
   return e;
 }
 
-// Row copies between an event's host arrays and a batch's pinned staging.
-// A large batch's rows take a millisecond or more on one core, on the
-// path of every event in it, so above a few MB they are spread over a few
-// host threads.
-struct RowCopy {
-  const void* src;
-  void* dst;
-  int64_t n;     // elements
-  int size;      // bytes per element
-};
-
-static void run_copy(const RowCopy& t) { memcpy(t.dst, t.src, (size_t)t.n * t.size); }
-
-static void run_copies(const std::vector<RowCopy>& rows) {
-  size_t bytes = 0;
-  for (const RowCopy& t : rows) bytes += (size_t)t.n * t.size;
-  const int nt = bytes > ((size_t)4 << 20) ? 4 : 1;
-  if (nt == 1) {
-    for (const RowCopy& t : rows) run_copy(t);
-    return;
-  }
-  // rows cut into pieces of at most 256K elements, dealt round robin
-  std::vector<RowCopy> tasks;
-  constexpr int64_t kPiece = 256 * 1024;
-  for (const RowCopy& t : rows)
-    for (int64_t o = 0; o < t.n; o += kPiece)
-      tasks.push_back({static_cast<const char*>(t.src) + o * t.size, static_cast<char*>(t.dst) + o * t.size,
-                       std::min(kPiece, t.n - o), t.size});
-  std::vector<std::thread> th;
-  for (int w = 1; w < nt; ++w)
-    th.emplace_back([&tasks, w, nt] {
-      for (size_t i = w; i < tasks.size(); i += nt) run_copy(tasks[i]);
-    });
-  for (size_t i = 0; i < tasks.size(); i += nt) run_copy(tasks[i]);
-  for (std::thread& x : th) x.join();
-}
-
-// Byte offsets of a batch's outputs in the lane's output buffer: the part
-// the host reads (hit indices and the final fit's results) comes first and
-// is the only part copied back; the building's own fit outputs follow.
-struct OutLayout {
-  size_t hit, f_state, f_cov, f_chi2, f_nu, f_st, host;
-  size_t b_state, b_cov, b_chi2, b_nh, b_st, total;
-};
-
-template <typename TS>
-static OutLayout out_layout(int L, int64_t Np) {
-  OutLayout o;
-  o.hit = 0;
-  o.f_state = align256(o.hit + sizeof(int32_t) * L * Np);
-  o.f_cov = align256(o.f_state + sizeof(TS) * 6 * Np);
-  o.f_chi2 = align256(o.f_cov + sizeof(TS) * 21 * Np);
-  o.f_nu = align256(o.f_chi2 + sizeof(double) * Np);
-  o.f_st = align256(o.f_nu + sizeof(int32_t) * Np);
-  o.host = align256(o.f_st + sizeof(uint32_t) * Np);
-  o.b_state = o.host;
-  o.b_cov = align256(o.b_state + sizeof(TS) * 6 * Np);
-  o.b_chi2 = align256(o.b_cov + sizeof(TS) * 21 * Np);
-  o.b_nh = align256(o.b_chi2 + sizeof(double) * Np);
-  o.b_st = align256(o.b_nh + sizeof(int32_t) * Np);
-  o.total = align256(o.b_st + sizeof(uint32_t) * Np);
-  return o;
-}
-
 template <typename TS>
 static int launch_batch_t(ktf_ctx* c, Lane& ln) {
   const ktf_config& cfg = c->cfg;
@@ -270,54 +186,23 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
   ln.N = N;
   const int64_t Np = std::max<int64_t>(N, 1), Hp = std::max<int64_t>(H, 1);
   // packed inputs: offsets, hits [3][H], state [6][N], cov [21][N], seed_hit, q
-  std::vector<int64_t> hoff((size_t)E * L + 1);
-  ln.seed_off.assign(E + 1, 0);
-  {
-    int64_t hb = 0;
-    for (int e = 0; e < E; ++e) {
-      ServeEvent* ev = ln.batch[e];
-      ln.seed_off[e + 1] = ln.seed_off[e] + ev->n_seeds;
-      for (int l = 0; l < L; ++l) hoff[(size_t)e * L + l] = hb + ev->hit_off[l];
-      hb += ev->n_hits;
-    }
-    hoff[(size_t)E * L] = hb;
-  }
-  size_t o_soff = 0;
-  size_t o_hoff = align256(o_soff + sizeof(int64_t) * (E + 1));
-  size_t o_hits = align256(o_hoff + sizeof(int64_t) * hoff.size());
-  size_t o_state = align256(o_hits + sizeof(TS) * 3 * Hp);
-  size_t o_cov = align256(o_state + sizeof(TS) * 6 * Np);
-  size_t o_sh = align256(o_cov + sizeof(TS) * 21 * Np);
-  size_t o_q = align256(o_sh + sizeof(int32_t) * NSL * Np);
-  size_t in_bytes = align256(o_q + Np);
+  std::vector<EventRows> rows;
+  rows.reserve(E);
+  for (ServeEvent* ev : ln.batch)
+    rows.push_back({ev->n_seeds, ev->n_hits, ev->hit_off.data(), ev->hits.data(), ev->state.data(), ev->cov.data(),
+                    ev->q.data(), ev->seed_hit.data()});
+  std::vector<int64_t> hoff;
+  batch_offsets(rows, L, ln.seed_off, hoff);
+  const InLayout il = in_layout(E, L, NSL, Np, Hp, sizeof(TS));
+  const size_t o_soff = il.soff, o_hoff = il.hoff, o_hits = il.hits, o_state = il.state, o_cov = il.cov,
+               o_sh = il.sh, o_q = il.q, in_bytes = il.total;
   hipError_t e;
   if ((e = ensure_pinned(&ln.pin_in, &ln.pin_in_bytes, in_bytes)) != hipSuccess) return hip_fail(c, e, "serve staging");
   if ((e = ln.in.ensure(in_bytes)) != hipSuccess) return hip_fail(c, e, "serve inputs");
   char* P = static_cast<char*>(ln.pin_in);
-  memcpy(P + o_soff, ln.seed_off.data(), sizeof(int64_t) * (E + 1));
-  memcpy(P + o_hoff, hoff.data(), sizeof(int64_t) * hoff.size());
   {
-    TS* hh = reinterpret_cast<TS*>(P + o_hits);
-    TS* st = reinterpret_cast<TS*>(P + o_state);
-    TS* cv = reinterpret_cast<TS*>(P + o_cov);
-    int32_t* sh = reinterpret_cast<int32_t*>(P + o_sh);
-    int8_t* qq = reinterpret_cast<int8_t*>(P + o_q);
-    int64_t sb = 0, hb = 0;
     std::vector<RowCopy> tasks;
-    for (ServeEvent* ev : ln.batch) {
-      const int64_t n = ev->n_seeds, nh = ev->n_hits;
-      // rows of the event into rows of the batch
-      const TS* eh = reinterpret_cast<const TS*>(ev->hits.data());
-      const TS* es = reinterpret_cast<const TS*>(ev->state.data());
-      const TS* ec = reinterpret_cast<const TS*>(ev->cov.data());
-      for (int k = 0; k < 3; ++k) tasks.push_back({eh + k * nh, hh + k * H + hb, nh, (int)sizeof(TS)});
-      for (int k = 0; k < 6; ++k) tasks.push_back({es + k * n, st + k * N + sb, n, (int)sizeof(TS)});
-      for (int k = 0; k < 21; ++k) tasks.push_back({ec + k * n, cv + k * N + sb, n, (int)sizeof(TS)});
-      for (int k = 0; k < NSL; ++k) tasks.push_back({ev->seed_hit.data() + k * n, sh + k * N + sb, n, 4});
-      tasks.push_back({ev->q.data(), qq + sb, n, 1});
-      sb += n;
-      hb += nh;
-    }
+    pack_rows(rows, L, NSL, sizeof(TS), ln.seed_off, hoff, P, il, tasks);
     run_copies(tasks);
   }
   if ((e = hipMemcpyAsync(ln.in.p, P, in_bytes, hipMemcpyHostToDevice, ln.stream)) != hipSuccess)
@@ -326,7 +211,7 @@ static int launch_batch_t(ktf_ctx* c, Lane& ln) {
 
   // outputs of building and fit: what goes back to the host first (hit
   // indices, the fit's results), then the building's own fit outputs
-  const OutLayout ol = out_layout<TS>(L, Np);
+  const OutLayout ol = out_layout(L, Np, sizeof(TS));
   const size_t b_hit = ol.hit, f_state = ol.f_state, f_cov = ol.f_cov, f_chi2 = ol.f_chi2, f_nu = ol.f_nu,
                f_st = ol.f_st, b_state = ol.b_state, b_cov = ol.b_cov, b_chi2 = ol.b_chi2, b_nh = ol.b_nh,
                b_st = ol.b_st, out_bytes = ol.total;
@@ -390,29 +275,16 @@ template <typename TS>
 static void unpack_batch_t(ktf_ctx* c, Lane& ln) {
   const int L = c->cfg.n_layers;
   const int64_t N = ln.N, Np = std::max<int64_t>(N, 1);
-  const OutLayout ol = out_layout<TS>(L, Np);
-  const char* O = static_cast<const char*>(ln.pin_out);
-  const int32_t* hit = reinterpret_cast<const int32_t*>(O + ol.hit);
-  const TS* st = reinterpret_cast<const TS*>(O + ol.f_state);
-  const TS* cv = reinterpret_cast<const TS*>(O + ol.f_cov);
-  const double* c2 = reinterpret_cast<const double*>(O + ol.f_chi2);
-  const int32_t* nu = reinterpret_cast<const int32_t*>(O + ol.f_nu);
-  const uint32_t* ss = reinterpret_cast<const uint32_t*>(O + ol.f_st);
-  int64_t sb = 0;
-  std::vector<RowCopy> tasks;
+  std::vector<int64_t> ns;
+  std::vector<ResultRows> res;
   for (ServeEvent* ev : ln.batch) {
     const int64_t n = ev->n_seeds;
-    int32_t* r_hit = ev->r_hit.get((size_t)L * n);
-    TS* r_state = reinterpret_cast<TS*>(ev->r_state.get(sizeof(TS) * 6 * n));
-    TS* r_cov = reinterpret_cast<TS*>(ev->r_cov.get(sizeof(TS) * 21 * n));
-    for (int l = 0; l < L; ++l) tasks.push_back({hit + l * N + sb, r_hit + l * n, n, 4});
-    for (int k = 0; k < 6; ++k) tasks.push_back({st + k * N + sb, r_state + k * n, n, (int)sizeof(TS)});
-    for (int k = 0; k < 21; ++k) tasks.push_back({cv + k * N + sb, r_cov + k * n, n, (int)sizeof(TS)});
-    tasks.push_back({c2 + sb, ev->r_chi2.get(n), n, 8});
-    tasks.push_back({nu + sb, ev->r_nh.get(n), n, 4});
-    tasks.push_back({ss + sb, ev->r_st.get(n), n, 4});
-    sb += n;
+    ns.push_back(n);
+    res.push_back({ev->r_hit.get((size_t)L * n), ev->r_state.get(sizeof(TS) * 6 * n),
+                   ev->r_cov.get(sizeof(TS) * 21 * n), ev->r_chi2.get(n), ev->r_nh.get(n), ev->r_st.get(n)});
   }
+  std::vector<RowCopy> tasks;
+  unpack_rows(ns, res, L, sizeof(TS), Np, static_cast<const char*>(ln.pin_out), out_layout(L, Np, sizeof(TS)), tasks);
   run_copies(tasks);
 }
 
@@ -579,14 +451,8 @@ int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
   if (!c || !ev || !ticket) return KTF_EINVAL;
   const ktf_config& cfg = c->cfg;
   const int L = cfg.n_layers, NSL = cfg.n_seed_layers;
-  if (ev->n_seeds < 0 || !ev->hit_off || (ev->prec != KTF_FP64 && ev->prec != KTF_FP32_BULK))
-    return fail(c, KTF_EINVAL, "ktf_submit: bad event");
-  if (ev->hit_off[0] != 0) return fail(c, KTF_EINVAL, "ktf_submit: hit_off[0] != 0");
-  for (int l = 0; l < L; ++l)
-    if (ev->hit_off[l + 1] < ev->hit_off[l]) return fail(c, KTF_EINVAL, "ktf_submit: hit_off not monotone");
+  if (const char* why = check_event_host(ev, L)) return fail(c, KTF_EINVAL, "ktf_submit: %s", why);
   const int64_t n = ev->n_seeds, nh = ev->hit_off[L];
-  if ((n > 0 && (!ev->seed_state || !ev->seed_cov || !ev->charge || !ev->seed_hit)) || (nh > 0 && !ev->hits))
-    return fail(c, KTF_EINVAL, "ktf_submit: null buffer");
   const size_t fp = footprint_of(cfg, n, nh, ev->prec);
   const size_t ts = ev->prec == KTF_FP64 ? 8 : 4;
   if (fp > cfg.hbm_budget_bytes)
@@ -600,7 +466,7 @@ int ktf_submit(ktf_ctx* c, const ktf_event_host* ev, uint64_t* ticket) {
     // a collected event whose buffers already hold this one's hits, else
     // the largest one kept
     std::lock_guard<std::mutex> g(S->mu);
-    const size_t need = (size_t)(3 * nh);
+    const size_t need = ts * 3 * (size_t)nh;
     int fit = -1, big = -1;
     for (int i = 0; i < (int)S->pool.size(); ++i) {
       const size_t cap = S->pool[i]->hits.cap;
