@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "ctx.hpp"
@@ -170,17 +171,31 @@ template <> struct __align__(16) BinHit<double> {
   int32_t id, pad;
 };
 
+// The phi bin in double, for the rare hits near a bin edge, and the eta
+// row: out of line, so that callers keep only the registers of the common
+// path (a z row from a float phi estimate).
+__device__ __attribute__((noinline)) int phi_bin_near_edge(double x, double y, int nphi) {
+#pragma clang fp contract(off)
+  const double phi = atan2(y, x);
+  return (int)floor((phi + kPi) * nphi / (2.0 * kPi));
+}
+__device__ __attribute__((noinline)) double eta_row_of(double x, double y, double z, double eta_max, int nz) {
+#pragma clang fp contract(off)
+  const double eta = asinh(z / sqrt(x * x + y * y));
+  return floor((eta + eta_max) * nz / (2.0 * eta_max));
+}
+
 // bin of a hit: its row is the z bin, zbin = floor((z + zh) nz / (2 zh))
 // clamped, or (eta rows) the eta bin, floor((asinh(z / rho) + eta_max) nz /
 // (2 eta_max)) clamped; the phi bin as below
+
 __device__ __forceinline__ int hit_bin_of(double x, double y, double z, const BuildGeom& g) {
 #pragma clang fp contract(off)
   const double zh = g.z_half;
   const int nz = g.n_zbins, nphi = g.n_phibins;
   double zf;
   if (g.eta_rows) {
-    const double eta = asinh(z / sqrt(x * x + y * y));
-    zf = floor((eta + g.eta_max) * nz / (2.0 * g.eta_max));
+    zf = eta_row_of(x, y, z, g.eta_max, nz);
   } else {
     zf = floor((z + zh) * nz / (2.0 * zh));
   }
@@ -198,8 +213,7 @@ __device__ __forceinline__ int hit_bin_of(double x, double y, double z, const Bu
   if (fr > mf && fr < 1.0f - mf) {
     pb = (int)fl;
   } else {
-    const double phi = atan2(y, x);
-    pb = (int)floor((phi + kPi) * nphi / (2.0 * kPi));
+    pb = phi_bin_near_edge(x, y, nphi);
   }
   pb = ((pb % nphi) + nphi) % nphi;
   return zb * nphi + pb;
@@ -321,13 +335,25 @@ constexpr int kLdsBins = 32768;
 // together, so a phase costs one memory round trip per batch.
 constexpr int kPackMaxHits = 32768;
 constexpr int kBinBatch = 8;
-template <typename TS>
-__global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
-  __shared__ uint32_t cnt[kLdsBins / 2];  // bin b in half b & 1 of word b >> 1
-  __shared__ uint16_t permr[kPackMaxHits];
+// MB batches of BB x kBinThreads hits: a group of at most MB x BB x 1024
+// hits.  The LDS holds the bin table (one word per two bins) and the
+// unordered scatter (one 16-bit index per hit), sized by the host for the
+// launch's bins and largest group, so that a layer of a few thousand hits
+// over 32,768 bins (78 KB) lets two blocks share a CU; batches of four
+// keep the registers within the eight waves per SIMD that two blocks need.
+template <int BB> struct BinWaves { static constexpr int v = BB == 4 ? 8 : 4; };
+inline size_t bin_lds_bytes(int n_bins, int64_t max_group) {
+  return (size_t)((n_bins + 1) >> 1) * 4 + (size_t)((max_group + 1) & ~int64_t(1)) * 2;
+}
+template <typename TS, int MB, int BB>
+__global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(BinWaves<BB>::v)))
+void bin_group16_kernel(BuildArgs a) {
+  extern __shared__ uint32_t bin_lds[];
   __shared__ int32_t wsum[kBinThreads / 64];
   const int g = blockIdx.x;
   const int nb = a.n_bins, nwords = (nb + 1) >> 1;
+  uint32_t* cnt = bin_lds;  // bin b in half b & 1 of word b >> 1
+  uint16_t* permr = reinterpret_cast<uint16_t*>(bin_lds + nwords);
   const int tid = threadIdx.x;
   const int64_t base = a.hit_off[g];
   const int32_t n = (int32_t)(a.hit_off[g + 1] - base);
@@ -336,10 +362,10 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
   for (int w = tid; w < nwords; w += kBinThreads) cnt[w] = 0;
   __syncthreads();
   // count
-  for (int32_t j0 = 0; j0 < n; j0 += kBinBatch * kBinThreads) {
-    TS x[kBinBatch], y[kBinBatch], z[kBinBatch];
+  for (int32_t j0 = 0; j0 < n; j0 += BB * kBinThreads) {
+    TS x[BB], y[BB], z[BB];
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
       x[u] = y[u] = z[u] = TS(0);
       if (j < n) {
@@ -349,7 +375,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
       }
     }
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
       if (j < n) {
         const int b = hit_bin_of((double)x[u], (double)y[u], (double)z[u], a.g);
@@ -389,15 +415,15 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
   if (tid == 0) off[nb] = n;
   __syncthreads();
   // scatter through the cursors (a bin's cursor ends at the next offset)
-  for (int32_t j0 = 0; j0 < n; j0 += kBinBatch * kBinThreads) {
-    int bb[kBinBatch];
+  for (int32_t j0 = 0; j0 < n; j0 += BB * kBinThreads) {
+    int bb[BB];
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
       bb[u] = j < n ? a.hit_bin[base + j] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
       if (j < n) {
         const int sh = (bb[u] & 1) * 16;
@@ -411,19 +437,19 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
   // bin's hits with a smaller index; the places stay in registers until all
   // are taken, then the permutation goes to LDS and out in coalesced rows
   // (scattered 4-byte stores would each cost HBM a line)
-  constexpr int kMaxBatches = kPackMaxHits / (kBinBatch * kBinThreads);
-  int dst[kMaxBatches][kBinBatch];
+  constexpr int kMaxBatches = MB;
+  int dst[kMaxBatches][BB];
 #pragma unroll
   for (int bi = 0; bi < kMaxBatches; ++bi) {
-    const int32_t j0 = bi * kBinBatch * kBinThreads;
-    int bb[kBinBatch];
+    const int32_t j0 = bi * BB * kBinThreads;
+    int bb[BB];
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
       bb[u] = j < n ? a.hit_bin[base + j] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t j = j0 + u * kBinThreads + tid;
       dst[bi][u] = -1;
       if (j < n) {
@@ -440,20 +466,20 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
 #pragma unroll
   for (int bi = 0; bi < kMaxBatches; ++bi)
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u)
-      if (dst[bi][u] >= 0) permr[dst[bi][u]] = (uint16_t)(bi * kBinBatch * kBinThreads + u * kBinThreads + tid);
+    for (int u = 0; u < BB; ++u)
+      if (dst[bi][u] >= 0) permr[dst[bi][u]] = (uint16_t)(bi * BB * kBinThreads + u * kBinThreads + tid);
   __syncthreads();
   BinHit<TS>* o = static_cast<BinHit<TS>*>(a.hb);
-  for (int32_t i0 = 0; i0 < n; i0 += kBinBatch * kBinThreads) {
-    int32_t jj[kBinBatch];
-    TS x[kBinBatch], y[kBinBatch], z[kBinBatch];
+  for (int32_t i0 = 0; i0 < n; i0 += BB * kBinThreads) {
+    int32_t jj[BB];
+    TS x[BB], y[BB], z[BB];
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t i = i0 + u * kBinThreads + tid;
       jj[u] = i < n ? (int32_t)permr[i] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t i = i0 + u * kBinThreads + tid;
       x[u] = y[u] = z[u] = TS(0);
       if (i < n) {
@@ -463,7 +489,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_group16_kernel(BuildArgs a) {
       }
     }
 #pragma unroll
-    for (int u = 0; u < kBinBatch; ++u) {
+    for (int u = 0; u < BB; ++u) {
       const int32_t i = i0 + u * kBinThreads + tid;
       if (i < n) {
         const int64_t d = base + i;
@@ -1659,12 +1685,33 @@ static void launch_merge(const BuildArgs& a, int l, int cur, hipStream_t st) {
   }
 }
 
+// a launch with more than 64 KB of dynamic LDS first raises the kernel's
+// limit to what it asks for
+template <typename... P, typename... A>
+static hipError_t launch_dyn_lds(void (*k)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t st, A&&... args) {
+  if (lds > 65536) {
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, grid, block, lds, st, std::forward<A>(args)...);
+  return hipGetLastError();
+}
+
 template <typename TS, typename TP>
 static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) {
   const int bs = 256;
   const int64_t nbins_all = (int64_t)a.n_groups * a.n_bins;
   if (nbins_all > 0 && a.n_bins <= kLdsBins && a.max_group <= kPackMaxHits) {
-    hipLaunchKernelGGL((bin_group16_kernel<TS>), dim3(a.n_groups), dim3(kBinThreads), 0, st, a);
+    const size_t lds = bin_lds_bytes(a.n_bins, a.max_group);
+    hipError_t e = hipSuccess;
+    if (a.max_group <= 2 * 4 * kBinThreads)
+      e = launch_dyn_lds(bin_group16_kernel<TS, 2, 4>, dim3(a.n_groups), dim3(kBinThreads), lds, st, a);
+    else if (a.max_group <= 2 * kBinBatch * kBinThreads)
+      e = launch_dyn_lds(bin_group16_kernel<TS, 2, kBinBatch>, dim3(a.n_groups), dim3(kBinThreads), lds, st, a);
+    else
+      e = launch_dyn_lds(bin_group16_kernel<TS, 4, kBinBatch>, dim3(a.n_groups), dim3(kBinThreads), lds, st, a);
+    if (e != hipSuccess) return e;
   } else if (nbins_all > 0) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nbins_all, bs)), dim3(bs), 0, st, a.bin_cur, nbins_all, 0);
     if (a.n_hits > 0)
