@@ -57,6 +57,17 @@ def fused_bytes_per_track(prec_bytes, n_layers):
     return (27 * prec_bytes + 1 + n_layers * (3 * prec_bytes + 1)) + (27 * prec_bytes + 8 + 4 + 4)
 
 
+def cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -781,7 +792,10 @@ def main():
         result["cpu_baseline"] = {"value": round(m / t_cpu), "unit": "tracks/s", "cores": cores,
                                   "kind": "oracle",
                                   "sample": f"first {m} of the {n} tracks, FP64 scalar C, "
-                                            f"{cores} threads, wall {t_cpu:.2f} s"}
+                                            f"{cores} threads, wall {t_cpu:.2f} s",
+                                  "value_1core": round(1.0 / per_track),
+                                  "sample_1core": f"first {probe} tracks on one thread",
+                                  "cpu_model": cpu_model(), "nproc": os.cpu_count()}
         # accuracy of every GPU path on the oracle's sample
         from tests.helpers import fp32_errors, param_rel_errors, pulls
         acc = {}
