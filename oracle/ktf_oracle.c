@@ -530,10 +530,20 @@ static int cmp_bin_key(const void *a, const void *b) {
   return (x->idx > y->idx) - (x->idx < y->idx);
 }
 
+/* A hit with a coordinate that is not a number has no place in a bin
+ * formula; it goes to the first z (eta) row and phi bin 0, so that it is
+ * kept, and no window reaches it in a way that matters: its chi2 is not
+ * below any cut. */
 static int32_t phi_bin(const double *h, int32_t nphi) {
   double phi = atan2(h[1], h[0]);
-  int32_t pb = (int32_t)floor((phi + ORC_PI) * nphi / (2.0 * ORC_PI));
+  double pf = floor((phi + ORC_PI) * nphi / (2.0 * ORC_PI));
+  if (!(pf == pf)) return 0;
+  int32_t pb = (int32_t)pf;
   return ((pb % nphi) + nphi) % nphi;
+}
+
+static int32_t row_of(double f, int32_t nrows) {
+  return f >= 0.0 ? (f > nrows - 1 ? nrows - 1 : (int32_t)f) : 0;
 }
 
 static void bin_sort(int64_t n, bin_key *keys, int32_t nb, int32_t *offsets, int32_t *perm);
@@ -543,8 +553,7 @@ void orc_bin_layer(int64_t n, const double *hits, double z_half, int32_t nz, int
   bin_key *keys = (bin_key *)malloc(sizeof(bin_key) * (size_t)(n > 0 ? n : 1));
   for (int64_t i = 0; i < n; ++i) {
     const double *h = hits + 3 * i;
-    double zf = floor((h[2] + z_half) * nz / (2.0 * z_half));
-    int32_t zb = zf < 0.0 ? 0 : (zf > nz - 1 ? nz - 1 : (int32_t)zf);
+    int32_t zb = row_of(floor((h[2] + z_half) * nz / (2.0 * z_half)), nz);
     keys[i].bin = zb * nphi + phi_bin(h, nphi);
     keys[i].idx = (int32_t)i;
   }
@@ -561,8 +570,7 @@ void orc_bin_layer_eta(int64_t n, const double *hits, double eta_max, int32_t ne
   bin_key *keys = (bin_key *)malloc(sizeof(bin_key) * (size_t)(n > 0 ? n : 1));
   for (int64_t i = 0; i < n; ++i) {
     const double *h = hits + 3 * i;
-    double ef = floor((orc_eta(h) + eta_max) * neta / (2.0 * eta_max));
-    int32_t eb = ef < 0.0 ? 0 : (ef > neta - 1 ? neta - 1 : (int32_t)ef);
+    int32_t eb = row_of(floor((orc_eta(h) + eta_max) * neta / (2.0 * eta_max)), neta);
     keys[i].bin = eb * nphi + phi_bin(h, nphi);
     keys[i].idx = (int32_t)i;
   }

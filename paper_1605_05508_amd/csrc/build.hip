@@ -177,7 +177,8 @@ template <> struct __align__(16) BinHit<double> {
 __device__ __attribute__((noinline)) int phi_bin_near_edge(double x, double y, int nphi) {
 #pragma clang fp contract(off)
   const double phi = atan2(y, x);
-  return (int)floor((phi + kPi) * nphi / (2.0 * kPi));
+  const double pf = floor((phi + kPi) * nphi / (2.0 * kPi));
+  return pf == pf ? (int)pf : 0;  // a coordinate that is not a number: bin 0
 }
 __device__ __attribute__((noinline)) double eta_row_of(double x, double y, double z, double eta_max, int nz) {
 #pragma clang fp contract(off)
@@ -199,7 +200,8 @@ __device__ __forceinline__ int hit_bin_of(double x, double y, double z, const Bu
   } else {
     zf = floor((z + zh) * nz / (2.0 * zh));
   }
-  const int zb = zf < 0.0 ? 0 : (zf > nz - 1 ? nz - 1 : (int)zf);
+  // (not a number: the first row, as a number below the range)
+  const int zb = zf >= 0.0 ? (zf > nz - 1 ? nz - 1 : (int)zf) : 0;
   // the phi bin from a float estimate of its position, unless that lies
   // within 1e-5 rad of a bin edge: the float angle's error (coordinates
   // rounded to float, atan2f, the sum and the scale) is below 2e-6 rad, so
@@ -542,10 +544,10 @@ __global__ void seed_key_kernel(BuildArgs a) {
     py = xo.pos[1];
     pz = xo.pos[2];
   }
-  int cp = (int)((atan2f((float)py, (float)px) + (float)kPi) * (float)(256.0 / (2.0 * kPi)));
-  int cz = (int)floor((pz + a.g.z_half) * (32.0 / (2.0 * a.g.z_half)));
-  cp = cp < 0 ? 0 : (cp > 255 ? 255 : cp);
-  cz = cz < 0 ? 0 : (cz > 31 ? 31 : cz);
+  // clamped before the conversion (a position that is not a number: cell 0)
+  const int cp = (int)fminf(255.0f, fmaxf(0.0f, (atan2f((float)py, (float)px) + (float)kPi) *
+                                                     (float)(256.0 / (2.0 * kPi))));
+  const int cz = (int)fmin(31.0, fmax(0.0, floor((pz + a.g.z_half) * (32.0 / (2.0 * a.g.z_half)))));
   int key = 0;
 #pragma unroll
   for (int b = 0; b < 5; ++b) key |= (((cz >> b) & 1) << (2 * b)) | (((cp >> b) & 1) << (2 * b + 1));
@@ -1021,8 +1023,8 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     zlo = (int)fmax(-1.0, floor((e0 + em) * nz / (2.0 * em)));
     zhi = (int)fmin((double)nz, floor((e1 + em) * nz / (2.0 * em)));
   } else {
-    zlo = (int)floor((zp - bzw + zh) * nz / (2.0 * zh));
-    zhi = (int)floor((zp + bzw + zh) * nz / (2.0 * zh));
+    zlo = (int)fmax(-1.0, floor((zp - bzw + zh) * nz / (2.0 * zh)));
+    zhi = (int)fmin((double)nz, floor((zp + bzw + zh) * nz / (2.0 * zh)));
   }
   zlo = max(0, min(nz - 1, zlo));
   zhi = max(0, min(nz - 1, zhi));

@@ -119,6 +119,43 @@ def test_bins_at_phi_edges(k, orc):
                 assert np.array_equal(perm[a:b], op), (prec, e, l)
 
 
+@pytest.mark.parametrize("eta", [False, True])
+def test_bins_and_build_with_not_a_number_hits(k, orc, eta):
+    """Hits with a coordinate that is not a number (x, y, z or all) bin as
+    the oracle bins them (the first row, phi bin 0 without x or y), on the
+    one-block path and on the multi-kernel path (a group above 32,768 hits),
+    and building around them gives the oracle's hits: their chi2 is never
+    below the cut."""
+    nan = np.float32("nan")
+    for n_tracks, n_layers in ((400, 6), (30_000, 4)):
+        bs = small_batch(11, 1, n_tracks, n_layers=n_layers)
+        L = bs.det.n_layers
+        rng = np.random.default_rng(12)
+        for l in range(L):  # one event: group l is layer l
+            a, b = bs.hit_off[l], bs.hit_off[l + 1]
+            loc = rng.choice(b - a, 12, replace=False)
+            loc = loc[~np.isin(loc, bs.true_idx[l])]  # no seed's own hit
+            for j, h in enumerate(a + loc):
+                bs.hits[[[0], [1], [2], [0, 1, 2]][j % 4], h] = nan
+        kw = dict(n_etabins=21, eta_max=1.2) if eta else {}
+        ctx = ctx_for(k, bs.det, **kw)
+        for prec in ("fp64", "fp32b"):
+            offs, perm = ctx.bin_hits(build_inputs(bs, prec, hit_pad=64))
+            offs, perm = offs.cpu().numpy(), perm.cpu().numpy()
+            for l in range(L):
+                h = bs.layer_hits(0, l)
+                oo, op = orc.bin_layer_eta(h, 1.2, 21, 512) if eta else orc.bin_layer(h, 100.0, 64, 512)
+                a, b = bs.hit_off[l], bs.hit_off[l + 1]
+                assert np.array_equal(offs[l], oo), (prec, l, n_tracks)
+                assert np.array_equal(perm[a:b], op), (prec, l, n_tracks)
+        if n_tracks <= 400:
+            g = host(ctx.build(build_inputs(bs, "fp64")), bs.n_seeds)
+            o = orc.build_event(bs, 0)
+            assert np.array_equal(g["hit_idx"], o["hit_idx"])
+            np.testing.assert_allclose(g["chi2"], o["chi2"], rtol=1e-10)
+        ctx.close()
+
+
 @pytest.mark.parametrize("ghosts", [False, True])
 @pytest.mark.parametrize("seed_order", [0, 1])
 def test_fp64_build_matches_oracle(k, orc, ghosts, seed_order):

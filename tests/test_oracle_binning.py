@@ -69,6 +69,33 @@ def test_empty_layer(orc):
     assert perm.size == 0 and np.all(offs == 0)
 
 
+def test_not_a_number_hits(orc):
+    """A hit with a coordinate that is not a number has no bin by the
+    formulas: its row is the first when the row's formula gives no number,
+    and its phi bin 0 when x or y is not a number.  The hit is kept; the
+    other hits bin as usual."""
+    nan = float("nan")
+    # 0: a plain hit; 1, 2: x or y not a number; 3: z not a number (phi
+    # bin of (5, -5): 192 of 512); 4: nothing a number
+    hits = np.array([[10.0, nan, 10.0, 5.0, nan],
+                     [0.5, 1.0, nan, -5.0, nan],
+                     [20.0, 3.0, -7.0, nan, nan]])
+    pb0 = int(np.floor((math.atan2(0.5, 10.0) + math.pi) * 512 / (2 * math.pi)))
+    zrow = lambda z: int(np.floor((z + 100.0) * 64 / 200.0))
+    offs, perm = orc.bin_layer(hits, 100.0, 64, 512)
+    bins = {0: [4], 192: [3], zrow(-7.0) * 512: [2], zrow(3.0) * 512: [1], zrow(20.0) * 512 + pb0: [0]}
+    for bb, idx in bins.items():
+        assert list(perm[offs[bb]:offs[bb + 1]]) == idx, bb
+    assert offs[-1] == 5
+    # eta rows: x or y not a number leaves no eta either (row 0, bin 0);
+    # hit 0 has eta asinh(20 / 10.01) > 1.2: the last of 21 rows
+    offs, perm = orc.bin_layer_eta(hits, 1.2, 21, 512)
+    bins = {0: [1, 2, 4], 192: [3], 20 * 512 + pb0: [0]}
+    for bb, idx in bins.items():
+        assert list(perm[offs[bb]:offs[bb + 1]]) == idx, bb
+    assert offs[-1] == 5
+
+
 def test_eta_is_minus_log_tan_half_theta(orc):
     """The pseudorapidity of the eta partition (Sec. 3): -ln tan(theta / 2)
     with theta the polar angle of the point seen from the origin."""
