@@ -44,11 +44,13 @@ def sweep_bytes_per_track_layer(prec_bytes):
     """HBM bytes of one layer step of one track in the per-layer sweep:
     read + write state (6) and covariance (21), read the hit (3) and its
     valid flag, charge, end layer, status, chi2 and hit count, write status,
-    chi2, hit count; FP32 storage adds the double position round trip."""
-    b = 2 * 27 * prec_bytes + 3 * prec_bytes + 1 + 1 + 1 + 2 * (4 + 8 + 4)
+    chi2, hit count.  FP32 storage carries the position in double between
+    layers instead of its stored float copy, which is written only where
+    the track ends."""
+    b = 3 * prec_bytes + 1 + 1 + 1 + 2 * (4 + 8 + 4)
     if prec_bytes == 4:
-        b += 2 * 3 * 8
-    return b
+        return b + 2 * 24 * prec_bytes + 2 * 3 * 8
+    return b + 2 * 27 * prec_bytes
 
 
 def fused_bytes_per_track(prec_bytes, n_layers):

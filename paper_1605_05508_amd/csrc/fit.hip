@@ -378,6 +378,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void fi
   if (!propagate<TP, NewtonIters<TP>::n>(x, k, a.radii[l], l == 0, xp, F)) {
     status |= kNoReach;
     if (l > 0) {
+      // the track ends with the layer before: its position, carried in
+      // double between layers, becomes the stored one now
+      if (a.pos_ws != nullptr) {
+        TS* so = static_cast<TS*>(a.state_o);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
+      }
       a.status[i] = status;
       return;
     }
@@ -403,12 +410,19 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void fi
   }
   TS* so = static_cast<TS*>(a.state_o);
   TS* co = static_cast<TS*>(a.cov_o);
-  if (a.pos_ws != nullptr) {  // float storage: positions carried in double
+  // float storage: positions are carried in double between layers and
+  // stored in the storage type only where the track ends (its last layer
+  // with a hit, or a layer it cannot leave: not reaching the next one is
+  // handled above, a state that is not finite stops it here)
+  const bool last = a.pos_ws == nullptr || l + 1 >= lend || (status & (kNoReach | kNonFinite));
+  if (a.pos_ws != nullptr) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.pos_ws[c * p + i] = x.pos[c];
   }
+  if (last) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
+    for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x.mom[c];
 #pragma unroll
