@@ -291,10 +291,13 @@ typedef struct {
 int ktf_build(ktf_ctx *ctx, const ktf_event_batch *ev, ktf_build_out *out, void *hip_stream);
 
 /* Bin the hits of every (event, layer) of a batch: offsets
- * [n_events*n_layers][n_zbins*n_phibins+1] (device int32, CSR within each
- * (event, layer)) and perm [hit_pitch] (device int32: original index, within
- * its (event, layer), of the hit at each binned position; binned positions
- * are ordered by (bin, original index)).  Exposed for tests and tools. */
+ * [n_events*n_layers][rows*n_phibins+1] (rows = n_etabins if > 0, else
+ * n_zbins; device int32, CSR within each (event, layer)) and perm
+ * [hit_pitch] (device int32: original index, within its (event, layer), of
+ * the hit at each binned position; binned positions are ordered by (bin,
+ * original index)).  A hit with a coordinate that is not a number is kept:
+ * in row 0 when its row has no number, in phi bin 0 when x or y is not a
+ * number.  Exposed for tests and tools. */
 int ktf_bin_hits(ktf_ctx *ctx, const ktf_event_batch *ev, int32_t *offsets, int32_t *perm,
                  void *hip_stream);
 
