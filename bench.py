@@ -353,11 +353,12 @@ def dense_events_workload(args):
 
 def shapes_workload(args):
     """Launch shape and problem size, the GPU's counterpart of the paper's
-    vector-width and thread-count scans (Sec. 3.2): the fused FP32-bulk fit's
-    time for every launch shape the tuner tries on 1e6 tracks (tracks per
-    block, register budget in waves per SIMD, plain or persistent grid), and
-    the tuned fit's throughput from 1e3 to 1e7 tracks (1e7 as ten copies of
-    the 1e6 tracks)."""
+    vector-width and thread-count scans (Sec. 3.2): the fused fit's time (in
+    the precision of --prec, the headline's by default) for every launch
+    shape the tuner tries on 1e6 tracks (tracks per block, register budget in
+    waves per SIMD, plain or persistent grid, tracks per lane), and the tuned
+    fit's throughput from 1e3 to 1e7 tracks (1e7 as ten copies of the 1e6
+    tracks)."""
     import torch
     import paper_1605_05508_amd as ktf
     import trackgen as tg
@@ -366,10 +367,13 @@ def shapes_workload(args):
     fs = tg.config2()
     n = fs.n
     ctx = ktf.Context.for_detector(fs.det)
-    d = fit_inputs(fs, "fp32b", pitch=n)
-    out = ctx.alloc_fit_out(n, n, torch.float32)
-    ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out)
-    tuned = json.loads(ctx.tuned_shape("fp32b", n, trials=True))
+    prec = args.prec
+    pp = None if prec == "fp32b" else prec
+    d = fit_inputs(fs, "fp64" if prec == "fp64" else "fp32b", pitch=n)
+    dt = d["state"].dtype
+    out = ctx.alloc_fit_out(n, n, dt)
+    ctx.autotune_fit(d["state"], d["cov"], d["q"], d["hits"], d["valid"], out=out, prec=pp)
+    tuned = json.loads(ctx.tuned_shape(prec, n, trials=True))
     trials = [{"block": b, "waves_per_simd": w, "persistent": bool(p), "tracks_per_lane": tp, "ms": ms}
               for b, w, p, tp, ms in tuned.pop("trials")]
     del out
@@ -384,15 +388,15 @@ def shapes_workload(args):
             x = dict(state=d["state"].repeat(1, k), cov=d["cov"].repeat(1, k), q=d["q"].repeat(k),
                      hits=d["hits"].repeat(1, 1, k), valid=d["valid"].repeat(1, k))
             pitch = m
-        o = ctx.alloc_fit_out(m, pitch, torch.float32)
-        ctx.autotune_fit(x["state"], x["cov"], x["q"], x["hits"], x["valid"], out=o)
-        run = lambda: ctx.fit(x["state"], x["cov"], x["q"], x["hits"], x["valid"], out=o)
+        o = ctx.alloc_fit_out(m, pitch, dt)
+        ctx.autotune_fit(x["state"], x["cov"], x["q"], x["hits"], x["valid"], out=o, prec=pp)
+        run = lambda: ctx.fit(x["state"], x["cov"], x["q"], x["hits"], x["valid"], out=o, prec=pp)
         ms, _ = timed_loop(run, args.steps, args.warmup, torch)
         scan.append({"tracks": m, "ms": round(ms, 4), "tracks_per_s": round(m / (ms * 1e-3)),
-                     "launch": json.loads(ctx.tuned_shape("fp32b", m))})
+                     "launch": json.loads(ctx.tuned_shape(prec, m))})
         del x, o
         torch.cuda.synchronize()
-    print(json.dumps({"metric": "fused FP32-bulk fit time per launch shape and tracks/s per problem size",
+    print(json.dumps({"metric": f"fused fit ({prec}) time per launch shape and tracks/s per problem size",
                       "value": scan[-2]["tracks_per_s"], "unit": "tracks/s", "n_gpus": 1,
                       "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
                       "config": {"workload": "1,000,000 tracks, 10 barrel layers r=4..40 cm, Bz=3.8 T, "
