@@ -39,7 +39,7 @@ extern "C" {
 #endif
 
 #define KTF_VERSION_MAJOR 0
-#define KTF_VERSION_MINOR 1
+#define KTF_VERSION_MINOR 2
 
 #define KTF_MAX_LAYERS 32
 #define KTF_MAX_CANDS 16
@@ -142,6 +142,11 @@ int ktf_create(const ktf_config *cfg, ktf_ctx **out);
 int ktf_destroy(ktf_ctx *ctx);
 /* Message for the last failed call on ctx (never NULL; "" if none). */
 const char *ktf_last_error(const ktf_ctx *ctx);
+/* sizeof(ktf_config) as the library was built: ktf_config grows by
+ * appended fields from one minor version to the next, and the library
+ * reads the whole structure, so a caller checks this against its own
+ * sizeof(ktf_config) before ktf_create. */
+size_t ktf_config_bytes(void);
 
 /* ---------------------------------------------------------------- fitting
  * Kalman-filter fit (Sec. 2: "repeatedly apply the KF algorithm without

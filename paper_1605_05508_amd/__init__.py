@@ -27,7 +27,7 @@ MAX_LAYERS = 32
 
 EXPORTS = ["ktf_create", "ktf_destroy", "ktf_last_error", "ktf_fit", "ktf_autotune_fit",
            "ktf_tuned_shape", "ktf_build", "ktf_bin_hits", "ktf_submit", "ktf_poll", "ktf_now",
-           "ktf_serving_stats", "ktf_fit_noalloc", "ktf_debug_fail_next_event"]
+           "ktf_serving_stats", "ktf_fit_noalloc", "ktf_debug_fail_next_event", "ktf_config_bytes"]
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
@@ -113,6 +113,11 @@ def load_library(path: str = LIB_PATH):
     lib.ktf_serving_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]
     lib.ktf_debug_fail_next_event.argtypes = [vp]
+    lib.ktf_config_bytes.argtypes = []
+    lib.ktf_config_bytes.restype = C.c_size_t
+    if lib.ktf_config_bytes() != C.sizeof(_Config):
+        raise RuntimeError(f"{path} was built with a ktf_config of {lib.ktf_config_bytes()} bytes, "
+                           f"this binding has {C.sizeof(_Config)}: rebuild the library")
     _lib = lib
     return lib
 

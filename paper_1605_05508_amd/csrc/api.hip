@@ -195,6 +195,8 @@ int ktf_destroy(ktf_ctx* c) {
   return KTF_OK;
 }
 
+size_t ktf_config_bytes(void) { return sizeof(ktf_config); }
+
 const char* ktf_last_error(const ktf_ctx* c) {
   if (!c) return "";
   return c->last_error.c_str();

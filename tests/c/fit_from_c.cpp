@@ -57,6 +57,7 @@ int main(int argc, char** argv) {
   read_n(f, valid.data(), valid.size());
   std::fclose(f);
 
+  if (ktf_config_bytes() != sizeof(ktf_config)) die("ktf_config differs between this program and the library");
   ktf_config cfg;
   std::memset(&cfg, 0, sizeof cfg);
   cfg.n_layers = L;
