@@ -17,8 +17,15 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libktf.so")
 ARCH = os.environ.get("KTF_OFFLOAD_ARCH", "gfx950")
 
+# A kernel's by-value argument structure is copied to private memory and
+# read from there unless the optimiser can prove the copy redundant, which
+# it stops trying past a number of uses (300 by default): the building's
+# score kernel reads its arguments in more places than that and would keep
+# a 1.3 KB copy per lane in scratch.  The limit is raised for every file;
+# below it the code is the same.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-instcombine-max-copied-from-constant-users=4096",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-command-line-argument"]
 
 

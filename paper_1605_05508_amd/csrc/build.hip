@@ -37,11 +37,10 @@ namespace ktf {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Candidate rows are split into kRegions regions of RS rows, each with its
-// own row counter (kCtrStride ints apart, one 128-byte line each), so that
-// row reservations spread over many addresses: same-address atomics
-// serialise in the memory system.
-constexpr int kRegions = 64;
+// Candidate rows are split into NR <= kMaxRegions regions of RS rows, each
+// with its own row counter (kCtrStride ints apart, one 128-byte line each),
+// so that row reservations spread over many addresses: same-address
+// atomics serialise in the memory system.
 constexpr int kCtrStride = 32;
 
 template <typename T> struct BuildNewton;
@@ -54,8 +53,9 @@ struct BuildArgs {
   int32_t n_groups;        // n_events * n_layers
   int32_t n_bins;          // n_zbins * n_phibins
   int64_t n_seeds, sp;     // seeds, seed pitch
-  int64_t S;               // candidate rows = kRegions * RS
+  int64_t S;               // candidate rows = NR * RS
   int64_t RS;              // rows per region
+  int NR;                  // regions in use
   int64_t n_hits;          // total hits
   int64_t max_group;       // most hits in one (event, layer)
   int64_t hp;              // hit pitch
@@ -99,7 +99,7 @@ struct BuildArgs {
   int32_t* sel_parent;     // [S]: per child row, its parent's row
   int32_t* sel_hit;        // [S]: per child row, the hit it takes as its position among the binned records (-1: missed layer)
   double* sel_chi2;        // [S]: per child row, its chi2 total
-  unsigned* ccount;        // [n_layers][kRegions][kCtrStride]: rows used per region after each layer
+  unsigned* ccount;        // [n_layers][kMaxRegions][kCtrStride]: rows used per region after each layer
   void* hb;                // [n_hits] BinHit<TS>: binned coordinates and local index
   // candidates (double buffered), propagated parents, records
   double* cpos[2];
@@ -740,21 +740,21 @@ __device__ __forceinline__ int64_t block_reserve(unsigned* counter, int n, int* 
 }
 
 // Region of this block in a launch that reserves rows (seed fit, merge):
-// contiguous ranges of at most ceil(gridDim / kRegions) blocks share a
-// region, so a region holds the candidates of neighbouring seeds (one or
-// two events), and blocks in flight together still spread their row
-// reservations over several counters.
-__device__ __forceinline__ int block_region() {
-  return (int)(((int64_t)blockIdx.x * kRegions) / gridDim.x);
+// contiguous ranges of at most ceil(gridDim / NR) blocks share a region, so
+// a region holds the candidates of neighbouring seeds (one or two events),
+// and blocks in flight together still spread their row reservations over
+// several counters.
+__device__ __forceinline__ int block_region(const BuildArgs& a) {
+  return (int)(((int64_t)blockIdx.x * a.NR) / gridDim.x);
 }
 
 __device__ __forceinline__ unsigned* region_ctr(const BuildArgs& a, int l, int r) {
-  return a.ccount + ((int64_t)l * kRegions + r) * kCtrStride;
+  return a.ccount + ((int64_t)l * kMaxRegions + r) * kCtrStride;
 }
 
 // The row kernel (score) runs one lane per live candidate row after
-// layer l.  A launch has kRegions * k blocks: block b takes region
-// b % kRegions and, within it, the kRowChunks chunks b / kRegions + j k
+// layer l.  A launch has NR * k blocks: block b takes region b % NR
+// and, within it, the kRowChunks chunks b / NR + j k
 // (j = 0 .. kRowChunks - 1) of blockDim rows, each while it holds live
 // rows.  Consecutive blocks take the same chunk of consecutive regions, so
 // the rows in flight together belong to seeds close in index (same events,
@@ -769,11 +769,12 @@ constexpr int kRowChunks = 4;
   }
 #define ROW_CHUNKS(a, l, CALL)                                                          \
   do {                                                                                  \
-    const int r_ = (int)(blockIdx.x % kRegions);                                        \
+    const unsigned nr_ = (unsigned)(a).NR;                                              \
+    const int r_ = (int)(blockIdx.x % nr_);                                             \
     const int64_t n_ = *region_ctr(a, l, r_);                                           \
     const int64_t rs_ = (a).RS;                                                         \
-    const int64_t step_ = (int64_t)(gridDim.x / kRegions) * blockDim.x;                 \
-    const int64_t l0_ = (int64_t)(blockIdx.x / kRegions) * blockDim.x + threadIdx.x;    \
+    const int64_t step_ = (int64_t)(gridDim.x / nr_) * blockDim.x;                      \
+    const int64_t l0_ = (int64_t)(blockIdx.x / nr_) * blockDim.x + threadIdx.x;         \
     static_assert(kRowChunks == 4, "ROW_CHUNKS writes out four chunks");                \
     ROW_CHUNK(0, CALL) ROW_CHUNK(1, CALL) ROW_CHUNK(2, CALL) ROW_CHUNK(3, CALL)         \
   } while (0)
@@ -885,7 +886,7 @@ void build_seed_kernel(BuildArgs a) {
   }
   __shared__ int wtot[256 / 64 + 1];
   const int alive = valid && reached == NSL ? 1 : 0;
-  const int reg = block_region();
+  const int reg = block_region(a);
   const int64_t row = reg * a.RS + block_reserve(region_ctr(a, NSL - 1, reg), alive, wtot);
   if (alive) {
     a.cstart[0][s] = (int32_t)row;
@@ -1277,9 +1278,6 @@ __device__ __forceinline__ bool final_less(int nh1, double c1, int e1, int r1, i
 // Fewer lanes per seed issue fewer instructions per seed (a lane-local
 // compare costs less than an exchange, and a group's lanes all execute
 // every pick) but hold more parents' heads in registers.
-constexpr int kMergeThreads = 256;
-constexpr int merge_lanes(int max_cands) { return max_cands <= 4 ? 1 : (max_cands <= 10 ? 2 : 4); }
-constexpr int merge_seeds(int lps) { return kMergeThreads / lps; }
 
 // a record-list head as ranked by the merge: key = 0 for none, else the hit
 // count it gives plus one; pj = parent << 16 | records in its list << 8 |
@@ -1481,7 +1479,7 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
 #pragma unroll
   for (int u = 0; u < PPL; ++u) nrec_lane += rc[u] > 0 ? rc[u] : 0;
   const int nsel = min(NC, group_sum<LPS>(nrec_lane));
-  const int reg = block_region();
+  const int reg = block_region(a);
   const int local = (int)block_reserve(region_ctr(a, l, reg), q == 0 ? nsel : 0, wtot);
   const int64_t first = reg * a.RS + group_first<LPS>(local);
   if (real && q == 0) {
@@ -1637,18 +1635,6 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
 // -------------------------------------------------------------- host side
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Rows per region: enough for the blocks that reserve in one region (at
-// most ceil(blocks / kRegions), see block_region), for the seed kernel (256 seeds of one row
-// each per block) and for the merge (merge_seeds seeds of up to max_cands
-// rows each per block); a multiple of 256 rows (the row-kernel block).
-static int64_t region_rows(int64_t n_seeds, int nc) {
-  const int64_t sb = merge_seeds(merge_lanes(nc));
-  const int64_t per_merge = (((n_seeds + sb - 1) / sb + kRegions - 1) / kRegions) * sb * nc;
-  const int64_t per_seed = (((n_seeds + 255) / 256 + kRegions - 1) / kRegions) * 256;
-  const int64_t r = std::max<int64_t>(std::max(per_merge, per_seed), 1);
-  return (r + 255) / 256 * 256;
-}
-
 template <typename TS, typename TP, bool STAGE>
 static void launch_score(const BuildArgs& a, int l, int cur, bool child, dim3 rows, size_t lds, hipStream_t st) {
   const dim3 blk(256);
@@ -1726,7 +1712,7 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || bins_only || a.n_seeds == 0) return e;
-  const int64_t nctr = (int64_t)a.g.n_layers * kRegions * kCtrStride;
+  const int64_t nctr = (int64_t)a.g.n_layers * kMaxRegions * kCtrStride;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nctr, bs)), dim3(bs), 0, st, reinterpret_cast<int32_t*>(a.ccount),
                      nctr, 0);
   if (a.seed_order) {  // the seeds of each event in order of their predicted cell
@@ -1744,7 +1730,7 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   // indices per thread
   const size_t rec_lds = (size_t)a.g.max_cands * bs * (sizeof(double) + 2 * sizeof(int32_t)) +
                          (a.seed_order ? (size_t)(bs / 64) * StageArea<TS>::bytes : 0);
-  const dim3 rows((unsigned)(kRegions * ((a.RS / bs + kRowChunks - 1) / kRowChunks)));
+  const dim3 rows((unsigned)(a.NR * ((a.RS / bs + kRowChunks - 1) / kRowChunks)));
   for (int l = a.g.n_seed_layers; l < a.g.n_layers; ++l) {
     const bool child = l > a.g.n_seed_layers;  // candidates kept on layer l - 1, not yet made
     if (a.seed_order)
@@ -1770,7 +1756,8 @@ static int validate_batch(ktf_ctx* c, const ktf_event_batch* ev) {
   if (const char* why = check_event_batch(ev, c->cfg.n_layers, c->cfg.max_cands))
     return fail(c, KTF_EINVAL, "ktf_build: %s", why);
   // seed_pitch * max_cands < 2^31 here, so the row count cannot overflow
-  if (region_rows(ev->seed_off[ev->n_events], c->cfg.max_cands) * kRegions > INT32_MAX)
+  const int64_t n = ev->seed_off[ev->n_events];
+  if (region_rows(n, c->cfg.max_cands) * region_count(n, c->cfg.max_cands) > INT32_MAX)
     return fail(c, KTF_EINVAL, "ktf_build: more than 2^31 candidate rows");
   return KTF_OK;
 }
@@ -1802,7 +1789,8 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.n_seeds = ev->seed_off[ev->n_events];
   a.sp = ev->seed_pitch;
   a.RS = region_rows(a.n_seeds, cfg.max_cands);
-  a.S = a.RS * kRegions;
+  a.NR = region_count(a.n_seeds, cfg.max_cands);
+  a.S = a.RS * a.NR;
   a.n_hits = ev->hit_off[a.n_groups];
   a.max_group = 0;
   for (int g = 0; g < a.n_groups; ++g)
@@ -1950,7 +1938,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
     a.n_keys = kMaxKeys;
   }
   const size_t ctr_at = ((size_t)S * 4 + (size_t)sp * 2 + kCtrStride - 1) / kCtrStride * kCtrStride;
-  if ((e = c->b_list.ensure((ctr_at + (size_t)L * kRegions * kCtrStride) * 4)) != hipSuccess)
+  if ((e = c->b_list.ensure((ctr_at + (size_t)L * kMaxRegions * kCtrStride) * 4)) != hipSuccess)
     return hip_fail(c, e, "list workspace");
   {
     int32_t* p = static_cast<int32_t*>(c->b_list.p);

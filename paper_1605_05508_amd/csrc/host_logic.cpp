@@ -111,17 +111,18 @@ size_t footprint_of(const ktf_config& cfg, int64_t n, int64_t nh, ktf_precision 
   const size_t ts = prec == KTF_FP64 ? 8 : 4;
   const size_t L = cfg.n_layers, NC = cfg.max_cands;
   const size_t per_seed_in = 27 * ts + 1 + 4 * cfg.n_seed_layers;
-  // candidate rows: max_cands per seed plus the slack of the 64 row regions;
-  // per row: two candidate buffers, two propagated-state buffers, records,
-  // the row lists (seed x2, parent, hit) and the child chi2
+  // candidate rows (the building's regions); per row: two candidate
+  // buffers, two propagated-state buffers, records, the row lists (info x2,
+  // parent, hit) and the child chi2
   const size_t per_row = 2 * (24 + 24 * ts + 12) + 2 * (24 + 24 * ts) + 16 * NC + 4 + 16 + 8;
-  const size_t rows = (size_t)n * NC + 64 * 257;
+  const size_t rows = (size_t)region_count(n, cfg.max_cands) * (size_t)region_rows(n, cfg.max_cands);
   const size_t per_seed_ws = L * NC * 8 + L * 4 + (24 + 24 * ts + 20) + 8;
   const size_t per_seed_fit = L * (3 * ts + 1) + 27 * ts + 16 + L * 4;
+  const size_t counters = L * kMaxRegions * 128;
   const size_t bin_rows = cfg.n_etabins > 0 ? (size_t)cfg.n_etabins : (size_t)cfg.n_zbins;
   const size_t bins = L * (bin_rows * cfg.n_phibins * 8 + 8);
   return rows * per_row + (size_t)n * (per_seed_in + per_seed_ws + per_seed_fit) + (size_t)nh * (3 * ts * 2 + 8) +
-         bins;
+         counters + bins;
 }
 
 InLayout in_layout(int E, int L, int NSL, int64_t N, int64_t H, size_t ts) {

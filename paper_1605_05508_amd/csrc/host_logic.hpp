@@ -21,6 +21,38 @@ constexpr int64_t kMaxPitch = int64_t(1) << 40;
 constexpr int64_t kMaxEventSeeds = INT32_MAX;
 constexpr int64_t kMaxEventHits = INT32_MAX;
 
+// The building's candidate rows are split into region_count regions, each
+// with its own row counter (spreading same-address atomics).  Two launches
+// reserve rows: the seed fit (blocks of 256 seeds, one row each) and the
+// merge (blocks of merge_seeds seeds, up to max_cands rows each); block b of
+// a launch of G blocks reserves in region b * regions / G, so a region
+// serves at most ceil(G / regions) blocks of either.
+constexpr int kMaxRegions = 64;
+constexpr int kMergeThreads = 256;
+// lanes per seed in the merge, and seeds per merge block
+constexpr int merge_lanes(int max_cands) { return max_cands <= 4 ? 1 : (max_cands <= 10 ? 2 : 4); }
+constexpr int merge_seeds(int lps) { return kMergeThreads / lps; }
+inline int64_t seed_blocks(int64_t n_seeds) { return n_seeds > 0 ? (n_seeds + 255) / 256 : 1; }
+inline int64_t merge_blocks(int64_t n_seeds, int max_cands) {
+  const int64_t sb = merge_seeds(merge_lanes(max_cands));
+  return n_seeds > 0 ? (n_seeds + sb - 1) / sb : 1;
+}
+// as many regions as the smaller launch has blocks, at most kMaxRegions
+inline int region_count(int64_t n_seeds, int max_cands) {
+  int64_t r = seed_blocks(n_seeds) < merge_blocks(n_seeds, max_cands) ? seed_blocks(n_seeds)
+                                                                         : merge_blocks(n_seeds, max_cands);
+  return (int)(r < kMaxRegions ? r : kMaxRegions);
+}
+// rows per region, a multiple of 256 (the row-kernel block)
+inline int64_t region_rows(int64_t n_seeds, int max_cands) {
+  const int64_t nr = region_count(n_seeds, max_cands);
+  const int64_t per_merge = (merge_blocks(n_seeds, max_cands) + nr - 1) / nr *
+                            merge_seeds(merge_lanes(max_cands)) * max_cands;
+  const int64_t per_seed = (seed_blocks(n_seeds) + nr - 1) / nr * 256;
+  const int64_t r = per_merge > per_seed ? per_merge : per_seed;
+  return (r + 255) / 256 * 256;
+}
+
 // nullptr when the argument is valid, else why it is not
 const char* check_config(const ktf_config* cfg);
 const char* check_fit_in(const ktf_fit_in* in, const ktf_fit_out* out);

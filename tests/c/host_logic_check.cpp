@@ -11,6 +11,7 @@
 //    exactly their size, and read back;
 //  - row copies above 4 MB take the threaded path.
 // Prints "host logic OK" and returns 0 when every check holds.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -241,6 +242,42 @@ static void check_batches(std::mt19937_64& rng) {
   CHECK(fmax > footprint_of(c, kMaxEventSeeds / 2, kMaxEventHits, KTF_FP64));
 }
 
+// The building's row regions: for random and edge seed counts, walk the
+// blocks of both launches that reserve rows (seed fit: 256 seeds, one row
+// each; merge: merge_seeds seeds, up to max_cands rows each) through the
+// block-to-region map b * regions / blocks and check that no region is
+// asked for more rows than it has, that the regions are few for small
+// events and that the slack over n * max_cands stays bounded.
+static void check_regions(std::mt19937_64& rng) {
+  std::vector<int64_t> ns = {0, 1, 255, 256, 257, 300, 4095, 20000, 50000, 500000, 1000003};
+  for (int i = 0; i < 60; ++i) ns.push_back(1 + (int64_t)(rng() % 3000000));
+  for (int64_t n : ns) {
+    for (int nc = 1; nc <= KTF_MAX_CANDS; ++nc) {
+      const int nr = region_count(n, nc);
+      const int64_t rs = region_rows(n, nc);
+      CHECK(nr >= 1 && nr <= kMaxRegions && rs % 256 == 0 && rs > 0);
+      const int64_t sb = merge_seeds(merge_lanes(nc));
+      struct Launch {
+        int64_t per_block, rows_per_seed;
+      } launches[2] = {{256, 1}, {sb, nc}};
+      for (const Launch& ln : launches) {
+        const int64_t G = n > 0 ? (n + ln.per_block - 1) / ln.per_block : 1;
+        std::vector<int64_t> used(nr, 0);
+        for (int64_t b = 0; b < G; ++b) {
+          const int64_t seeds = std::min<int64_t>(ln.per_block, std::max<int64_t>(n - b * ln.per_block, 0));
+          const int64_t r = b * nr / G;
+          CHECK(r >= 0 && r < nr);
+          if (r >= 0 && r < nr) used[r] += seeds * ln.rows_per_seed;
+        }
+        for (int r = 0; r < nr; ++r) CHECK(used[r] <= rs);
+      }
+      if (n > 0 && n <= 256) CHECK(nr == 1);
+      // slack: at most one block of either launch per region, plus rounding
+      CHECK(nr * rs <= n * nc + (int64_t)nr * (sb * nc + 256 + 255));
+    }
+  }
+}
+
 // pattern value of (event, array, row, element) so that every packed or
 // unpacked element can be checked where it lands
 static uint64_t pat(int e, int arr, int row, int64_t i) {
@@ -398,6 +435,7 @@ int main() {
   check_configs(rng);
   check_fits(rng);
   check_batches(rng);
+  check_regions(rng);
   for (int it = 0; it < 40; ++it) {
     const int E = 1 + (int)(rng() % 9), L = 1 + (int)(rng() % 17), NSL = 1 + (int)(rng() % L);
     if (it % 2)
