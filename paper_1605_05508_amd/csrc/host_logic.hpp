@@ -37,11 +37,13 @@ inline int64_t merge_blocks(int64_t n_seeds, int max_cands) {
   const int64_t sb = merge_seeds(merge_lanes(max_cands));
   return n_seeds > 0 ? (n_seeds + sb - 1) / sb : 1;
 }
-// as many regions as the smaller launch has blocks, at most kMaxRegions
+// at most kMaxRegions regions, as many as spread the merge's blocks evenly
+// (each region then serves ceil(blocks / regions) of them with little
+// rounding: the merge reserves nearly all rows)
 inline int region_count(int64_t n_seeds, int max_cands) {
-  int64_t r = seed_blocks(n_seeds) < merge_blocks(n_seeds, max_cands) ? seed_blocks(n_seeds)
-                                                                         : merge_blocks(n_seeds, max_cands);
-  return (int)(r < kMaxRegions ? r : kMaxRegions);
+  const int64_t g = merge_blocks(n_seeds, max_cands);
+  const int64_t per = (g + kMaxRegions - 1) / kMaxRegions;
+  return (int)((g + per - 1) / per);
 }
 // rows per region, a multiple of 256 (the row-kernel block)
 inline int64_t region_rows(int64_t n_seeds, int max_cands) {

@@ -271,7 +271,9 @@ static void check_regions(std::mt19937_64& rng) {
         }
         for (int r = 0; r < nr; ++r) CHECK(used[r] <= rs);
       }
-      if (n > 0 && n <= 256) CHECK(nr == 1);
+      // never more regions than merge blocks: one for an event of one block
+      CHECK(nr <= merge_blocks(n, nc));
+      if (n <= sb) CHECK(nr == 1);
       // slack: at most one block of either launch per region, plus rounding
       CHECK(nr * rs <= n * nc + (int64_t)nr * (sb * nc + 256 + 255));
     }
