@@ -51,6 +51,7 @@ struct BuildArgs {
   BuildGeom g;
   int32_t n_events;
   int32_t n_groups;        // n_events * n_layers
+  int32_t bin_l0;          // first layer binned (the seed layers' bins are not searched by a build)
   int32_t n_bins;          // n_zbins * n_phibins
   int64_t n_seeds, sp;     // seeds, seed pitch
   int64_t S;               // candidate rows = NR * RS
@@ -231,6 +232,7 @@ __global__ void bin_count_kernel(BuildArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n_hits) return;
   const int g = find_event(a.hit_off, a.n_groups, j);
+  if (g % a.g.n_layers < a.bin_l0) return;
   const TS* h = static_cast<const TS*>(a.hits);
   const int b = hit_bin_of((double)h[j], (double)h[a.hp + j], (double)h[2 * a.hp + j], a.g);
   a.hit_bin[j] = b;
@@ -245,6 +247,7 @@ constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(BuildArgs a) {
   __shared__ int32_t wsum[kScanThreads / 64];
   const int g = blockIdx.x;
+  if (g % a.g.n_layers < a.bin_l0) return;  // the whole block
   const int nb = a.n_bins;
   int32_t* cnt = a.bin_cur + (int64_t)g * nb;
   int32_t* off = a.bin_off + (int64_t)g * (nb + 1);
@@ -287,6 +290,7 @@ __global__ void bin_scatter_kernel(BuildArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n_hits) return;
   const int g = find_event(a.hit_off, a.n_groups, j);
+  if (g % a.g.n_layers < a.bin_l0) return;
   const int b = a.hit_bin[j];
   const int32_t pos = atomicAdd(&a.bin_cur[(int64_t)g * a.n_bins + b], 1);
   a.perm_raw[a.hit_off[g] + pos] = (int32_t)(j - a.hit_off[g]);
@@ -301,6 +305,7 @@ __global__ void bin_rank_kernel(BuildArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n_hits) return;
   const int g = find_event(a.hit_off, a.n_groups, j);
+  if (g % a.g.n_layers < a.bin_l0) return;
   const int b = a.hit_bin[j];
   const int32_t* off = a.bin_off + (int64_t)g * (a.n_bins + 1);
   const int64_t base = a.hit_off[g];
@@ -353,6 +358,7 @@ void bin_group16_kernel(BuildArgs a) {
   extern __shared__ uint32_t bin_lds[];
   __shared__ int32_t wsum[kBinThreads / 64];
   const int g = blockIdx.x;
+  if (g % a.g.n_layers < a.bin_l0) return;  // the whole block
   const int nb = a.n_bins, nwords = (nb + 1) >> 1;
   uint32_t* cnt = bin_lds;  // bin b in half b & 1 of word b >> 1
   uint16_t* permr = reinterpret_cast<uint16_t*>(bin_lds + nwords);
@@ -1785,6 +1791,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.g.mat = material_of(c);
   a.n_events = ev->n_events;
   a.n_groups = ev->n_events * L;
+  a.bin_l0 = bins_only ? 0 : cfg.n_seed_layers;
   a.n_bins = a.g.n_zbins * cfg.n_phibins;
   a.n_seeds = ev->seed_off[ev->n_events];
   a.sp = ev->seed_pitch;
