@@ -1492,6 +1492,10 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     a.count[(int64_t)l * sp + s] = nsel;
     if (nsel > 0) a.cstart[cur ^ 1][s] = (int32_t)first;
   }
+  // every load issued so far is complete before the picks: otherwise the
+  // wait for the heads' loads sits at the top of the pick loop, and with the
+  // stores of each pick in flight it would wait for those every time
+  __builtin_amdgcn_s_waitcnt(0);
   for (int k = 0; k < nsel; ++k) {
     MHead w{hk[0], hc[0], mpj(q, rc[0], hd[0]), hh[0], hp[0]};
 #pragma unroll
@@ -1508,7 +1512,11 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       a.cinfo[cur ^ 1][first + k] = info;
     }
     // the owner lane replaces the taken head by the next record of its list
-    // (selects, not branches; a record beyond the LDS ones is loaded, rarely)
+    // (selects, not branches).  A record beyond the LDS ones is loaded in a
+    // branch of its own that also consumes it, rarely: a load whose value
+    // is used after the branch would make every pick wait on the memory
+    // counter, which on this chip also counts the stores above, so each pick
+    // would wait for the previous pick's child to be written.
     const int wj = mpj_parent(w.pj);
     const int us = wj / LPS;               // the winner's slot in its owner lane
     const int nx = mpj_rec(w.pj) + 1;      // the next record of its list
@@ -1517,19 +1525,31 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     double ncv = qc_s[vq * PPL + us][tid];
     int nhv = qh_s[vq * PPL + us][tid];
     int npv = qp_s[vq * PPL + us][tid];
-    if (more && nx > PF && wj % LPS == q) {
-      const int64_t far = (int64_t)nx * S + pbase + wj;
-      ncv = a.rchi[far];
-      nhv = a.rhit[far];
-      npv = a.rpos[far];
+    const bool far = more && nx > PF && wj % LPS == q;
+    if (__any(far)) {
+      if (far) {
+        const int64_t fr = (int64_t)nx * S + pbase + wj;
+        ncv = a.rchi[fr];
+        nhv = a.rhit[fr];
+        npv = a.rpos[fr];
+      }
+      // the loaded values go into the heads here, inside the branch
+#pragma unroll
+      for (int u = 0; u < PPL; ++u) {
+        const bool adv = far && wj == q + LPS * u;
+        hc[u] = adv ? ncv : hc[u];
+        hh[u] = adv ? nhv : hh[u];
+        hp[u] = adv ? npv : hp[u];
+      }
     }
 #pragma unroll
     for (int u = 0; u < PPL; ++u) {
       const bool adv = wj == q + LPS * u;
+      const bool lds = adv && !far;
       hd[u] = adv ? nx : hd[u];
-      hc[u] = adv ? ncv : hc[u];
-      hh[u] = adv ? nhv : hh[u];
-      hp[u] = adv ? npv : hp[u];
+      hc[u] = lds ? ncv : hc[u];
+      hh[u] = lds ? nhv : hh[u];
+      hp[u] = lds ? npv : hp[u];
       hk[u] = adv && !more ? 0 : hk[u];
     }
   }
