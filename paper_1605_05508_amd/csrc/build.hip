@@ -1606,15 +1606,29 @@ __global__ __launch_bounds__(256) void build_backtrack_kernel(BuildArgs a, int c
   const int L = a.g.n_layers, NC = a.g.max_cands;
   const FinalChoice f = final_choice<LAZY>(a, cur, s);
   for (int l = L - 1; l >= f.end_layer; --l) a.o_hit[(int64_t)l * a.sp + s] = -1;
+  // The walk is a chain of dependent loads; each layer's record is loaded
+  // before the layer above it is stored, so that waiting for the load does
+  // not also wait for that store (the memory counter counts both).
   int r = f.rank;
-  for (int l = f.end_layer - 1; l >= 0; --l) {
-    if (r < 0 || r >= NC) {  // no record: nothing further back
-      a.o_hit[(int64_t)l * a.sp + s] = -1;
-      continue;
-    }
+  int l = f.end_layer - 1;
+  int hit = -1, nr = -1;
+  if (l >= 0 && r >= 0 && r < NC) {
     const int64_t hb = ((int64_t)l * NC + r) * 2 * a.sp;
-    a.o_hit[(int64_t)l * a.sp + s] = a.hist[hb + a.sp + s];
-    r = a.hist[hb + s];
+    hit = a.hist[hb + a.sp + s];
+    nr = a.hist[hb + s];
+  }
+  for (; l >= 0; --l) {
+    // the record of layer l (hit, parent rank nr) is in flight or done;
+    // issue layer l - 1's before storing layer l's hit
+    const bool rec = r >= 0 && r < NC;
+    const int h_l = rec ? hit : -1;
+    r = rec ? nr : -1;
+    if (l > 0 && r >= 0 && r < NC) {
+      const int64_t hb = ((int64_t)(l - 1) * NC + r) * 2 * a.sp;
+      hit = a.hist[hb + a.sp + s];
+      nr = a.hist[hb + s];
+    }
+    a.o_hit[(int64_t)l * a.sp + s] = h_l;
   }
 }
 
