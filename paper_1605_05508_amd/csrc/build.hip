@@ -1449,19 +1449,40 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
     const int e_nh = eb.key - 1, ej = mpj_parent(eb.pj);
     const int be = a.bend[s];
     if (be < 0 || final_less(e_nh, eb.c, l, ej, meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s])) {
-      // the seed's lanes copy the ended candidate element by element
+      // the seed's lanes copy the ended candidate in chunks of five
+      // elements, a chunk's loads before its stores (a load issued after a
+      // store waits for it: the memory counter counts both); float elements
+      // go through double exactly
       const int64_t pe = pbase + ej;
       const TS* mo = static_cast<const TS*>(a.cmom[cur]);
       const TS* co = static_cast<const TS*>(a.ccov[cur]);
       TS* bm = static_cast<TS*>(a.bmom);
       TS* bc = static_cast<TS*>(a.bcov);
-      for (int e = q; e < 27; e += LPS) {
-        if (e < 3)
-          a.bpos[e * sp + s] = a.cpos[cur][e * S + pe];
-        else if (e < 6)
-          bm[(e - 3) * sp + s] = mo[(e - 3) * S + pe];
-        else
-          bc[(e - 6) * sp + s] = co[(e - 6) * S + pe];
+      constexpr int NE = (27 + LPS - 1) / LPS, CH = 5;
+#pragma unroll
+      for (int i0 = 0; i0 < NE; i0 += CH) {
+        double ev[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int e = q + LPS * (i0 + i);
+          ev[i] = 0.0;
+          if (e < 3)
+            ev[i] = a.cpos[cur][e * S + pe];
+          else if (e < 6)
+            ev[i] = (double)mo[(e - 3) * S + pe];
+          else if (e < 27)
+            ev[i] = (double)co[(e - 6) * S + pe];
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int e = q + LPS * (i0 + i);
+          if (e < 3)
+            a.bpos[e * sp + s] = ev[i];
+          else if (e < 6)
+            bm[(e - 3) * sp + s] = (TS)ev[i];
+          else if (e < 27)
+            bc[(e - 6) * sp + s] = (TS)ev[i];
+        }
       }
       if (q == 0) {
         const uint32_t m = a.cmeta[cur][pe];
