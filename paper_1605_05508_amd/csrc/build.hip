@@ -1589,8 +1589,15 @@ struct FinalChoice {
 template <bool LAZY>
 __device__ __forceinline__ FinalChoice final_choice(const BuildArgs& a, int cur, int64_t s) {
   const int L = a.g.n_layers;
+  // the seed's own words first, all in one round trip: its survivors and
+  // its best ended candidate
   const int nalive = a.count[(int64_t)(L - 1) * a.sp + s];
-  FinalChoice f{false, L, -1, nalive > 0 ? (int64_t)a.cstart[cur][s] : 0};
+  const int64_t cst = a.cstart[cur][s];
+  const int be = a.bend[s];
+  const int e_nh = meta_nh(a.bmeta[s]);
+  const double e_c2 = a.bchi2[s];
+  const int e_rank = a.brank[s];
+  FinalChoice f{false, L, -1, nalive > 0 ? cst : 0};
   // The survivors are in rank order, and the rank order (more hits, then
   // lower chi2, then the pick order) is the final key among candidates that
   // all end on the last layer: the best survivor is the first.
@@ -1606,12 +1613,10 @@ __device__ __forceinline__ FinalChoice final_choice(const BuildArgs& a, int cur,
       bc2 = a.cchi2[cur][f.base];
     }
   }
-  const int be = a.bend[s];
-  if (be >= 0 && (f.rank < 0 || final_less(meta_nh(a.bmeta[s]), a.bchi2[s], be, a.brank[s], bnh, bc2, L,
-                                           f.rank))) {
+  if (be >= 0 && (f.rank < 0 || final_less(e_nh, e_c2, be, e_rank, bnh, bc2, L, f.rank))) {
     f.from_ended = true;
     f.end_layer = be;
-    f.rank = a.brank[s];
+    f.rank = e_rank;
   }
   return f;
 }
