@@ -7,7 +7,9 @@ instructions are disabled for all device code.
 """
 import concurrent.futures as cf
 import glob
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -30,6 +32,28 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
+# the compiler's per-kernel resource report (registers, scratch, occupancy),
+# kept in _build/resources.json for the test that guards against kernels
+# falling into scratch memory
+REMARKS = ["-Rpass-analysis=kernel-resource-usage"]
+RESOURCES = os.path.join(OBJ, "resources.json")
+
+
+def _resources(text):
+    """Kernel name -> {vgpr, sgpr, scratch, occupancy} from the remarks."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"remark:\s+Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        for key, pat in (("vgpr", r"remark:\s+VGPRs: (\d+)"), ("sgpr", r"remark:\s+TotalSGPRs: (\d+)"),
+                         ("scratch", r"ScratchSize \[bytes/lane\]: (\d+)"),
+                         ("occupancy", r"Occupancy \[waves/SIMD\]: (\d+)")):
+            m = re.search(pat, line)
+            if m and cur is not None:
+                cur[key] = int(m.group(1))
+    return out
 
 
 def _compile(src):
@@ -37,11 +61,11 @@ def _compile(src):
     if src.endswith(".cpp"):
         cmd = ["g++", *HOST_FLAGS, "-c", src, "-o", obj]
     else:
-        cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
+        cmd = ["hipcc", *FLAGS, *REMARKS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    return obj
+    return obj, (_resources(r.stderr) if src.endswith(".hip") else {})
 
 
 def build(verbose=False) -> str:
@@ -49,7 +73,13 @@ def build(verbose=False) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = min(len(srcs), max(1, (os.cpu_count() or 4) // 2), 8)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        done = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in done]
+    res = {}
+    for _, r in done:
+        res.update(r)
+    with open(RESOURCES, "w") as f:
+        json.dump({"arch": ARCH, "kernels": res}, f, indent=0, sort_keys=True)
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
