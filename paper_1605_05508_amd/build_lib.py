@@ -36,7 +36,6 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 # kept in _build/resources.json for the test that guards against kernels
 # falling into scratch memory
 REMARKS = ["-Rpass-analysis=kernel-resource-usage"]
-RESOURCES = os.path.join(OBJ, "resources.json")
 
 
 def _resources(text):
@@ -78,7 +77,7 @@ def build(verbose=False) -> str:
     res = {}
     for _, r in done:
         res.update(r)
-    with open(RESOURCES, "w") as f:
+    with open(os.path.join(OBJ, "resources.json"), "w") as f:
         json.dump({"arch": ARCH, "kernels": res}, f, indent=0, sort_keys=True)
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
