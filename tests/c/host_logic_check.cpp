@@ -103,7 +103,7 @@ static void check_configs(std::mt19937_64& rng) {
   x0[4] = nan;
   c.mass = 0.1396;
   CHECK(check_config(&c) != nullptr);
-  // random extreme values: no undefined behaviour whatever the verdict
+  // random extreme values: no undefined behaviour, accepted or not
   const int32_t ints[] = {INT32_MIN, -1, 0, 1, 2, 3, 16, 17, 32, 33, 512, 1 << 20, INT32_MAX};
   const double dbls[] = {-inf, -1.0, 0.0, 1e-300, 0.5, 1.2, 3.8, 100.0, 1e300, inf, nan};
   for (int it = 0; it < 20000; ++it) {

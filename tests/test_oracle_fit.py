@@ -280,7 +280,7 @@ def test_nonfinite_status(orc):
 
 
 def test_ten_percent_prior_pulls_belong_to_the_linearisation(orc):
-    """With the survey's 10% momentum prior the filter's momentum pulls
+    """With a 10% momentum prior (the seed recipe's) the filter's momentum pulls
     exceed one, while the batch maximum-a-posteriori fit of the same hits
     with the same prior (Gauss-Newton, numerical Jacobians, its Laplace
     covariance carried to the last layer) has unit pulls: the prior and the
