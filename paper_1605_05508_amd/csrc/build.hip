@@ -52,6 +52,7 @@ struct BuildArgs {
   int32_t n_events;
   int32_t n_groups;        // n_events * n_layers
   int32_t bin_l0;          // first layer binned (the seed layers' bins are not searched by a build)
+  int32_t off16;           // the bin offsets are 16-bit (a build whose groups all fit one binning block)
   int32_t n_bins;          // n_zbins * n_phibins
   int64_t n_seeds, sp;     // seeds, seed pitch
   int64_t S;               // candidate rows = NR * RS
@@ -419,8 +420,14 @@ void bin_group16_kernel(BuildArgs a) {
     run += (int32_t)(lo + (v >> 16));
   }
   __syncthreads();
-  for (int b = tid; b < nb; b += kBinThreads) off[b] = (int32_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
-  if (tid == 0) off[nb] = n;
+  if (a.off16) {  // the offsets (at most 32,768) in half the bytes, for the build's own use
+    uint16_t* o16 = reinterpret_cast<uint16_t*>(a.bin_off) + (int64_t)g * (nb + 1);
+    for (int b = tid; b < nb; b += kBinThreads) o16[b] = (uint16_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
+    if (tid == 0) o16[nb] = (uint16_t)n;
+  } else {
+    for (int b = tid; b < nb; b += kBinThreads) off[b] = (int32_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
+    if (tid == 0) off[nb] = n;
+  }
   __syncthreads();
   // scatter through the cursors (a bin's cursor ends at the next offset)
   for (int32_t j0 = 0; j0 < n; j0 += BB * kBinThreads) {
@@ -903,6 +910,13 @@ void build_seed_kernel(BuildArgs a) {
   }
 }
 
+// A group's CSR bin offsets, 32- or 16-bit (the same for the whole launch)
+struct BinOffsets {
+  const int32_t* o32;
+  const uint16_t* o16;  // null: 32-bit
+  __device__ __forceinline__ int32_t operator[](int i) const { return o16 ? (int32_t)o16[i] : o32[i]; }
+};
+
 // ---------------------------------------------------------------- scoring
 // A wave's LDS area for staging its window box: 8 reduction words, the
 // box's offsets (rows x (bins + 1)), the start of each row's hits and
@@ -1048,7 +1062,8 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     full_phi = (phi_hi - plo + 1) >= nphi;
   }
   const int g = e * L + l;
-  const int32_t* off = a.bin_off + (int64_t)g * (a.n_bins + 1);
+  const BinOffsets off{a.bin_off + (int64_t)g * (a.n_bins + 1),
+                       a.off16 ? reinterpret_cast<const uint16_t*>(a.bin_off) + (int64_t)g * (a.n_bins + 1) : nullptr};
   const int64_t base = a.hit_off[g];
   const BinHit<TS>* hb = static_cast<const BinHit<TS>*>(a.hb);
   const HitRes hr = hit_res(a);
@@ -1862,6 +1877,10 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.max_group = 0;
   for (int g = 0; g < a.n_groups; ++g)
     a.max_group = std::max<int64_t>(a.max_group, ev->hit_off[g + 1] - ev->hit_off[g]);
+  // a build binned by the one-block kernel (every group within its limits,
+  // as run_build decides) keeps its offsets in 16 bits; ktf_bin_hits hands
+  // the caller 32-bit ones
+  a.off16 = !bins_only && a.n_bins <= kLdsBins && a.max_group <= kPackMaxHits ? 1 : 0;
   a.hp = ev->hit_pitch;
   a.hits = ev->hits;
   a.seed_state = ev->seed_state;
