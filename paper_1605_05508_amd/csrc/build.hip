@@ -983,8 +983,9 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   if constexpr (CHILD) {
     meta = make_child<TS, TP>(a, l - 1, cur ^ 1, c, x, P);
     pchi2 = ld_nt(a.sel_chi2 + c);
-    st_nt(a.cmeta[cur] + c, meta);
-    st_nt(a.cchi2[cur] + c, pchi2);
+    // plain stores: the merge reads these right after, from the caches
+    a.cmeta[cur][c] = meta;
+    a.cchi2[cur][c] = pchi2;
   } else {
     load_cand<TS, TP>(a.cpos[cur], a.cmom[cur], a.ccov[cur], S, c, x, P);
     meta = a.cmeta[cur][c];
@@ -1260,12 +1261,14 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
       return;
     }
   }
+  // the record list and its count go out with plain stores: the merge
+  // reads them right after this launch, while they are still in the caches
   for (int k = 0; k < nrec; ++k) {
-    st_nt(a.rchi + (int64_t)k * S + c, lc[k * B + t]);
-    st_nt(a.rhit + (int64_t)k * S + c, lh[k * B + t]);
-    st_nt(a.rpos + (int64_t)k * S + c, lp[k * B + t]);
+    a.rchi[(int64_t)k * S + c] = lc[k * B + t];
+    a.rhit[(int64_t)k * S + c] = lh[k * B + t];
+    a.rpos[(int64_t)k * S + c] = lp[k * B + t];
   }
-  st_nt(a.rcount + c, (int32_t)nrec);
+  a.rcount[c] = (int32_t)nrec;
 }
 
 template <typename TS, typename TP, bool MAT, bool CHILD, bool STAGE>
