@@ -691,13 +691,12 @@ __device__ __forceinline__ void store_cand(double* pos, void* mom, void* cov, in
   for (int k = 0; k < 21; ++k) c[k * S + slot] = (TS)P[k];
 }
 
-// Streaming accesses (each element touched once per launch) carry the
-// non-temporal hint, so that they do not evict the hit bins and offsets
-// that a launch's candidates search over and over from L2.
-template <typename T>
-__device__ __forceinline__ T ld_nt(const T* p) {
-  return __builtin_nontemporal_load(p);
-}
+// A store that nothing reads back within the launch or the next one (the
+// propagated state, read a layer later) carries the non-temporal hint, so
+// that it does not evict the hit bins and offsets that a launch's
+// candidates search over and over from L2.  Data that the next kernel
+// reads right away (the merge's child rows, the score kernel's record
+// lists) goes through the caches with plain accesses.
 template <typename T>
 __device__ __forceinline__ void st_nt(T* p, T v) {
   __builtin_nontemporal_store(v, p);
@@ -943,8 +942,8 @@ __device__ __forceinline__ void wave_sync() {
 template <typename TS, typename TP>
 __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int from, int64_t c,
                                                TrackState<TP>& x, TP P[21]) {
-  const int64_t p = ld_nt(a.sel_parent + c);
-  const int32_t h = ld_nt(a.sel_hit + c);
+  const int64_t p = a.sel_parent[c];
+  const int32_t h = a.sel_hit[c];
   const uint32_t pm = a.cmeta[from][p];
   load_cand<TS, TP>(a.ppos[l & 1], a.pmom[l & 1], a.pcov[l & 1], a.S, p, x, P);
   int cnh = meta_nh(pm), cnm = meta_nm(pm);
@@ -972,7 +971,7 @@ __device__ __forceinline__ uint32_t make_child(const BuildArgs& a, int l, int fr
 // than the few registers the cap spills in double.)
 template <typename TS, typename TP, bool MAT, bool CHILD, bool STAGE>
 __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, int64_t c) {
-  const int32_t info = ld_nt(a.cinfo[cur] + c);
+  const int32_t info = a.cinfo[cur][c];
   const int L = a.g.n_layers, NC = a.g.max_cands;
   const int64_t S = a.S;
   const int e = info_event(info);
@@ -982,7 +981,7 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   double pchi2;
   if constexpr (CHILD) {
     meta = make_child<TS, TP>(a, l - 1, cur ^ 1, c, x, P);
-    pchi2 = ld_nt(a.sel_chi2 + c);
+    pchi2 = a.sel_chi2[c];
     // plain stores: the merge reads these right after, from the caches
     a.cmeta[cur][c] = meta;
     a.cchi2[cur][c] = pchi2;
