@@ -882,8 +882,8 @@ void build_seed_kernel(BuildArgs a) {
           status |= kSNotPD;
         }
       }
-      a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 0 * a.sp + s] = 0;
-      a.hist[((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 1 * a.sp + s] = used;
+      st_nt(a.hist + ((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 0 * a.sp + s, (int32_t)0);
+      st_nt(a.hist + ((int64_t)l * a.g.max_cands + 0) * 2 * a.sp + 1 * a.sp + s, (int32_t)used);
     }
     for (int l = 0; l < NSL; ++l) a.count[(int64_t)l * a.sp + s] = l < reached ? 1 : 0;
     if (reached < NSL) {  // the seed itself ended: it is the best ended candidate
@@ -1541,9 +1541,10 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       mhead_take_later(w, MHead{hk[u], hc[u], mpj(q + LPS * u, rc[u], hd[u]), hh[u], hp[u]});
     }
     group_best<LPS>(w);
-    if (q == 0) {  // the seed's k-th child: its parent, hit and chi2 total
-      a.hist[((int64_t)l * NC + k) * 2 * sp + 0 * sp + s] = mpj_parent(w.pj);
-      a.hist[((int64_t)l * NC + k) * 2 * sp + 1 * sp + s] = w.hit;
+    if (q == 0) {  // the seed's k-th child: its parent, hit and chi2 total (the
+                   // history is read only by the backtrack: non-temporal)
+      st_nt(a.hist + ((int64_t)l * NC + k) * 2 * sp + 0 * sp + s, (int32_t)mpj_parent(w.pj));
+      st_nt(a.hist + ((int64_t)l * NC + k) * 2 * sp + 1 * sp + s, (int32_t)w.hit);
       a.sel_parent[first + k] = (int32_t)(pbase + mpj_parent(w.pj));
       a.sel_hit[first + k] = w.pos;
       a.sel_chi2[first + k] = w.c;
@@ -1648,7 +1649,7 @@ __global__ __launch_bounds__(256) void build_backtrack_kernel(BuildArgs a, int c
   if (s >= a.n_seeds) return;
   const int L = a.g.n_layers, NC = a.g.max_cands;
   const FinalChoice f = final_choice<LAZY>(a, cur, s);
-  for (int l = L - 1; l >= f.end_layer; --l) a.o_hit[(int64_t)l * a.sp + s] = -1;
+  for (int l = L - 1; l >= f.end_layer; --l) st_nt(a.o_hit + (int64_t)l * a.sp + s, (int32_t)-1);
   // The walk is a chain of dependent loads; each layer's record is loaded
   // before the layer above it is stored, so that waiting for the load does
   // not also wait for that store (the memory counter counts both).
@@ -1671,7 +1672,7 @@ __global__ __launch_bounds__(256) void build_backtrack_kernel(BuildArgs a, int c
       hit = a.hist[hb + a.sp + s];
       nr = a.hist[hb + s];
     }
-    a.o_hit[(int64_t)l * a.sp + s] = h_l;
+    st_nt(a.o_hit + (int64_t)l * a.sp + s, (int32_t)h_l);
   }
 }
 
@@ -1700,14 +1701,15 @@ __global__ __launch_bounds__(256) void build_final_kernel(BuildArgs a, int cur) 
     meta = a.cmeta[cur][f.base + f.rank];
     c2 = a.cchi2[cur][f.base + f.rank];
   }
+  // the results are not read again by the build: non-temporal
   TS* so = static_cast<TS*>(a.o_state);
   TS* co = static_cast<TS*>(a.o_cov);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) so[c * a.sp + s] = (TS)x.pos[c];
+  for (int c = 0; c < 3; ++c) st_nt(so + c * a.sp + s, (TS)x.pos[c]);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) so[(c + 3) * a.sp + s] = (TS)x.mom[c];
+  for (int c = 0; c < 3; ++c) st_nt(so + (c + 3) * a.sp + s, (TS)x.mom[c]);
 #pragma unroll
-  for (int c = 0; c < 21; ++c) co[c * a.sp + s] = (TS)P[c];
+  for (int c = 0; c < 21; ++c) st_nt(co + c * a.sp + s, (TS)P[c]);
   uint32_t st = meta_st(meta);
   if (!finite_state(x, P)) st |= kNonFinite;
   a.o_chi2[s] = c2;
