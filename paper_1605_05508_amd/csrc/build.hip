@@ -2086,8 +2086,12 @@ int build_impl(ktf_ctx* c, const ktf_event_batch* ev, ktf_build_out* out, hipStr
     const int64_t nh = (int64_t)L * NC * 2 * sp;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nh, 256)), dim3(256), 0, st, a.hist, nh, -1);
   }
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk((int64_t)L * sp, 256)), dim3(256), 0, st, a.count,
-                     (int64_t)L * sp, 0);
+  // every count the build reads is written first (the seed fit's layers
+  // for every seed, then each merge's layer), so only a caller's array,
+  // pitch padding included, is cleared
+  if (out->cand_count)
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk((int64_t)L * sp, 256)), dim3(256), 0, st, a.count,
+                       (int64_t)L * sp, 0);
   a.u_hit = out->hit_idx;
   a.u_state = out->state;
   a.u_cov = out->cov;
