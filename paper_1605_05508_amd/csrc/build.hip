@@ -350,6 +350,10 @@ constexpr int kBinBatch = 8;
 // over 32,768 bins (78 KB) lets two blocks share a CU; batches of four
 // keep the registers within the eight waves per SIMD that two blocks need.
 template <int BB> struct BinWaves { static constexpr int v = BB == 4 ? 8 : 4; };
+// 16-bit offsets: a group's row of n_bins + 1 rounded up to 16 bytes, so
+// that the binning block writes it in whole 16-byte stores (within the
+// 32-bit row's bytes for n_bins >= 8, which the host requires)
+__host__ __device__ inline int64_t off16_pitch(int nb) { return ((int64_t)nb + 8) & ~int64_t(7); }
 inline size_t bin_lds_bytes(int n_bins, int64_t max_group) {
   return (size_t)((n_bins + 1) >> 1) * 4 + (size_t)((max_group + 1) & ~int64_t(1)) * 2;
 }
@@ -370,8 +374,15 @@ void bin_group16_kernel(BuildArgs a) {
   const TS* h = static_cast<const TS*>(a.hits);
   for (int w = tid; w < nwords; w += kBinThreads) cnt[w] = 0;
   __syncthreads();
-  // count
-  for (int32_t j0 = 0; j0 < n; j0 += BB * kBinThreads) {
+  // count; each hit's bin (below 32,768) stays in a 16-bit half of a
+  // register for the scatter and the ordering, whose place then replaces it
+  uint32_t bk[MB][BB / 2];
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi) {
+    const int32_t j0 = bi * BB * kBinThreads;
+#pragma unroll
+    for (int u = 0; u < BB / 2; ++u) bk[bi][u] = 0;
+    if (j0 >= n) continue;
     TS x[BB], y[BB], z[BB];
 #pragma unroll
     for (int u = 0; u < BB; ++u) {
@@ -388,7 +399,7 @@ void bin_group16_kernel(BuildArgs a) {
       const int32_t j = j0 + u * kBinThreads + tid;
       if (j < n) {
         const int b = hit_bin_of((double)x[u], (double)y[u], (double)z[u], a.g);
-        a.hit_bin[base + j] = b;
+        bk[bi][u >> 1] |= (uint32_t)b << ((u & 1) * 16);
         atomicAdd(&cnt[b >> 1], 1u << ((b & 1) * 16));
       }
     }
@@ -420,69 +431,69 @@ void bin_group16_kernel(BuildArgs a) {
     run += (int32_t)(lo + (v >> 16));
   }
   __syncthreads();
-  if (a.off16) {  // the offsets (at most 32,768) in half the bytes, for the build's own use
-    uint16_t* o16 = reinterpret_cast<uint16_t*>(a.bin_off) + (int64_t)g * (nb + 1);
-    for (int b = tid; b < nb; b += kBinThreads) o16[b] = (uint16_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
-    if (tid == 0) o16[nb] = (uint16_t)n;
+  if (a.off16) {
+    // the offsets (at most 32,768) in half the bytes, for the build's own
+    // use: a word of the table is the two 16-bit offsets of its bins in
+    // order, so the row is the table itself, then n (in the high half of
+    // the last word already, for an odd bin count) and padding
+    const int64_t pitch = off16_pitch(nb);
+    uint4* row = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(a.bin_off) + (int64_t)g * pitch);
+    const uint32_t tail = (uint32_t)n * 0x10001u;
+    for (int q = tid; q < (int)(pitch >> 3); q += kBinThreads) {
+      const int w = 4 * q;
+      uint4 v;
+      v.x = w < nwords ? cnt[w] : tail;
+      v.y = w + 1 < nwords ? cnt[w + 1] : tail;
+      v.z = w + 2 < nwords ? cnt[w + 2] : tail;
+      v.w = w + 3 < nwords ? cnt[w + 3] : tail;
+      row[q] = v;
+    }
   } else {
     for (int b = tid; b < nb; b += kBinThreads) off[b] = (int32_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
     if (tid == 0) off[nb] = n;
   }
   __syncthreads();
   // scatter through the cursors (a bin's cursor ends at the next offset)
-  for (int32_t j0 = 0; j0 < n; j0 += BB * kBinThreads) {
-    int bb[BB];
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
     for (int u = 0; u < BB; ++u) {
-      const int32_t j = j0 + u * kBinThreads + tid;
-      bb[u] = j < n ? a.hit_bin[base + j] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < BB; ++u) {
-      const int32_t j = j0 + u * kBinThreads + tid;
+      const int32_t j = bi * BB * kBinThreads + u * kBinThreads + tid;
       if (j < n) {
-        const int sh = (bb[u] & 1) * 16;
-        const uint32_t pos = (atomicAdd(&cnt[bb[u] >> 1], 1u << sh) >> sh) & 0xffffu;
+        const int b = (int)((bk[bi][u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+        const int sh = (b & 1) * 16;
+        const uint32_t pos = (atomicAdd(&cnt[b >> 1], 1u << sh) >> sh) & 0xffffu;
         permr[pos] = (uint16_t)j;
       }
     }
-  }
   __syncthreads();
   // order every bin by original index: a hit's place is the number of its
   // bin's hits with a smaller index; the places stay in registers until all
   // are taken, then the permutation goes to LDS and out in coalesced rows
   // (scattered 4-byte stores would each cost HBM a line)
-  constexpr int kMaxBatches = MB;
-  int dst[kMaxBatches][BB];
 #pragma unroll
-  for (int bi = 0; bi < kMaxBatches; ++bi) {
-    const int32_t j0 = bi * BB * kBinThreads;
-    int bb[BB];
+  for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
     for (int u = 0; u < BB; ++u) {
-      const int32_t j = j0 + u * kBinThreads + tid;
-      bb[u] = j < n ? a.hit_bin[base + j] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < BB; ++u) {
-      const int32_t j = j0 + u * kBinThreads + tid;
-      dst[bi][u] = -1;
+      const int32_t j = bi * BB * kBinThreads + u * kBinThreads + tid;
       if (j < n) {
-        const int b = bb[u];
+        const int sh = (u & 1) * 16;
+        const int b = (int)((bk[bi][u >> 1] >> sh) & 0xffffu);
         const int32_t hi = (int32_t)((cnt[b >> 1] >> ((b & 1) * 16)) & 0xffffu);
         const int32_t lo = b > 0 ? (int32_t)((cnt[(b - 1) >> 1] >> (((b - 1) & 1) * 16)) & 0xffffu) : 0;
         int32_t rank = 0;
         for (int32_t k = lo; k < hi; ++k) rank += permr[k] < j ? 1 : 0;
-        dst[bi][u] = lo + rank;
+        bk[bi][u >> 1] = (bk[bi][u >> 1] & (0xffff0000u >> sh)) | ((uint32_t)(lo + rank) << sh);
       }
     }
-  }
   __syncthreads();  // every place is taken; the unordered scatter is done with
 #pragma unroll
-  for (int bi = 0; bi < kMaxBatches; ++bi)
+  for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
-    for (int u = 0; u < BB; ++u)
-      if (dst[bi][u] >= 0) permr[dst[bi][u]] = (uint16_t)(bi * BB * kBinThreads + u * kBinThreads + tid);
+    for (int u = 0; u < BB; ++u) {
+      const int32_t j = bi * BB * kBinThreads + u * kBinThreads + tid;
+      if (j < n) permr[(bk[bi][u >> 1] >> ((u & 1) * 16)) & 0xffffu] = (uint16_t)j;
+    }
   __syncthreads();
   BinHit<TS>* o = static_cast<BinHit<TS>*>(a.hb);
   for (int32_t i0 = 0; i0 < n; i0 += BB * kBinThreads) {
@@ -1063,7 +1074,7 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   }
   const int g = e * L + l;
   const BinOffsets off{a.bin_off + (int64_t)g * (a.n_bins + 1),
-                       a.off16 ? reinterpret_cast<const uint16_t*>(a.bin_off) + (int64_t)g * (a.n_bins + 1) : nullptr};
+                       a.off16 ? reinterpret_cast<const uint16_t*>(a.bin_off) + (int64_t)g * off16_pitch(a.n_bins) : nullptr};
   const int64_t base = a.hit_off[g];
   const BinHit<TS>* hb = static_cast<const BinHit<TS>*>(a.hb);
   const HitRes hr = hit_res(a);
@@ -1884,7 +1895,7 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   // a build binned by the one-block kernel (every group within its limits,
   // as run_build decides) keeps its offsets in 16 bits; ktf_bin_hits hands
   // the caller 32-bit ones
-  a.off16 = !bins_only && a.n_bins <= kLdsBins && a.max_group <= kPackMaxHits ? 1 : 0;
+  a.off16 = !bins_only && a.n_bins >= 8 && a.n_bins <= kLdsBins && a.max_group <= kPackMaxHits ? 1 : 0;
   a.hp = ev->hit_pitch;
   a.hits = ev->hits;
   a.seed_state = ev->seed_state;
