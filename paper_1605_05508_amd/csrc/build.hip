@@ -405,13 +405,24 @@ void bin_group16_kernel(BuildArgs a) {
     }
   }
   __syncthreads();
-  // exclusive scan: each thread a contiguous run of words, then the block
+  // exclusive scan: each thread a contiguous run of words, then the block.
+  // A thread walks its run from a lane-dependent start, wrapping round, so
+  // that the lanes of a wave (runs 16 words apart) touch distinct LDS banks
+  // at each step, where a common start would put 16 of them on one bank;
+  // the sum from that start to the run's end gives the prefix at the start,
+  // and the prefix restarts at the run's first word
   const int per = (nwords + kBinThreads - 1) / kBinThreads;
-  const int w0 = min(nwords, tid * per), w1 = min(nwords, w0 + per);
-  int32_t sum = 0;
-  for (int w = w0; w < w1; ++w) {
-    const uint32_t v = cnt[w];
-    sum += (int32_t)((v & 0xffffu) + (v >> 16));
+  const int w0 = min(nwords, tid * per), len = min(nwords, w0 + per) - w0;
+  const int rot = per > 0 ? ((((tid >> 1) & 15) ^ ((tid >> 5) & 1)) % per) : 0;
+  int32_t sum = 0, upper = 0;
+  for (int k = 0; k < per; ++k) {
+    const int m = k + rot < per ? k + rot : k + rot - per;
+    if (m < len) {
+      const uint32_t v = cnt[w0 + m];
+      const int32_t c = (int32_t)((v & 0xffffu) + (v >> 16));
+      sum += c;
+      upper += m >= rot ? c : 0;
+    }
   }
   const int lane = tid & 63, wave = tid >> 6;
   int32_t x = sum;
@@ -422,13 +433,18 @@ void bin_group16_kernel(BuildArgs a) {
   }
   if (lane == 63) wsum[wave] = x;
   __syncthreads();
-  int32_t run = x - sum;
-  for (int w = 0; w < wave; ++w) run += wsum[w];
-  for (int w = w0; w < w1; ++w) {
-    const uint32_t v = cnt[w];
-    const uint32_t lo = v & 0xffffu;
-    cnt[w] = (uint32_t)run | ((uint32_t)(run + (int32_t)lo) << 16);
-    run += (int32_t)(lo + (v >> 16));
+  int32_t first = x - sum;
+  for (int w = 0; w < wave; ++w) first += wsum[w];
+  int32_t run = first + (sum - upper);
+  for (int k = 0; k < per; ++k) {
+    const int m = k + rot < per ? k + rot : k + rot - per;
+    if (m == 0) run = first;
+    if (m < len) {
+      const uint32_t v = cnt[w0 + m];
+      const uint32_t lo = v & 0xffffu;
+      cnt[w0 + m] = (uint32_t)run | ((uint32_t)(run + (int32_t)lo) << 16);
+      run += (int32_t)(lo + (v >> 16));
+    }
   }
   __syncthreads();
   if (a.off16) {
