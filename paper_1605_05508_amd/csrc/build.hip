@@ -360,7 +360,7 @@ inline size_t bin_lds_bytes(int n_bins, int64_t max_group) {
 template <typename TS, int MB, int BB>
 __global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(BinWaves<BB>::v)))
 void bin_group16_kernel(BuildArgs a) {
-  extern __shared__ uint32_t bin_lds[];
+  extern __shared__ __align__(16) uint32_t bin_lds[];
   __shared__ int32_t wsum[kBinThreads / 64];
   const int g = blockIdx.x;
   if (g % a.g.n_layers < a.bin_l0) return;  // the whole block
@@ -458,10 +458,14 @@ void bin_group16_kernel(BuildArgs a) {
     for (int q = tid; q < (int)(pitch >> 3); q += kBinThreads) {
       const int w = 4 * q;
       uint4 v;
-      v.x = w < nwords ? cnt[w] : tail;
-      v.y = w + 1 < nwords ? cnt[w + 1] : tail;
-      v.z = w + 2 < nwords ? cnt[w + 2] : tail;
-      v.w = w + 3 < nwords ? cnt[w + 3] : tail;
+      if (w + 3 < nwords) {  // one 16-byte LDS read: consecutive lanes, no bank shared
+        v = *reinterpret_cast<const uint4*>(cnt + w);
+      } else {
+        v.x = w < nwords ? cnt[w] : tail;
+        v.y = w + 1 < nwords ? cnt[w + 1] : tail;
+        v.z = w + 2 < nwords ? cnt[w + 2] : tail;
+        v.w = w + 3 < nwords ? cnt[w + 3] : tail;
+      }
       row[q] = v;
     }
   } else {
