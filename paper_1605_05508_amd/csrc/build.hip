@@ -1572,14 +1572,26 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       mhead_take_later(w, MHead{hk[u], hc[u], mpj(q + LPS * u, rc[u], hd[u]), hh[u], hp[u]});
     }
     group_best<LPS>(w);
-    if (q == 0) {  // the seed's k-th child: its parent, hit and chi2 total (the
-                   // history is read only by the backtrack: non-temporal)
+    // the seed's k-th child: its parent, hit and chi2 total (the history
+    // is read only by the backtrack: non-temporal)
+    if constexpr (LPS == 1) {
       st_nt(a.hist + ((int64_t)l * NC + k) * 2 * sp + 0 * sp + s, (int32_t)mpj_parent(w.pj));
       st_nt(a.hist + ((int64_t)l * NC + k) * 2 * sp + 1 * sp + s, (int32_t)w.hit);
       a.sel_parent[first + k] = (int32_t)(pbase + mpj_parent(w.pj));
       a.sel_hit[first + k] = w.pos;
       a.sel_chi2[first + k] = w.c;
       a.cinfo[cur ^ 1][first + k] = info;
+    } else if (q < 2) {
+      // the seed's first two lanes share the stores: one instruction writes
+      // the parent from one lane and the hit from the other
+      const bool p0 = q == 0;
+      st_nt(a.hist + (((int64_t)l * NC + k) * 2 + q) * sp + s, p0 ? (int32_t)mpj_parent(w.pj) : (int32_t)w.hit);
+      int32_t* sel = p0 ? a.sel_parent : a.sel_hit;
+      sel[first + k] = p0 ? (int32_t)(pbase + mpj_parent(w.pj)) : w.pos;
+      if (p0)
+        a.cinfo[cur ^ 1][first + k] = info;
+      else
+        a.sel_chi2[first + k] = w.c;
     }
     // the owner lane replaces the taken head by the next record of its list
     // (selects, not branches).  A record beyond the LDS ones is loaded in a
