@@ -203,6 +203,32 @@ def test_eta_bins_build(k, orc, prec):
         assert (o["dbg_n"] > 1).any()
 
 
+@pytest.mark.parametrize("nz,nphi", [(63, 255), (3, 3), (1, 7)])
+def test_odd_bin_tables_build(k, orc, nz, nphi):
+    """Building over bin tables of odd sizes: 63 x 255 (the 16-bit offset
+    row's last word carries the hit total in its high half; eight words per
+    scan lane), 3 x 3 (one word per scan lane) and 1 x 7 (below the 16-bit
+    rows' minimum of eight bins: 32-bit offsets).  FP64 hit indices, counts
+    and chi2 are the oracle's brute force, which uses no bins; FP32 bulk
+    gives bit for bit the outputs of the default 64 x 512 table."""
+    bs = small_batch(13, 2, 300, ghosts=True)
+    ctx = ctx_for(k, bs.det, n_zbins=nz, n_phibins=nphi)
+    g = host(ctx.build(build_inputs(bs, "fp64"), hist=True), bs.n_seeds)
+    o = oracle_batch(orc, bs)
+    assert np.array_equal(g["hit_idx"], o["hit_idx"])
+    assert np.array_equal(g["count"], o["dbg_n"])
+    np.testing.assert_allclose(g["chi2"], o["chi2"], rtol=1e-10, atol=1e-12)
+    assert (o["dbg_n"] > 1).any()
+    ref = ctx_for(k, bs.det)
+    d = build_inputs(bs, "fp32b")
+    gb = host(ctx.build(d, hist=True), bs.n_seeds)
+    gr = host(ref.build(d, hist=True), bs.n_seeds)
+    for key in ("hit_idx", "nhits", "chi2", "state", "cov", "status", "count", "hist"):
+        assert np.array_equal(gb[key], gr[key], equal_nan=gb[key].dtype.kind == "f"), key
+    ctx.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("nc,missed", [(1, 1), (3, 0), (16, 2)])
 def test_beam_widths(k, orc, nc, missed):
     bs = small_batch(3, 2, 150, n_layers=9, ghosts=True)
