@@ -414,14 +414,31 @@ void bin_group16_kernel(BuildArgs a) {
   const int per = (nwords + kBinThreads - 1) / kBinThreads;
   const int w0 = min(nwords, tid * per), len = min(nwords, w0 + per) - w0;
   const int rot = per > 0 ? ((((tid >> 1) & 15) ^ ((tid >> 5) & 1)) % per) : 0;
+  // a run of the usual 16 words (32,768 bins over 1,024 threads) is read
+  // once into registers, its loads issued together; any other run length
+  // takes the loops below
+  constexpr int kRun = 16;
+  const bool full = per == kRun && len == kRun;
+  uint32_t rv[kRun];
   int32_t sum = 0, upper = 0;
-  for (int k = 0; k < per; ++k) {
-    const int m = k + rot < per ? k + rot : k + rot - per;
-    if (m < len) {
-      const uint32_t v = cnt[w0 + m];
-      const int32_t c = (int32_t)((v & 0xffffu) + (v >> 16));
+  if (full) {
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) rv[k] = cnt[w0 + ((k + rot) & (kRun - 1))];
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) {
+      const int32_t c = (int32_t)((rv[k] & 0xffffu) + (rv[k] >> 16));
       sum += c;
-      upper += m >= rot ? c : 0;
+      upper += k < kRun - rot ? c : 0;  // words from the start to the run's end
+    }
+  } else {
+    for (int k = 0; k < per; ++k) {
+      const int m = k + rot < per ? k + rot : k + rot - per;
+      if (m < len) {
+        const uint32_t v = cnt[w0 + m];
+        const int32_t c = (int32_t)((v & 0xffffu) + (v >> 16));
+        sum += c;
+        upper += m >= rot ? c : 0;
+      }
     }
   }
   const int lane = tid & 63, wave = tid >> 6;
@@ -436,14 +453,24 @@ void bin_group16_kernel(BuildArgs a) {
   int32_t first = x - sum;
   for (int w = 0; w < wave; ++w) first += wsum[w];
   int32_t run = first + (sum - upper);
-  for (int k = 0; k < per; ++k) {
-    const int m = k + rot < per ? k + rot : k + rot - per;
-    if (m == 0) run = first;
-    if (m < len) {
-      const uint32_t v = cnt[w0 + m];
-      const uint32_t lo = v & 0xffffu;
-      cnt[w0 + m] = (uint32_t)run | ((uint32_t)(run + (int32_t)lo) << 16);
-      run += (int32_t)(lo + (v >> 16));
+  if (full) {
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) {
+      if (k == ((kRun - rot) & (kRun - 1))) run = first;  // the run's first word
+      const uint32_t lo = rv[k] & 0xffffu;
+      cnt[w0 + ((k + rot) & (kRun - 1))] = (uint32_t)run | ((uint32_t)(run + (int32_t)lo) << 16);
+      run += (int32_t)(lo + (rv[k] >> 16));
+    }
+  } else {
+    for (int k = 0; k < per; ++k) {
+      const int m = k + rot < per ? k + rot : k + rot - per;
+      if (m == 0) run = first;
+      if (m < len) {
+        const uint32_t v = cnt[w0 + m];
+        const uint32_t lo = v & 0xffffu;
+        cnt[w0 + m] = (uint32_t)run | ((uint32_t)(run + (int32_t)lo) << 16);
+        run += (int32_t)(lo + (v >> 16));
+      }
     }
   }
   __syncthreads();
