@@ -372,7 +372,10 @@ void bin_group16_kernel(BuildArgs a) {
   const int32_t n = (int32_t)(a.hit_off[g + 1] - base);
   int32_t* off = a.bin_off + (int64_t)g * (nb + 1);
   const TS* h = static_cast<const TS*>(a.hits);
-  for (int w = tid; w < nwords; w += kBinThreads) cnt[w] = 0;
+  // cleared in 16-byte words (the table starts 16-byte aligned), then the
+  // last few words one by one
+  for (int q = tid; q < (nwords >> 2); q += kBinThreads) reinterpret_cast<uint4*>(cnt)[q] = make_uint4(0u, 0u, 0u, 0u);
+  if (tid < (nwords & 3)) cnt[(nwords & ~3) + tid] = 0;
   __syncthreads();
   // count; each hit's bin (below 32,768) stays in a 16-bit half of a
   // register for the scatter and the ordering, whose place then replaces it
