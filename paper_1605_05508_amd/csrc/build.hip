@@ -720,9 +720,13 @@ __global__ void seed_scatter_kernel(BuildArgs a) {
 }
 
 // event of every seed, once per build
+// each seed's event; and the per-region row counters cleared for the
+// layers to come (the seed kernel, next, counts its rows there)
 __global__ void seed_event_kernel(BuildArgs a) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s < a.n_seeds) a.sev[s] = find_event(a.seed_off, a.n_events, s);
+  const int64_t nctr = (int64_t)a.g.n_layers * kMaxRegions * kCtrStride;
+  for (int64_t i = s; i < nctr; i += (int64_t)gridDim.x * blockDim.x) a.ccount[i] = 0u;
 }
 
 // ------------------------------------------------------------- candidates
@@ -1870,9 +1874,6 @@ static hipError_t run_build(const BuildArgs& a, bool bins_only, hipStream_t st) 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || bins_only || a.n_seeds == 0) return e;
-  const int64_t nctr = (int64_t)a.g.n_layers * kMaxRegions * kCtrStride;
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nctr, bs)), dim3(bs), 0, st, reinterpret_cast<int32_t*>(a.ccount),
-                     nctr, 0);
   if (a.seed_order) {  // the seeds of each event in order of their predicted cell
     hipLaunchKernelGGL((seed_key_kernel<TS, TP>), dim3(nblk(a.n_seeds, bs)), dim3(bs), 0, st, a);
     hipLaunchKernelGGL(seed_order_kernel, dim3(a.n_events), dim3(kOrderThreads), 0, st, a);
