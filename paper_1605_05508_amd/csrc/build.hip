@@ -182,6 +182,10 @@ __device__ __attribute__((noinline)) int phi_bin_near_edge(double x, double y, i
   const double pf = floor((phi + kPi) * nphi / (2.0 * kPi));
   return pf == pf ? (int)pf : 0;  // a coordinate that is not a number: bin 0
 }
+__device__ __attribute__((noinline)) double z_row_near_edge(double z, double zh, int nz) {
+#pragma clang fp contract(off)
+  return floor((z + zh) * nz / (2.0 * zh));
+}
 __device__ __attribute__((noinline)) double eta_row_of(double x, double y, double z, double eta_max, int nz) {
 #pragma clang fp contract(off)
   const double eta = asinh(z / sqrt(x * x + y * y));
@@ -200,7 +204,20 @@ __device__ __forceinline__ int hit_bin_of(double x, double y, double z, const Bu
   if (g.eta_rows) {
     zf = eta_row_of(x, y, z, g.eta_max, nz);
   } else {
-    zf = floor((z + zh) * nz / (2.0 * zh));
+    // the z row from a float estimate u of its position in rows, unless
+    // that lies within m = 2e-6 (nz + |u|) of a row edge: rounding the
+    // coordinate, the sum, the scale and the product to float moves u by
+    // at most 2^-24 (1.5 nz + 3 |u|) for a position inside the table, well
+    // below m, so away from an edge it floors to the row of the double
+    // form, which decides the rest (a position beyond the table clamps to
+    // the same end row either way; not a number goes to the double form)
+    const float uz = ((float)z + (float)zh) * ((float)nz / (float)(2.0 * zh));
+    const float flz = floorf(uz), frz = uz - flz, mz = 2e-6f * ((float)nz + fabsf(uz));
+    if (frz > mz && frz < 1.0f - mz) {
+      zf = (double)flz;
+    } else {
+      zf = z_row_near_edge(z, zh, nz);
+    }
   }
   // (not a number: the first row, as a number below the range)
   const int zb = zf >= 0.0 ? (zf > nz - 1 ? nz - 1 : (int)zf) : 0;

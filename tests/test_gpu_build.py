@@ -119,6 +119,41 @@ def test_bins_at_phi_edges(k, orc):
                 assert np.array_equal(perm[a:b], op), (prec, e, l)
 
 
+@pytest.mark.parametrize("nz,nphi", [(64, 512), (1000, 32)])
+def test_bins_at_z_edges(k, orc, nz, nphi):
+    """Hits on and within a few 1e-5 cm of z-row edges, at the table's two
+    ends and beyond them: the kernel takes a float estimate of the z row
+    away from the edges (its margin grows with the row count) and the
+    double form near them, so every hit must land in the oracle's row.
+    Coordinates are float-representable, so both precisions see the same
+    hits."""
+    zh = 100.0
+    bs = small_batch(9, 2, 1500, n_layers=4)
+    rng = np.random.default_rng(99)
+    deltas = np.array([0.0, 1e-7, -1e-7, 1e-6, -1e-6, 1e-5, -1e-5, 6e-5, -6e-5,
+                       2e-4, -2e-4, 1e-3, -1e-3, 0.3, -0.3])
+    L = bs.det.n_layers
+    for g in range(bs.n_events * L):
+        a, b = bs.hit_off[g], bs.hit_off[g + 1]
+        n = b - a
+        rows = rng.integers(0, nz + 1, size=n)
+        z = -zh + rows * (2 * zh / nz) + deltas[rng.integers(0, len(deltas), size=n)]
+        z[:6] = [-zh, zh, -zh - 5.0, zh + 5.0, -1e4, 1e4]
+        bs.hits[2, a:b] = z.astype(np.float32)
+    ctx = ctx_for(k, bs.det, n_zbins=nz, n_phibins=nphi)
+    for prec in ("fp64", "fp32b"):
+        offs, perm = ctx.bin_hits(build_inputs(bs, prec, hit_pad=64))
+        offs, perm = offs.cpu().numpy(), perm.cpu().numpy()
+        for e in range(bs.n_events):
+            for l in range(L):
+                g = e * L + l
+                oo, op = orc.bin_layer(bs.layer_hits(e, l), zh, nz, nphi)
+                a, b = bs.hit_off[g], bs.hit_off[g + 1]
+                assert np.array_equal(offs[g], oo), (prec, e, l)
+                assert np.array_equal(perm[a:b], op), (prec, e, l)
+    ctx.close()
+
+
 @pytest.mark.parametrize("eta", [False, True])
 def test_bins_and_build_with_not_a_number_hits(k, orc, eta):
     """Hits with a coordinate that is not a number (x, y, z or all) bin as
