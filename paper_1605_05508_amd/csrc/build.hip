@@ -1123,11 +1123,13 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     const double e0 = asinh(z0 / (z0 >= 0.0 ? rb : ra)) - 1e-9;
     const double e1 = asinh(z1 / (z1 >= 0.0 ? ra : rb)) + 1e-9;
     const double em = a.g.eta_max;
-    zlo = (int)fmax(-1.0, floor((e0 + em) * nz / (2.0 * em)));
-    zhi = (int)fmin((double)nz, floor((e1 + em) * nz / (2.0 * em)));
+    zlo = (int)fmax(-1.0, floor((e0 + em) * a.g.row_scale));
+    zhi = (int)fmin((double)nz, floor((e1 + em) * a.g.row_scale));
   } else {
-    zlo = (int)fmax(-1.0, floor((zp - bzw + zh) * nz / (2.0 * zh)));
-    zhi = (int)fmin((double)nz, floor((zp + bzw + zh) * nz / (2.0 * zh)));
+    // (the scale rounded once instead of a division: a few ulp of a row,
+    // far inside the window's 5% margin)
+    zlo = (int)fmax(-1.0, floor((zp - bzw + zh) * a.g.row_scale));
+    zhi = (int)fmin((double)nz, floor((zp + bzw + zh) * a.g.row_scale));
   }
   zlo = max(0, min(nz - 1, zlo));
   zhi = max(0, min(nz - 1, zhi));
@@ -1139,8 +1141,8 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
     // of a few 1e-7 rad, covered by the 1e-5 added)
     const double dphi = 1.1 * sphi + 1e-5;
     const double php = (double)atan2f((float)xp.pos[1], (float)xp.pos[0]);
-    plo = (int)floor((php - dphi + kPi) * nphi / (2.0 * kPi));
-    phi_hi = (int)floor((php + dphi + kPi) * nphi / (2.0 * kPi));
+    plo = (int)floor((php - dphi + kPi) * a.g.phi_scale);
+    phi_hi = (int)floor((php + dphi + kPi) * a.g.phi_scale);
     full_phi = (phi_hi - plo + 1) >= nphi;
   }
   const int g = e * L + l;
@@ -1953,6 +1955,8 @@ static int prepare(ktf_ctx* c, const ktf_event_batch* ev, bool bins_only, BuildA
   a.g.n_seed_layers = cfg.n_seed_layers;
   a.g.bz = cfg.bz;
   a.g.z_half = cfg.z_half;
+  a.g.row_scale = a.g.n_zbins / (2.0 * (a.g.eta_rows ? a.g.eta_max : a.g.z_half));
+  a.g.phi_scale = a.g.n_phibins / (2.0 * kPi);
   a.g.chi2_cut = cfg.chi2_cut;
   a.g.hr.sr2 = cfg.sigma_r * cfg.sigma_r;
   a.g.hr.srphi2 = cfg.sigma_rphi * cfg.sigma_rphi;

@@ -63,6 +63,10 @@ struct BuildGeom {
   int32_t n_layers, n_zbins, n_phibins, max_cands, max_missed, n_seed_layers;
   int32_t eta_rows;  // 1: rows are eta bins over |eta| < eta_max
   double bz, z_half, chi2_cut, eta_max;
+  // rows per unit of the row coordinate (z, or eta when eta_rows) and phi
+  // bins per radian, n_zbins / (2 z_half or 2 eta_max) and n_phibins /
+  // (2 pi), for the search windows, whose bounds need only be conservative
+  double row_scale, phi_scale;
   HitResD hr;
   double radii[KTF_MAX_LAYERS];
   MaterialD mat;
