@@ -1104,7 +1104,8 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   // are taken to lie within 1% of the layer radius)
   const double cut = a.g.chi2_cut;
   const double rho = sqrt(xp.pos[0] * xp.pos[0] + xp.pos[1] * xp.pos[1]);
-  const double tx = -xp.pos[1] / rho, ty = xp.pos[0] / rho;
+  const double irho = 1.0 / rho;  // one division for the window's three
+  const double tx = -xp.pos[1] * irho, ty = xp.pos[0] * irho;
   const double ptt = tx * tx * (double)Pp[pidx(0, 0)] + 2.0 * tx * ty * (double)Pp[pidx(0, 1)] +
                      ty * ty * (double)Pp[pidx(1, 1)];
   const double vmax = fmax(a.g.hr.sr2, a.g.hr.srphi2);
@@ -1133,7 +1134,7 @@ __device__ __forceinline__ void score_row(const BuildArgs& a, int l, int cur, in
   }
   zlo = max(0, min(nz - 1, zlo));
   zhi = max(0, min(nz - 1, zhi));
-  const double sphi = bt / (0.99 * rho);
+  const double sphi = bt * irho * (1.0 / 0.99);
   int plo = 0, phi_hi = nphi - 1;
   bool full_phi = true;
   if (sphi < 0.5) {
