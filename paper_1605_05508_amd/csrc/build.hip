@@ -1611,13 +1611,11 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
   const int reg = block_region(a);
   const int local = (int)block_reserve(region_ctr(a, l, reg), q == 0 ? nsel : 0, wtot);
   const int64_t first = reg * a.RS + group_first<LPS>(local);
-  if (real && q == 0) {
-    a.count[(int64_t)l * sp + s] = nsel;
-    if (nsel > 0) a.cstart[cur ^ 1][s] = (int32_t)first;
-  }
   // every load issued so far is complete before the picks: otherwise the
   // wait for the heads' loads sits at the top of the pick loop, and with the
-  // stores of each pick in flight it would wait for those every time
+  // stores of each pick in flight it would wait for those every time (the
+  // seed's count and first row are stored after the picks, so that this
+  // wait does not include them)
   __builtin_amdgcn_s_waitcnt(0);
   for (int k = 0; k < nsel; ++k) {
     MHead w{hk[0], hc[0], mpj(q, rc[0], hd[0]), hh[0], hp[0]};
@@ -1688,6 +1686,10 @@ __global__ __launch_bounds__(kMergeThreads) void build_merge_kernel(BuildArgs a,
       hp[u] = lds ? npv : hp[u];
       hk[u] = adv && !more ? 0 : hk[u];
     }
+  }
+  if (real && q == 0) {
+    a.count[(int64_t)l * sp + s] = nsel;
+    if (nsel > 0) a.cstart[cur ^ 1][s] = (int32_t)first;
   }
 }
 // ------------------------------------------------------------------ final
